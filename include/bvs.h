@@ -1,0 +1,225 @@
+/*
+ * bvs.h - C ABI of the MI355X (gfx950) vector-set search library.
+ *
+ * The library implements the data-parallel hot path of the cascade search
+ * for vector sets under the Hausdorff distance:
+ *
+ *   FlyHash encoding      h = WTA(W v), W a sparse 0/1 random projection into
+ *                         L = code_bits outputs, WTA keeping the wta_k largest
+ *                         (Def. 7; Alg. 1)
+ *   set sketches          count Bloom filter C = sum of member codes (Def. 8,
+ *                         Alg. 3) and binary Bloom filter B = OR of member
+ *                         codes, used as the set sketch (Def. 10, Alg. 5)
+ *   filtering             first layer: sets with C[p] >= M at one of the A
+ *                         largest positions p of the query's count filter;
+ *                         second layer: the T sets of the first layer closest
+ *                         to the query sketch in Hamming distance (Alg. 6)
+ *   re-ranking            exact Hausdorff distance (Def. 4) to the T
+ *                         survivors and the k smallest (Alg. 6, Def. 5)
+ *   brute force           exact Hausdorff distance to every set, k smallest
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named d_* are device pointers, h_* are host pointers.  The
+ *   library never allocates device memory: the caller passes the index
+ *   memory, workspaces and outputs, sized with the *_bytes queries, and
+ *   owns them.  The library keeps no host pointer after a call returns.
+ * - Every call returns a bvs_status; bvs_last_error() gives a thread-local
+ *   message for the last non-OK status.  Argument errors are detected on
+ *   the host before anything is launched.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Work is enqueued on it.  Calls that validate device data
+ *   (bvs_build_index, bvs_encode, bvs_search, bvs_search_candidates,
+ *   bvs_query_sketch, bvs_bruteforce, bvs_hausdorff_all) synchronise the
+ *   stream before returning so that they can report BVS_ERANGE.
+ * - Vectors are float32 rows [n][dim], row-major.  Every value must lie on
+ *   the 2^-12 grid (4096 * x is an integer) with |x| <= 1, and every row
+ *   must have Euclidean norm <= 2; otherwise BVS_ERANGE.  On this grid the
+ *   projection sums, squared distances and rankings are exact integers.
+ * - Sets are given by offsets [n_sets + 1] (host, uint64): set j holds rows
+ *   offsets[j] .. offsets[j+1]-1; offsets[0] = 0 and offsets must strictly
+ *   increase (a set has at least one vector, Def. 2).  A set id is its
+ *   position j.  Database sets hold at most 255 vectors, query sets at most
+ *   65535 (BVS_ERANGE otherwise).
+ * - Results are sorted ascending by (distance, id); distances are Euclidean
+ *   (not squared), float32.  With fewer than k results, count[q] says how
+ *   many are valid and the rest are id = 0xFFFFFFFF, distance = +inf.
+ * - The index is immutable after build; concurrent searches on one index
+ *   with distinct workspaces are allowed.  Outputs depend only on the data,
+ *   the parameters and the query, never on batch composition or stream.
+ */
+#ifndef BVS_H
+#define BVS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BVS_OK = 0,
+  BVS_EINVAL = -1,   /* invalid argument (null pointer, bad size, bad offsets) */
+  BVS_ERANGE = -2,   /* data outside the supported range (grid, norm, set size) */
+  BVS_ENOSPC = -3,   /* index memory or workspace smaller than required */
+  BVS_EDEVICE = -4,  /* a HIP call failed */
+  BVS_ESTATE = -5,   /* object in the wrong state */
+  BVS_ENOTSUP = -6   /* parameter combination not supported by the kernels */
+} bvs_status;
+
+/* Parameters Theta of Alg. 6 plus the hashing parameters of Def. 7.
+ *   dim           d, 1..1024
+ *   code_bits     L (the Bloom filter length b equals L): a power of two,
+ *                 256..4096
+ *   fan_in        s, input dimensions summed per projection output, 1..d;
+ *                 L * s <= 65536 and the WTA key must fit 32 bits
+ *                 (s * 8192 < 2^(32 - log2 L))
+ *   wta_k         L_wta, ones per code, 1..L
+ *   access_lists  A, inverted lists (positions) visited, 1..8
+ *   min_count     M, minimum count in the first layer, 0..255
+ *   top_t         T, survivors of the second layer, 1..4096
+ *   flags         must be 0
+ *   seed          seed of the projection (see bvs_projection) */
+typedef struct bvs_params {
+  uint32_t dim;
+  uint32_t code_bits;
+  uint32_t fan_in;
+  uint32_t wta_k;
+  uint32_t access_lists;
+  uint32_t min_count;
+  uint32_t top_t;
+  uint32_t flags;
+  uint64_t seed;
+} bvs_params;
+
+typedef struct bvs_index bvs_index;  /* opaque host handle */
+
+typedef struct bvs_index_info {
+  uint64_t n_sets;       /* n */
+  uint64_t n_vectors;    /* N */
+  uint64_t ld_sets;      /* leading dimension of the sketch views (n rounded up to 256) */
+  uint32_t dim_padded;   /* d rounded up to 64 (row stride of the internal planes) */
+  uint32_t max_set_size;
+} bvs_index_info;
+
+/* Fills *p with defaults: L = 1024, wta_k = 64, A = 3 and M = 1 are the
+ * paper's defaults (Sec. 6.1.5); s = 8 and T = 1000 are this library's
+ * (the paper's default of 50k candidates exceeds the T limit above);
+ * dim is left 0 and must be set. */
+void bvs_params_default(bvs_params* p);
+
+/* Checks a parameter block; BVS_EINVAL / BVS_ENOTSUP with a message. */
+bvs_status bvs_params_check(const bvs_params* p);
+
+/* The random projection W of Def. 7 as index rows, host only.
+ * h_idx[L][s] (uint16): the s distinct input dimensions of output j, sorted
+ * ascending.  Construction: one splitmix64 stream seeded with p->seed; each
+ * draw u gives i = ((u >> 32) * d) >> 32; a dimension already in the row is
+ * redrawn; rows are filled in order 0..L-1. */
+bvs_status bvs_projection(const bvs_params* p, uint16_t* h_idx);
+
+/* Device bytes of the index for n_sets sets holding n_vectors vectors. */
+bvs_status bvs_index_bytes(const bvs_params* p, uint64_t n_sets, uint64_t n_vectors,
+                           uint64_t* out_bytes);
+/* Device workspace bytes needed by bvs_build_index (released after it). */
+bvs_status bvs_build_workspace_bytes(const bvs_params* p, uint64_t n_sets,
+                                     uint64_t n_vectors, uint64_t* out_bytes);
+
+/* Builds the index (Algs. 1, 3, 5): validates and converts the vectors,
+ * encodes every vector and writes the per-set count Bloom filters
+ * (uint8 [L][ld_sets], position-major) and binary Bloom filters
+ * (chunk-major: 128-bit chunk c of set j at word offset 2*(c*ld_sets + j)).
+ * d_vectors: float32 [n_vectors][dim]; h_offsets: [n_sets + 1].
+ * The index keeps its own exact copy of the vectors; d_vectors may be freed
+ * after the call.  d_index_mem must stay valid while the index is used.
+ * On success *out receives a handle to release with bvs_index_destroy. */
+bvs_status bvs_build_index(const bvs_params* p, const float* d_vectors,
+                           const uint64_t* h_offsets, uint64_t n_sets,
+                           void* d_index_mem, uint64_t index_bytes,
+                           void* d_workspace, uint64_t workspace_bytes,
+                           void* stream, bvs_index** out);
+
+/* Releases the host handle (the caller frees the device memory). */
+void bvs_index_destroy(bvs_index* ix);
+
+bvs_status bvs_index_get_info(const bvs_index* ix, bvs_index_info* info);
+bvs_status bvs_index_get_params(const bvs_index* ix, bvs_params* p);
+
+/* Device views of the sketches (Defs. 8 and 10) for inspection:
+ *   *d_count: uint8 [L][ld_sets]; entry (i, j) = C^(j)[i]
+ *   *d_bits:  uint64 [L/128][ld_sets][2]; bit i of set j is bit (i % 64) of
+ *             word (i % 128) / 64 of chunk i / 128.
+ * Columns j >= n_sets are zero. */
+bvs_status bvs_sketch_views(const bvs_index* ix, const uint8_t** d_count,
+                            const uint64_t** d_bits);
+
+/* Workspace bytes for bvs_encode on n vectors. */
+bvs_status bvs_encode_workspace_bytes(const bvs_index* ix, uint64_t n, uint64_t* out_bytes);
+/* FlyHash codes (Def. 7, Alg. 1) of arbitrary vectors with the index's
+ * projection: d_codes uint64 [n][L/64], output j is bit j % 64 of word j / 64. */
+bvs_status bvs_encode(const bvs_index* ix, const float* d_x, uint64_t n,
+                      void* d_workspace, uint64_t workspace_bytes,
+                      uint64_t* d_codes, void* stream);
+
+/* Workspace bytes for bvs_search, bvs_search_candidates and bvs_query_sketch
+ * on n_q query sets holding n_q_vectors vectors in total. */
+bvs_status bvs_search_workspace_bytes(const bvs_index* ix, uint32_t n_q,
+                                      uint64_t n_q_vectors, uint64_t* out_bytes);
+
+/* Query-side preparation of Alg. 6: the query count filter C_Q
+ * (d_cq uint16 [n_q][L]), the query sketch S_Q (d_sq uint64 [n_q][L/64])
+ * and the A positions of largest count, ties to the lower position
+ * (d_pos uint32 [n_q][A]).  Any output pointer may be NULL. */
+bvs_status bvs_query_sketch(const bvs_index* ix, const float* d_q,
+                            const uint64_t* h_q_offsets, uint32_t n_q,
+                            void* d_workspace, uint64_t workspace_bytes,
+                            uint16_t* d_cq, uint64_t* d_sq, uint32_t* d_pos,
+                            void* stream);
+
+/* Both filter layers of Alg. 6: F2 of every query, sorted by (score, id).
+ * d_ids uint32 [n_q][T], d_scores uint16 [n_q][T], d_count uint32 [n_q]
+ * (= min(T, |F1|)); unused slots are id 0xFFFFFFFF, score 0xFFFF. */
+bvs_status bvs_search_candidates(const bvs_index* ix, const float* d_q,
+                                 const uint64_t* h_q_offsets, uint32_t n_q,
+                                 void* d_workspace, uint64_t workspace_bytes,
+                                 uint32_t* d_ids, uint16_t* d_scores,
+                                 uint32_t* d_count, void* stream);
+
+/* The whole cascade search (Alg. 6): top-k (k <= T, k <= 64) of every
+ * query.  d_ids uint32 [n_q][k], d_dist float32 [n_q][k], d_count uint32 [n_q]. */
+bvs_status bvs_search(const bvs_index* ix, const float* d_q,
+                      const uint64_t* h_q_offsets, uint32_t n_q, uint32_t k,
+                      void* d_workspace, uint64_t workspace_bytes,
+                      uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                      void* stream);
+
+/* Workspace bytes for bvs_bruteforce / bvs_hausdorff_all. */
+bvs_status bvs_bruteforce_workspace_bytes(const bvs_index* ix, uint32_t n_q,
+                                          uint64_t n_q_vectors, uint64_t* out_bytes);
+
+/* Exact top-k (k <= 64) by Hausdorff distance over every set (Def. 5 with
+ * failure probability 0); outputs as for bvs_search. */
+bvs_status bvs_bruteforce(const bvs_index* ix, const float* d_q,
+                          const uint64_t* h_q_offsets, uint32_t n_q, uint32_t k,
+                          void* d_workspace, uint64_t workspace_bytes,
+                          uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                          void* stream);
+
+/* Exact squared Hausdorff distance (Def. 4) of every query to every set,
+ * scaled by 2^24 (an integer on the grid): d_h2 uint32 [n_q][n_sets]. */
+bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q,
+                             const uint64_t* h_q_offsets, uint32_t n_q,
+                             void* d_workspace, uint64_t workspace_bytes,
+                             uint32_t* d_h2, void* stream);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char* bvs_last_error(void);
+
+/* Library version string. */
+const char* bvs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BVS_H */

@@ -1,0 +1,286 @@
+"""ctypes binding of libbvs.so (the C ABI in include/bvs.h).
+
+Argument marshalling only: every step of the search runs in the HIP
+library.  PyTorch supplies device memory (index, workspaces, outputs) and
+the current stream.  Importing torch before loading the library makes the
+library share torch's HIP runtime.  There is no fallback: if the library
+is not built, `lib()` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbvs.so")
+
+BVS_OK, BVS_EINVAL, BVS_ERANGE, BVS_ENOSPC, BVS_EDEVICE, BVS_ESTATE, BVS_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ERANGE", -3: "ENOSPC", -4: "EDEVICE", -5: "ESTATE", -6: "ENOTSUP"}
+
+EXPORTED = [
+    "bvs_params_default", "bvs_params_check", "bvs_projection", "bvs_index_bytes",
+    "bvs_build_workspace_bytes", "bvs_build_index", "bvs_index_destroy", "bvs_index_get_info",
+    "bvs_index_get_params", "bvs_sketch_views", "bvs_encode_workspace_bytes", "bvs_encode",
+    "bvs_search_workspace_bytes", "bvs_query_sketch", "bvs_search_candidates", "bvs_search",
+    "bvs_bruteforce_workspace_bytes", "bvs_bruteforce", "bvs_hausdorff_all", "bvs_last_error",
+    "bvs_version",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [("dim", C.c_uint32), ("code_bits", C.c_uint32), ("fan_in", C.c_uint32),
+                ("wta_k", C.c_uint32), ("access_lists", C.c_uint32), ("min_count", C.c_uint32),
+                ("top_t", C.c_uint32), ("flags", C.c_uint32), ("seed", C.c_uint64)]
+
+    @classmethod
+    def make(cls, dim, code_bits=1024, fan_in=8, wta_k=64, access_lists=3, min_count=1,
+             top_t=1000, seed=0):
+        return cls(dim, code_bits, fan_in, wta_k, access_lists, min_count, top_t, 0, seed)
+
+
+class IndexInfo(C.Structure):
+    _fields_ = [("n_sets", C.c_uint64), ("n_vectors", C.c_uint64), ("ld_sets", C.c_uint64),
+                ("dim_padded", C.c_uint32), ("max_set_size", C.c_uint32)]
+
+
+class BvsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+P = C.c_void_p
+U32, U64 = C.c_uint32, C.c_uint64
+PU64 = C.POINTER(C.c_uint64)
+
+
+def lib():
+    """Load libbvs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                               "python -m paper_2412_03301_amd.csrc.build")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "bvs_params_default": (None, [P]),
+            "bvs_params_check": (C.c_int, [P]),
+            "bvs_projection": (C.c_int, [P, P]),
+            "bvs_index_bytes": (C.c_int, [P, U64, U64, PU64]),
+            "bvs_build_workspace_bytes": (C.c_int, [P, U64, U64, PU64]),
+            "bvs_build_index": (C.c_int, [P, P, P, U64, P, U64, P, U64, P, C.POINTER(P)]),
+            "bvs_index_destroy": (None, [P]),
+            "bvs_index_get_info": (C.c_int, [P, P]),
+            "bvs_index_get_params": (C.c_int, [P, P]),
+            "bvs_sketch_views": (C.c_int, [P, C.POINTER(P), C.POINTER(P)]),
+            "bvs_encode_workspace_bytes": (C.c_int, [P, U64, PU64]),
+            "bvs_encode": (C.c_int, [P, P, U64, P, U64, P, P]),
+            "bvs_search_workspace_bytes": (C.c_int, [P, U32, U64, PU64]),
+            "bvs_query_sketch": (C.c_int, [P, P, P, U32, P, U64, P, P, P, P]),
+            "bvs_search_candidates": (C.c_int, [P, P, P, U32, P, U64, P, P, P, P]),
+            "bvs_search": (C.c_int, [P, P, P, U32, U32, P, U64, P, P, P, P]),
+            "bvs_bruteforce_workspace_bytes": (C.c_int, [P, U32, U64, PU64]),
+            "bvs_bruteforce": (C.c_int, [P, P, P, U32, U32, P, U64, P, P, P, P]),
+            "bvs_hausdorff_all": (C.c_int, [P, P, P, U32, P, U64, P, P]),
+            "bvs_last_error": (C.c_char_p, []),
+            "bvs_version": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != BVS_OK:
+        raise BvsError(status, lib().bvs_last_error().decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _offsets(off) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(off, dtype=np.uint64))
+    return a
+
+
+def _u64p(a: np.ndarray):
+    return a.ctypes.data_as(PU64)
+
+
+def projection(params: Params) -> np.ndarray:
+    L, s = params.code_bits, params.fan_in
+    out = np.zeros((L, s), np.uint16)
+    check(lib().bvs_projection(C.byref(params), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def params_check(params: Params) -> None:
+    check(lib().bvs_params_check(C.byref(params)))
+
+
+def _bytes(fn, *args) -> int:
+    out = C.c_uint64(0)
+    check(fn(*args, C.byref(out)))
+    return int(out.value)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+class Index:
+    """A built index.  `vectors` is a float32 CUDA tensor [N, dim] on the
+    2^-12 grid; `offsets` host offsets [n + 1]."""
+
+    def __init__(self, params: Params, vectors: torch.Tensor, offsets, stream=None):
+        L = lib()
+        if not (vectors.is_cuda and vectors.dtype == torch.float32 and vectors.is_contiguous()):
+            raise ValueError("vectors must be a contiguous float32 CUDA tensor")
+        self.params = Params.from_buffer_copy(params)
+        self.device = vectors.device
+        off = _offsets(offsets)
+        n = len(off) - 1
+        N = int(off[-1]) if n >= 0 else 0
+        nbytes = _bytes(L.bvs_index_bytes, C.byref(self.params), n, N)
+        wbytes = _bytes(L.bvs_build_workspace_bytes, C.byref(self.params), n, N)
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ws = _workspace(wbytes, self.device)
+        h = C.c_void_p()
+        check(L.bvs_build_index(C.byref(self.params), _ptr(vectors), _u64p(off), n, _ptr(self.mem), nbytes,
+                                _ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+        self._h = h
+        del ws
+        info = IndexInfo()
+        check(L.bvs_index_get_info(self._h, C.byref(info)))
+        self.n_sets, self.n_vectors, self.ld = int(info.n_sets), int(info.n_vectors), int(info.ld_sets)
+        self.dim_padded, self.max_set_size = int(info.dim_padded), int(info.max_set_size)
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bvs_index_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- inspection
+    def sketch_views(self):
+        """(count uint8 [L, ld], bits int64 [L/128, ld, 2]) views into the index memory."""
+        c, b = C.c_void_p(), C.c_void_p()
+        check(lib().bvs_sketch_views(self._h, C.byref(c), C.byref(b)))
+        base = self.mem.data_ptr()
+        Lb = self.params.code_bits
+        cnt = self.mem[c.value - base: c.value - base + Lb * self.ld].view(Lb, self.ld)
+        nb = (Lb // 64) * self.ld * 8
+        bits = self.mem[b.value - base: b.value - base + nb].view(torch.int64).view(Lb // 128, self.ld, 2)
+        return cnt, bits
+
+    def encode(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        """Codes int64 [n, L/64] (bit j % 64 of word j / 64 is output j)."""
+        n = x.shape[0]
+        out = torch.empty(n, self.params.code_bits // 64, dtype=torch.int64, device=self.device)
+        wb = _bytes(lib().bvs_encode_workspace_bytes, self._h, n)
+        ws = _workspace(wb, self.device)
+        check(lib().bvs_encode(self._h, _ptr(x), n, _ptr(ws), ws.numel(), _ptr(out), _stream(stream)))
+        return out
+
+    def _qargs(self, q: torch.Tensor, q_offsets):
+        if not (q.is_cuda and q.dtype == torch.float32 and q.is_contiguous()):
+            raise ValueError("queries must be a contiguous float32 CUDA tensor")
+        off = _offsets(q_offsets)
+        return off, len(off) - 1, int(off[-1])
+
+    def search_workspace(self, n_q: int, n_q_vectors: int) -> torch.Tensor:
+        return _workspace(_bytes(lib().bvs_search_workspace_bytes, self._h, n_q, n_q_vectors), self.device)
+
+    def brute_workspace(self, n_q: int, n_q_vectors: int) -> torch.Tensor:
+        return _workspace(_bytes(lib().bvs_bruteforce_workspace_bytes, self._h, n_q, n_q_vectors), self.device)
+
+    def query_sketch(self, q, q_offsets, stream=None):
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        L, A = self.params.code_bits, self.params.access_lists
+        cq = torch.empty(n_q, L, dtype=torch.int16, device=self.device)
+        sq = torch.empty(n_q, L // 64, dtype=torch.int64, device=self.device)
+        pos = torch.empty(n_q, A, dtype=torch.int32, device=self.device)
+        ws = self.search_workspace(n_q, NQ)
+        check(lib().bvs_query_sketch(self._h, _ptr(q), _u64p(off), n_q, _ptr(ws), ws.numel(), _ptr(cq),
+                                     _ptr(sq), _ptr(pos), _stream(stream)))
+        return cq, sq, pos
+
+    def candidates(self, q, q_offsets, stream=None):
+        """F2 per query: ids int32 [n_q, T], scores int16 [n_q, T], count int32 [n_q]."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        T = self.params.top_t
+        ids = torch.empty(n_q, T, dtype=torch.int32, device=self.device)
+        sc = torch.empty(n_q, T, dtype=torch.int16, device=self.device)
+        cnt = torch.empty(n_q, dtype=torch.int32, device=self.device)
+        ws = self.search_workspace(n_q, NQ)
+        check(lib().bvs_search_candidates(self._h, _ptr(q), _u64p(off), n_q, _ptr(ws), ws.numel(), _ptr(ids),
+                                          _ptr(sc), _ptr(cnt), _stream(stream)))
+        return ids, sc, cnt
+
+    def search(self, q, q_offsets, k: int, ws: torch.Tensor | None = None, out=None, stream=None):
+        """Top-k per query: ids int32 [n_q, k], dist float32 [n_q, k], count int32 [n_q]."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        if ws is None:
+            ws = self.search_workspace(n_q, NQ)
+        if out is None:
+            out = (torch.empty(n_q, k, dtype=torch.int32, device=self.device),
+                   torch.empty(n_q, k, dtype=torch.float32, device=self.device),
+                   torch.empty(n_q, dtype=torch.int32, device=self.device))
+        ids, dist, cnt = out
+        check(lib().bvs_search(self._h, _ptr(q), _u64p(off), n_q, k, _ptr(ws), ws.numel(), _ptr(ids),
+                               _ptr(dist), _ptr(cnt), _stream(stream)))
+        return ids, dist, cnt
+
+    def bruteforce(self, q, q_offsets, k: int, ws: torch.Tensor | None = None, out=None, stream=None):
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        if ws is None:
+            ws = self.brute_workspace(n_q, NQ)
+        if out is None:
+            out = (torch.empty(n_q, k, dtype=torch.int32, device=self.device),
+                   torch.empty(n_q, k, dtype=torch.float32, device=self.device),
+                   torch.empty(n_q, dtype=torch.int32, device=self.device))
+        ids, dist, cnt = out
+        check(lib().bvs_bruteforce(self._h, _ptr(q), _u64p(off), n_q, k, _ptr(ws), ws.numel(), _ptr(ids),
+                                   _ptr(dist), _ptr(cnt), _stream(stream)))
+        return ids, dist, cnt
+
+    def hausdorff_all(self, q, q_offsets, stream=None) -> torch.Tensor:
+        """2^24 * Hausdorff^2 of every (query, set) pair, int32 [n_q, n_sets] (values < 2^28)."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        out = torch.empty(n_q, self.n_sets, dtype=torch.int32, device=self.device)
+        ws = self.brute_workspace(n_q, NQ)
+        check(lib().bvs_hausdorff_all(self._h, _ptr(q), _u64p(off), n_q, _ptr(ws), ws.numel(), _ptr(out),
+                                      _stream(stream)))
+        return out
+
+
+def as_u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def as_u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def as_u16(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint16)

@@ -1,0 +1,634 @@
+// Host runtime of the library: parameter and data validation, the device
+// memory plan of the index and of each call's workspace, and the launch
+// sequences behind the C ABI declared in include/bvs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bvs.h"
+#include "device.h"
+#include "launch.h"
+
+using namespace bvs;
+
+namespace {
+
+thread_local std::string g_err;
+
+bvs_status fail(bvs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(BVS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define BVS_TRY(expr)            \
+  do {                           \
+    bvs_status s_ = (expr);      \
+    if (s_ != BVS_OK) return s_; \
+  } while (0)
+
+// ------------------------------------------------------------------ geometry
+struct Geometry {
+  uint32_t d, dp, L, lgL, R, s, SP, wta_k, A, M, T;
+};
+
+const uint32_t kSupportedKs[] = {1, 2, 4, 6, 8, 12, 16};
+
+uint32_t padded_dim(uint32_t d) {
+  const uint32_t ks = (d + 63) / 64;
+  for (uint32_t k : kSupportedKs)
+    if (k >= ks) return 64 * k;
+  return 0;
+}
+
+bvs_status derive(const bvs_params* p, Geometry* g) {
+  if (!p) return fail(BVS_EINVAL, "params is NULL");
+  if (p->flags != 0) return fail(BVS_EINVAL, "flags must be 0");
+  if (p->dim < 1 || p->dim > 1024) return fail(BVS_ENOTSUP, "dim %u outside 1..1024", p->dim);
+  const uint32_t L = p->code_bits;
+  if (L < 256 || L > 4096 || (L & (L - 1)) != 0)
+    return fail(BVS_ENOTSUP, "code_bits %u must be a power of two in 256..4096", L);
+  if (p->fan_in < 1 || p->fan_in > p->dim) return fail(BVS_EINVAL, "fan_in %u outside 1..dim", p->fan_in);
+  const uint32_t SP = (p->fan_in + 7) / 8 * 8;
+  if ((uint64_t)L * SP > 65536) return fail(BVS_ENOTSUP, "code_bits * fan_in (rounded to 8) exceeds 65536");
+  uint32_t lgL = 0;
+  while ((1u << lgL) < L) ++lgL;
+  // key = ((y + s*4096) << lgL) | (L-1-j) with y + s*4096 <= s*8192 must fit 32 bits
+  if (((uint64_t)p->fan_in * 8192ull) >= (1ull << (32 - lgL)))
+    return fail(BVS_ENOTSUP, "fan_in %u too large for code_bits %u (winner-take-all key exceeds 32 bits)",
+                p->fan_in, L);
+  if (p->wta_k < 1 || p->wta_k > L) return fail(BVS_EINVAL, "wta_k %u outside 1..code_bits", p->wta_k);
+  if (p->access_lists < 1 || p->access_lists > 8) return fail(BVS_EINVAL, "access_lists %u outside 1..8", p->access_lists);
+  if (p->min_count > 255) return fail(BVS_EINVAL, "min_count %u outside 0..255", p->min_count);
+  if (p->top_t < 1 || p->top_t > 4096) return fail(BVS_ENOTSUP, "top_t %u outside 1..4096", p->top_t);
+  g->d = p->dim;
+  g->dp = padded_dim(p->dim);
+  g->L = L;
+  g->lgL = lgL;
+  g->R = L / 64;
+  g->s = p->fan_in;
+  g->SP = SP;
+  g->wta_k = p->wta_k;
+  g->A = p->access_lists;
+  g->M = p->min_count;
+  g->T = p->top_t;
+  return BVS_OK;
+}
+
+// Bump allocator over a caller-provided block (base = nullptr only measures).
+struct Carver {
+  uint8_t* base;
+  uint64_t off = 0;
+  explicit Carver(void* b) : base((uint8_t*)b) {}
+  template <typename T>
+  T* take(uint64_t count) {
+    off = align_up(off, 256);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int device_cus(int dev) {
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+  return n;
+}
+
+// splitmix64 (Steele, Lea and Flood, OOPSLA 2014).
+struct SplitMix64 {
+  uint64_t state;
+  uint64_t next() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+
+void make_projection(const Geometry& g, uint64_t seed, uint16_t* out /* [L][s] */) {
+  SplitMix64 rng{seed};
+  std::vector<uint32_t> row;
+  for (uint32_t j = 0; j < g.L; ++j) {
+    row.clear();
+    while (row.size() < g.s) {
+      const uint32_t i = (uint32_t)(((rng.next() >> 32) * (uint64_t)g.d) >> 32);
+      if (std::find(row.begin(), row.end(), i) == row.end()) row.push_back(i);
+    }
+    std::sort(row.begin(), row.end());
+    for (uint32_t i = 0; i < g.s; ++i) out[(uint64_t)j * g.s + i] = (uint16_t)row[i];
+  }
+}
+
+bvs_status check_offsets(const uint64_t* off, uint64_t n, uint32_t max_size, const char* what, uint32_t* max_m) {
+  if (!off) return fail(BVS_EINVAL, "%s offsets are NULL", what);
+  if (off[0] != 0) return fail(BVS_EINVAL, "%s offsets[0] must be 0", what);
+  uint64_t mm = 0;
+  for (uint64_t j = 0; j < n; ++j) {
+    if (off[j + 1] <= off[j]) return fail(BVS_EINVAL, "%s set %llu is empty or offsets decrease", what, (unsigned long long)j);
+    mm = std::max<uint64_t>(mm, off[j + 1] - off[j]);
+  }
+  if (mm > max_size)
+    return fail(BVS_ERANGE, "%s set of %llu vectors exceeds the limit %u", what, (unsigned long long)mm, max_size);
+  *max_m = (uint32_t)mm;
+  return BVS_OK;
+}
+
+bvs_status read_status(uint32_t* d_status, hipStream_t st, const char* what) {
+  uint32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, d_status, sizeof h, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h & ST_OFF_GRID)
+    return fail(BVS_ERANGE, "%s: a value is not on the 2^-12 grid, |x| > 1 or not finite", what);
+  if (h & ST_NORM) return fail(BVS_ERANGE, "%s: a vector has Euclidean norm above 2", what);
+  return BVS_OK;
+}
+
+}  // namespace
+
+struct bvs_index {
+  bvs_params p;
+  Geometry g;
+  uint64_t n, N, ld;
+  uint32_t max_m;
+  int device, n_cu;
+  uint16_t* idx;
+  uint64_t* offsets;
+  int8_t* hi;
+  uint8_t* lo;
+  uint32_t* norms;
+  uint8_t* cnt;
+  uint64_t* bits;
+};
+
+namespace {
+
+void layout_index(Carver& c, const Geometry& g, uint64_t n, uint64_t N, bvs_index* ix) {
+  const uint64_t ld = align_up(std::max<uint64_t>(n, 1), 256);
+  ix->idx = c.take<uint16_t>((uint64_t)g.L * g.SP);
+  ix->offsets = c.take<uint64_t>(n + 1);
+  ix->hi = c.take<int8_t>(N * g.dp);
+  ix->lo = c.take<uint8_t>(N * g.dp);
+  ix->norms = c.take<uint32_t>(N);
+  ix->cnt = c.take<uint8_t>((uint64_t)g.L * ld);
+  ix->bits = c.take<uint64_t>((uint64_t)g.R * ld);
+  ix->ld = ld;
+}
+
+HashGeom hash_geom(const bvs_index* ix) {
+  HashGeom h;
+  h.dim = ix->g.d;
+  h.dim_padded = ix->g.dp;
+  h.L = ix->g.L;
+  h.lgL = ix->g.lgL;
+  h.R = ix->g.R;
+  h.s = ix->g.s;
+  h.SP = ix->g.SP;
+  h.wta_k = ix->g.wta_k;
+  h.idx = ix->idx;
+  return h;
+}
+
+// Per-call query state carved from a workspace.
+struct QueryWs {
+  uint32_t* status;
+  uint64_t* qoff;
+  int8_t* qhi;
+  uint8_t* qlo;
+  uint32_t* qnorm;
+  // search only
+  uint64_t* codes;
+  uint16_t* cq;
+  uint64_t* sq;
+  uint32_t* pos;
+  uint64_t* gate;
+  uint64_t* gate_chunks;
+  uint16_t* scores;
+  SelectBufs sel;
+  uint32_t* f2_ids;
+  uint16_t* f2_scores;
+  uint32_t* f2_count;
+  uint32_t* h2;
+  uint64_t* topk_tmp;
+};
+
+constexpr uint32_t kMaxK = 64;
+
+void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, QueryWs* w) {
+  const Geometry& g = ix->g;
+  w->status = c.take<uint32_t>(4);
+  w->qoff = c.take<uint64_t>(n_q + 1);
+  w->qhi = c.take<int8_t>(NQ * g.dp);
+  w->qlo = c.take<uint8_t>(NQ * g.dp);
+  w->qnorm = c.take<uint32_t>(NQ);
+  w->codes = c.take<uint64_t>(NQ * g.R);
+  w->cq = c.take<uint16_t>((uint64_t)n_q * g.L);
+  w->sq = c.take<uint64_t>((uint64_t)n_q * g.R);
+  w->pos = c.take<uint32_t>((uint64_t)n_q * g.A);
+  w->gate = c.take<uint64_t>((uint64_t)n_q * g.R);
+  w->gate_chunks = c.take<uint64_t>(n_q);
+  w->scores = c.take<uint16_t>((uint64_t)n_q * ix->ld);
+  w->sel.hist = c.take<uint32_t>((uint64_t)n_q * (g.L + 2));
+  w->sel.sel = c.take<uint32_t>((uint64_t)n_q * 4);
+  w->sel.ctr = c.take<uint32_t>(n_q);
+  w->sel.eqcnt = c.take<uint32_t>((uint64_t)n_q * select_blocks(ix->ld));
+  w->sel.cand = c.take<uint64_t>((uint64_t)n_q * g.T);
+  w->f2_ids = c.take<uint32_t>((uint64_t)n_q * g.T);
+  w->f2_scores = c.take<uint16_t>((uint64_t)n_q * g.T);
+  w->f2_count = c.take<uint32_t>(n_q);
+  w->h2 = c.take<uint32_t>((uint64_t)n_q * g.T);
+  w->topk_tmp = c.take<uint64_t>(topk_tmp_words(g.T, n_q, kMaxK));
+}
+
+void layout_brute(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, QueryWs* w) {
+  const Geometry& g = ix->g;
+  std::memset(w, 0, sizeof *w);
+  w->status = c.take<uint32_t>(4);
+  w->qoff = c.take<uint64_t>(n_q + 1);
+  w->qhi = c.take<int8_t>(NQ * g.dp);
+  w->qlo = c.take<uint8_t>(NQ * g.dp);
+  w->qnorm = c.take<uint32_t>(NQ);
+  w->h2 = c.take<uint32_t>((uint64_t)n_q * ix->n);
+  w->topk_tmp = c.take<uint64_t>(topk_tmp_words(ix->n, n_q, kMaxK));
+}
+
+bvs_status check_queries(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                         uint32_t* max_rows) {
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (n_q == 0) return fail(BVS_EINVAL, "n_q must be positive");
+  if (!d_q) return fail(BVS_EINVAL, "query vectors are NULL");
+  BVS_TRY(check_offsets(h_q_off, n_q, 65535, "query", max_rows));
+  const uint32_t lim = haus_max_rows_supported(ix->g.dp);
+  if (*max_rows > lim)
+    return fail(BVS_ENOTSUP, "query set of %u vectors exceeds the %u supported at dim %u", *max_rows, lim, ix->g.d);
+  return BVS_OK;
+}
+
+// Upload offsets and convert the query vectors (status cleared first).
+bvs_status prepare_queries(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                           const QueryWs& w, hipStream_t st) {
+  const uint64_t NQ = h_q_off[n_q];
+  HIP_TRY(launch_fill_u32(w.status, 4, 0, st));
+  HIP_TRY(hipMemcpyAsync(w.qoff, h_q_off, (n_q + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_convert(d_q, NQ, ix->g.d, ix->g.dp, w.qhi, w.qlo, w.qnorm, w.status, ix->n_cu, st));
+  return BVS_OK;
+}
+
+bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const QueryWs& w, hipStream_t st) {
+  const Geometry& g = ix->g;
+  const HashGeom hg = hash_geom(ix);
+  HIP_TRY(launch_encode_vectors(hg, w.qhi, w.qlo, NQ, w.codes, ix->n_cu, st));
+  HIP_TRY(launch_query_sketch(w.codes, w.qoff, n_q, g.L, g.R, g.A, w.cq, w.sq, w.pos, w.gate, w.gate_chunks, st));
+  HIP_TRY(launch_filter(ix->bits, ix->cnt, ix->ld, ix->n, g.L, w.sq, w.gate, w.gate_chunks, w.pos, g.A, g.M, n_q,
+                        w.scores, st));
+  HIP_TRY(launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, w.f2_ids, w.f2_scores, w.f2_count, st));
+  return BVS_OK;
+}
+
+HausDb haus_db(const bvs_index* ix) {
+  HausDb d;
+  d.hi = ix->hi;
+  d.lo = ix->lo;
+  d.norms = ix->norms;
+  d.offsets = ix->offsets;
+  d.n_sets = ix->n;
+  d.dp = ix->g.dp;
+  return d;
+}
+
+HausQ haus_q(const QueryWs& w, uint32_t n_q, uint32_t max_rows) {
+  HausQ q;
+  q.hi = w.qhi;
+  q.lo = w.qlo;
+  q.norms = w.qnorm;
+  q.offsets = w.qoff;
+  q.n_q = n_q;
+  q.max_rows = max_rows;
+  return q;
+}
+
+bvs_status need_ws(uint64_t have, uint64_t need, void* ws) {
+  if (!ws) return fail(BVS_EINVAL, "workspace is NULL");
+  if (have < need)
+    return fail(BVS_ENOSPC, "workspace of %llu bytes, %llu needed", (unsigned long long)have, (unsigned long long)need);
+  return BVS_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* bvs_last_error(void) { return g_err.c_str(); }
+const char* bvs_version(void) { return "bvs 0.1 (gfx950)"; }
+
+void bvs_params_default(bvs_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->code_bits = 1024;
+  p->fan_in = 8;
+  p->wta_k = 64;
+  p->access_lists = 3;
+  p->min_count = 1;
+  p->top_t = 1000;
+}
+
+bvs_status bvs_params_check(const bvs_params* p) {
+  Geometry g;
+  return derive(p, &g);
+}
+
+bvs_status bvs_projection(const bvs_params* p, uint16_t* h_idx) {
+  Geometry g;
+  BVS_TRY(derive(p, &g));
+  if (!h_idx) return fail(BVS_EINVAL, "h_idx is NULL");
+  make_projection(g, p->seed, h_idx);
+  return BVS_OK;
+}
+
+bvs_status bvs_index_bytes(const bvs_params* p, uint64_t n_sets, uint64_t n_vectors, uint64_t* out) {
+  Geometry g;
+  BVS_TRY(derive(p, &g));
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  Carver c(nullptr);
+  bvs_index tmp;
+  layout_index(c, g, n_sets, n_vectors, &tmp);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_build_workspace_bytes(const bvs_params* p, uint64_t n_sets, uint64_t n_vectors, uint64_t* out) {
+  Geometry g;
+  BVS_TRY(derive(p, &g));
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  (void)n_vectors;
+  Carver c(nullptr);
+  c.take<uint32_t>(4);
+  c.take<uint8_t>(n_sets * g.L);
+  c.take<uint64_t>(n_sets * g.R);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_build_index(const bvs_params* p, const float* d_vectors, const uint64_t* h_offsets, uint64_t n_sets,
+                           void* d_index_mem, uint64_t index_bytes, void* d_ws, uint64_t ws_bytes, void* stream,
+                           bvs_index** out) {
+  Geometry g;
+  BVS_TRY(derive(p, &g));
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_sets == 0) return fail(BVS_EINVAL, "n_sets must be positive");
+  if (n_sets >= 0xFFFFFFFFull) return fail(BVS_ENOTSUP, "n_sets must be below 2^32 - 1");
+  if (!d_vectors) return fail(BVS_EINVAL, "vectors are NULL");
+  uint32_t max_m = 0;
+  BVS_TRY(check_offsets(h_offsets, n_sets, 255, "database", &max_m));
+  const uint64_t N = h_offsets[n_sets];
+  uint64_t need = 0, wneed = 0;
+  BVS_TRY(bvs_index_bytes(p, n_sets, N, &need));
+  BVS_TRY(bvs_build_workspace_bytes(p, n_sets, N, &wneed));
+  if (!d_index_mem) return fail(BVS_EINVAL, "index memory is NULL");
+  if (index_bytes < need)
+    return fail(BVS_ENOSPC, "index memory of %llu bytes, %llu needed", (unsigned long long)index_bytes,
+                (unsigned long long)need);
+  BVS_TRY(need_ws(ws_bytes, wneed, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+
+  bvs_index* ix = new bvs_index();
+  ix->p = *p;
+  ix->g = g;
+  ix->n = n_sets;
+  ix->N = N;
+  ix->max_m = max_m;
+  if (hipGetDevice(&ix->device) != hipSuccess) ix->device = 0;
+  ix->n_cu = device_cus(ix->device);
+  Carver c(d_index_mem);
+  layout_index(c, g, n_sets, N, ix);
+  Carver wc(d_ws);
+  uint32_t* status = wc.take<uint32_t>(4);
+  uint8_t* cnt_rm = wc.take<uint8_t>(n_sets * g.L);
+  uint64_t* bits_rm = wc.take<uint64_t>(n_sets * g.R);
+
+  // Projection rows padded to SP entries; padding indexes the zero slot dp.
+  std::vector<uint16_t> proj((size_t)g.L * g.s), padded((size_t)g.L * g.SP, (uint16_t)g.dp);
+  make_projection(g, p->seed, proj.data());
+  for (uint32_t j = 0; j < g.L; ++j)
+    for (uint32_t i = 0; i < g.s; ++i) padded[(size_t)j * g.SP + i] = proj[(size_t)j * g.s + i];
+
+  auto run = [&]() -> bvs_status {
+    HIP_TRY(hipMemcpyAsync(ix->idx, padded.data(), padded.size() * 2, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ix->offsets, h_offsets, (n_sets + 1) * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_fill_u32(status, 4, 0, st));
+    HIP_TRY(launch_convert(d_vectors, N, g.d, g.dp, ix->hi, ix->lo, ix->norms, status, ix->n_cu, st));
+    HIP_TRY(launch_encode_sets(hash_geom(ix), ix->hi, ix->lo, ix->offsets, n_sets, cnt_rm, bits_rm, ix->n_cu, st));
+    HIP_TRY(launch_transpose_sketches(cnt_rm, bits_rm, n_sets, ix->ld, g.L, ix->cnt, ix->bits, st));
+    return read_status(status, st, "database");
+  };
+  const bvs_status s = run();
+  if (s != BVS_OK) {
+    hipStreamSynchronize(st);
+    delete ix;
+    return s;
+  }
+  *out = ix;
+  return BVS_OK;
+}
+
+void bvs_index_destroy(bvs_index* ix) { delete ix; }
+
+bvs_status bvs_index_get_info(const bvs_index* ix, bvs_index_info* info) {
+  if (!ix || !info) return fail(BVS_EINVAL, "NULL argument");
+  info->n_sets = ix->n;
+  info->n_vectors = ix->N;
+  info->ld_sets = ix->ld;
+  info->dim_padded = ix->g.dp;
+  info->max_set_size = ix->max_m;
+  return BVS_OK;
+}
+
+bvs_status bvs_index_get_params(const bvs_index* ix, bvs_params* p) {
+  if (!ix || !p) return fail(BVS_EINVAL, "NULL argument");
+  *p = ix->p;
+  return BVS_OK;
+}
+
+bvs_status bvs_sketch_views(const bvs_index* ix, const uint8_t** d_count, const uint64_t** d_bits) {
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (d_count) *d_count = ix->cnt;
+  if (d_bits) *d_bits = ix->bits;
+  return BVS_OK;
+}
+
+bvs_status bvs_encode_workspace_bytes(const bvs_index* ix, uint64_t n, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  Carver c(nullptr);
+  c.take<uint32_t>(4);
+  c.take<int8_t>(n * ix->g.dp);
+  c.take<uint8_t>(n * ix->g.dp);
+  c.take<uint32_t>(n);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_encode(const bvs_index* ix, const float* d_x, uint64_t n, void* d_ws, uint64_t ws_bytes,
+                      uint64_t* d_codes, void* stream) {
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (n == 0) return BVS_OK;
+  if (!d_x || !d_codes) return fail(BVS_EINVAL, "NULL argument");
+  uint64_t need = 0;
+  BVS_TRY(bvs_encode_workspace_bytes(ix, n, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  uint32_t* status = c.take<uint32_t>(4);
+  int8_t* hi = c.take<int8_t>(n * ix->g.dp);
+  uint8_t* lo = c.take<uint8_t>(n * ix->g.dp);
+  uint32_t* norms = c.take<uint32_t>(n);
+  HIP_TRY(launch_fill_u32(status, 4, 0, st));
+  HIP_TRY(launch_convert(d_x, n, ix->g.d, ix->g.dp, hi, lo, norms, status, ix->n_cu, st));
+  HIP_TRY(launch_encode_vectors(hash_geom(ix), hi, lo, n, d_codes, ix->n_cu, st));
+  return read_status(status, st, "vectors");
+}
+
+bvs_status bvs_search_workspace_bytes(const bvs_index* ix, uint32_t n_q, uint64_t n_q_vectors, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  Carver c(nullptr);
+  QueryWs w;
+  layout_search(c, ix, n_q, n_q_vectors, &w);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_bruteforce_workspace_bytes(const bvs_index* ix, uint32_t n_q, uint64_t n_q_vectors, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  Carver c(nullptr);
+  QueryWs w;
+  layout_brute(c, ix, n_q, n_q_vectors, &w);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_query_sketch(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, void* d_ws,
+                            uint64_t ws_bytes, uint16_t* d_cq, uint64_t* d_sq, uint32_t* d_pos, void* stream) {
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_search_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  QueryWs w;
+  layout_search(c, ix, n_q, NQ, &w);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
+  const Geometry& g = ix->g;
+  HIP_TRY(launch_encode_vectors(hash_geom(ix), w.qhi, w.qlo, NQ, w.codes, ix->n_cu, st));
+  HIP_TRY(launch_query_sketch(w.codes, w.qoff, n_q, g.L, g.R, g.A, w.cq, w.sq, w.pos, w.gate, w.gate_chunks, st));
+  if (d_cq) HIP_TRY(hipMemcpyAsync(d_cq, w.cq, (uint64_t)n_q * g.L * 2, hipMemcpyDeviceToDevice, st));
+  if (d_sq) HIP_TRY(hipMemcpyAsync(d_sq, w.sq, (uint64_t)n_q * g.R * 8, hipMemcpyDeviceToDevice, st));
+  if (d_pos) HIP_TRY(hipMemcpyAsync(d_pos, w.pos, (uint64_t)n_q * g.A * 4, hipMemcpyDeviceToDevice, st));
+  return read_status(w.status, st, "queries");
+}
+
+bvs_status bvs_search_candidates(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                                 void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, uint16_t* d_scores,
+                                 uint32_t* d_count, void* stream) {
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  if (!d_ids || !d_scores || !d_count) return fail(BVS_EINVAL, "NULL output");
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_search_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  QueryWs w;
+  layout_search(c, ix, n_q, NQ, &w);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
+  const Geometry& g = ix->g;
+  const HashGeom hg = hash_geom(ix);
+  HIP_TRY(launch_encode_vectors(hg, w.qhi, w.qlo, NQ, w.codes, ix->n_cu, st));
+  HIP_TRY(launch_query_sketch(w.codes, w.qoff, n_q, g.L, g.R, g.A, w.cq, w.sq, w.pos, w.gate, w.gate_chunks, st));
+  HIP_TRY(launch_filter(ix->bits, ix->cnt, ix->ld, ix->n, g.L, w.sq, w.gate, w.gate_chunks, w.pos, g.A, g.M, n_q,
+                        w.scores, st));
+  HIP_TRY(launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, d_ids, d_scores, d_count, st));
+  return read_status(w.status, st, "queries");
+}
+
+bvs_status bvs_search(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
+                      void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                      void* stream) {
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
+  if (k < 1 || k > kMaxK || k > ix->g.T) return fail(BVS_EINVAL, "k %u outside 1..min(64, top_t)", k);
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_search_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  QueryWs w;
+  layout_search(c, ix, n_q, NQ, &w);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
+  BVS_TRY(run_filters(ix, n_q, NQ, w, st));
+  HIP_TRY(launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, w.h2, st));
+  HIP_TRY(launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st));
+  return read_status(w.status, st, "queries");
+}
+
+bvs_status bvs_bruteforce(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
+                          void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                          void* stream) {
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
+  if (k < 1 || k > kMaxK) return fail(BVS_EINVAL, "k %u outside 1..64", k);
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_bruteforce_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  QueryWs w;
+  layout_brute(c, ix, n_q, NQ, &w);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
+  HIP_TRY(launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), w.h2, st));
+  HIP_TRY(launch_topk(w.h2, nullptr, nullptr, ix->n, ix->n, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st));
+  return read_status(w.status, st, "queries");
+}
+
+bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                             void* d_ws, uint64_t ws_bytes, uint32_t* d_h2, void* stream) {
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  if (!d_h2) return fail(BVS_EINVAL, "NULL output");
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_bruteforce_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  QueryWs w;
+  layout_brute(c, ix, n_q, NQ, &w);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
+  HIP_TRY(launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), d_h2, st));
+  return read_status(w.status, st, "queries");
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Device helpers shared by the gfx950 kernels: wave-level ballots and
+// reductions, DPP row reductions and the int8 matrix-core step.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BVS_WAVE 64
+
+namespace bvs {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ uint32_t popc32(uint32_t x) { return __builtin_popcount(x); }
+__device__ __forceinline__ uint32_t popc64(uint64_t x) { return __builtin_popcountll(x); }
+
+// Order LDS traffic of one wave: the write of one lane is visible to a later
+// read of another lane of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t v, int m) {
+  return (uint32_t)__shfl_xor((int)v, m, BVS_WAVE);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = max(v, shfl_xor_u32(v, m));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = min(v, shfl_xor_u32(v, m));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_u32(v, m);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    uint32_t olo = shfl_xor_u32(lo, m), ohi = shfl_xor_u32(hi, m);
+    uint64_t s = ((uint64_t)hi << 32 | lo) + ((uint64_t)ohi << 32 | olo);
+    lo = (uint32_t)s; hi = (uint32_t)(s >> 32);
+  }
+  return (uint64_t)hi << 32 | lo;
+}
+
+// Minimum over the 16 lanes of a DPP row (lanes 16r .. 16r+15); every lane
+// of the row receives the result.  row_ror:n has DPP control 0x120 + n.
+__device__ __forceinline__ uint32_t row16_min_u32(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xF, 0xF, false));
+  return v;
+}
+
+// One 16x16x64 int8 matrix-core step with int32 accumulation:
+//   C[i][j] += sum_k A[i][k] * B[k][j]
+// A row i and B column j both come from lane (i or j) + 16 * g, which holds
+// 16 consecutive k of k-group g.  C[4 * (l / 16) + r][l % 16] is element r of
+// lane l.  Integer accumulation wraps modulo 2^32, so sums whose true value
+// fits int32 are exact whatever the partial sums are.
+__device__ __forceinline__ v4i mfma_i8(v4i a, v4i b, v4i c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
+__host__ __device__ constexpr uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Status bits raised by kernels that validate data.
+enum : uint32_t {
+  ST_OFF_GRID = 1u,     // a value is not a multiple of 2^-12 or |x| > 1 (or not finite)
+  ST_NORM = 2u,         // a row has Euclidean norm > 2
+};
+
+}  // namespace bvs

@@ -1,0 +1,433 @@
+// FlyHash encoding and per-set Bloom sketches on gfx950.
+//
+//   convert         float32 rows -> exact int8 planes (a = 4096 x = 64 hi + lo)
+//                   and squared norms; validates the 2^-12 grid
+//   encode_vectors  one wave per vector: projection y = W a (Def. 7) with the
+//                   sparse rows of W read from an LDS copy of the index table,
+//                   then winner-take-all (Alg. 1): the wta_k largest outputs
+//   encode_sets     one wave per set: the same per member, accumulating the
+//                   count Bloom filter (Def. 8, Alg. 3) in packed byte
+//                   counters and the binary Bloom filter (Def. 10, Alg. 5)
+//                   as OR bits; writes row-major scratch
+//   transpose       scratch -> position-major counts and chunk-major bits
+//   query_sketch    query count filter C_Q, sketch S_Q and the A positions of
+//                   largest count (first steps of Alg. 6)
+//
+// Winner-take-all with ties to the lower output index: output j of a vector
+// gets the unique key ((y_j + s*4096) << log2 L) | (L - 1 - j); y_j is an
+// integer in [-s*4096, s*4096] on the grid, so a larger key means a larger
+// y_j or, for equal y_j, a lower j.  The wta_k-th largest key is found by
+// setting bits from the top while at least wta_k keys stay >= the prefix;
+// counts are sums of wave ballots.  Lane l owns outputs j = l + 64 t, so the
+// ballot of "key_t >= threshold" is directly code word t.
+#include "device.h"
+#include "launch.h"
+
+namespace bvs {
+
+// ---------------------------------------------------------------- convert
+__global__ void __launch_bounds__(256)
+k_convert(const float* __restrict__ x, uint64_t n_rows, uint32_t d, uint32_t dp,
+          int8_t* __restrict__ hi, uint8_t* __restrict__ lo, uint32_t* __restrict__ norms,
+          uint32_t* __restrict__ status) {
+  const uint32_t lane = lane_id();
+  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / BVS_WAVE;
+  const uint64_t nwaves = (gridDim.x * (uint64_t)blockDim.x) / BVS_WAVE;
+  uint32_t bad = 0;
+  for (uint64_t r = wave; r < n_rows; r += nwaves) {
+    const float* xr = x + r * d;
+    uint64_t ss = 0;
+    for (uint32_t e = lane; e < dp; e += BVS_WAVE) {
+      int a = 0;
+      if (e < d) {
+        const float v = xr[e];
+        const float s = v * 4096.0f;
+        float ri = rintf(s);
+        if (!(ri == s) || !(fabsf(v) <= 1.0f)) { bad |= ST_OFF_GRID; ri = 0.0f; }
+        a = (int)ri;
+      }
+      hi[r * dp + e] = (int8_t)(a >> 6);   // floor(a / 64) in [-64, 64]
+      lo[r * dp + e] = (uint8_t)(a & 63);  // a - 64 floor(a / 64) in [0, 63]
+      ss += (uint64_t)(a * a);
+    }
+    ss = wave_sum_u64(ss);
+    if (ss > (1ull << 26)) bad |= ST_NORM;  // ||x|| > 2
+    if (lane == 0) norms[r] = (uint32_t)(ss > 0xFFFFFFFFull ? 0xFFFFFFFFull : ss);
+  }
+  const uint64_t b1 = ballot(bad & ST_OFF_GRID), b2 = ballot(bad & ST_NORM);
+  if (lane == 0 && (b1 | b2)) atomicOr(status, (b1 ? ST_OFF_GRID : 0u) | (b2 ? ST_NORM : 0u));
+}
+
+hipError_t launch_convert(const float* x, uint64_t n_rows, uint32_t d, uint32_t dp, int8_t* hi,
+                          uint8_t* lo, uint32_t* norms, uint32_t* status, int n_cu, hipStream_t st) {
+  if (n_rows == 0) return hipSuccess;
+  const uint64_t want = (n_rows + 3) / 4;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)n_cu * 32);
+  hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, st, x, n_rows, d, dp, hi, lo, norms, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- hashing
+// Stage one vector (a = 64 hi + lo) into the wave's LDS slot as int16.
+__device__ __forceinline__ void stage_vector(int16_t* __restrict__ av, const int8_t* __restrict__ hi,
+                                             const uint8_t* __restrict__ lo, uint64_t row, uint32_t dp,
+                                             uint32_t lane) {
+  const uint32_t* h4 = (const uint32_t*)(hi + row * dp);
+  const uint32_t* l4 = (const uint32_t*)(lo + row * dp);
+  for (uint32_t e4 = lane; e4 < dp / 4; e4 += BVS_WAVE) {
+    const uint32_t h = h4[e4], l = l4[e4];
+    int16_t v[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      v[b] = (int16_t)(64 * (int)(int8_t)(h >> (8 * b)) + (int)((l >> (8 * b)) & 0xFF));
+    uint2 packed;
+    packed.x = (uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
+    packed.y = (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16);
+    *(uint2*)(av + 4 * e4) = packed;
+  }
+}
+
+// Keys of the R outputs owned by this lane (j = lane + 64 t).
+template <int R>
+__device__ __forceinline__ void hash_keys(const int16_t* __restrict__ av, const uint16_t* __restrict__ idx,
+                                          uint32_t SP, uint32_t koff, uint32_t lgL, uint32_t L,
+                                          uint32_t lane, uint32_t (&key)[R]) {
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const uint32_t j = lane + 64u * t;
+    const uint16_t* row = idx + j * SP;
+    int y = 0;
+    for (uint32_t i0 = 0; i0 < SP; i0 += 8) {
+      const uint4 w = *(const uint4*)(row + i0);
+      y += av[w.x & 0xFFFF] + av[w.x >> 16] + av[w.y & 0xFFFF] + av[w.y >> 16] +
+           av[w.z & 0xFFFF] + av[w.z >> 16] + av[w.w & 0xFFFF] + av[w.w >> 16];
+    }
+    key[t] = ((uint32_t)(y + (int)koff) << lgL) | (L - 1u - j);
+  }
+}
+
+// The k-th largest of the wave's 64 R unique keys.
+template <int R>
+__device__ __forceinline__ uint32_t kth_largest(const uint32_t (&key)[R], uint32_t k, int topbit) {
+  uint32_t theta = 0;
+  for (int b = topbit; b >= 0; --b) {
+    const uint32_t cand = theta | (1u << b);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) cnt += popc64(ballot(key[t] >= cand));
+    if (cnt == k) {
+      // Exactly k keys reach the prefix: the k-th largest is their minimum.
+      uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+      for (int t = 0; t < R; ++t) mn = key[t] >= cand ? min(mn, key[t]) : mn;
+      return wave_min_u32(mn);
+    }
+    if (cnt > k) theta = cand;
+  }
+  return theta;
+}
+
+struct EncodeShared {
+  uint16_t* idx;   // [L][SP]
+  int16_t* av;     // this wave's staged vector, dim_padded + 8 entries (tail zero)
+};
+
+__device__ __forceinline__ EncodeShared encode_setup(const HashGeom& g, uint8_t* smem) {
+  EncodeShared sh;
+  sh.idx = (uint16_t*)smem;
+  const uint32_t tab_bytes = (uint32_t)align_up((uint64_t)g.L * g.SP * 2, 16);
+  const uint32_t w = threadIdx.x / BVS_WAVE;
+  sh.av = (int16_t*)(smem + tab_bytes) + w * (g.dim_padded + 8);
+  const uint32_t n16 = g.L * g.SP / 8;
+  for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) ((uint4*)sh.idx)[i] = ((const uint4*)g.idx)[i];
+  if (lane_id() < 8) sh.av[g.dim_padded + lane_id()] = 0;
+  __syncthreads();
+  return sh;
+}
+
+__host__ __device__ inline int key_topbit(const HashGeom& g) {
+  const uint64_t maxkey = ((uint64_t)(2u * g.s * 4096u) << g.lgL) | (g.L - 1u);
+  int b = 63;
+  while (b > 0 && !((maxkey >> b) & 1)) --b;
+  return b;
+}
+
+size_t encode_lds_bytes(const HashGeom& g, uint32_t waves) {
+  return align_up((uint64_t)g.L * g.SP * 2, 16) + (size_t)waves * (g.dim_padded + 8) * 2;
+}
+
+template <int R>
+__global__ void __launch_bounds__(512)
+k_encode_vectors(HashGeom g, const int8_t* __restrict__ hi, const uint8_t* __restrict__ lo, uint64_t n,
+                 uint64_t* __restrict__ codes, int topbit) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const EncodeShared sh = encode_setup(g, smem);
+  const uint32_t lane = lane_id();
+  const uint32_t nw = blockDim.x / BVS_WAVE;
+  const uint32_t koff = g.s * 4096u;
+  for (uint64_t v = blockIdx.x * (uint64_t)nw + threadIdx.x / BVS_WAVE; v < n; v += (uint64_t)gridDim.x * nw) {
+    stage_vector(sh.av, hi, lo, v, g.dim_padded, lane);
+    wave_lds_sync();
+    uint32_t key[R];
+    hash_keys<R>(sh.av, sh.idx, g.SP, koff, g.lgL, g.L, lane, key);
+    const uint32_t th = kth_largest<R>(key, g.wta_k, topbit);
+    uint64_t w0 = 0, w1 = 0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const uint64_t wv = ballot(key[t] >= th);
+      if (t < 64) { if (lane == (uint32_t)t) w0 = wv; }
+      else if (lane == (uint32_t)(t - 64)) w1 = wv;
+    }
+    if (lane < (uint32_t)R) codes[v * R + lane] = w0;
+    if (R > 64 && lane + 64 < (uint32_t)R) codes[v * R + lane + 64] = w1;
+    wave_lds_sync();
+  }
+}
+
+template <int R>
+__global__ void __launch_bounds__(512)
+k_encode_sets(HashGeom g, const int8_t* __restrict__ hi, const uint8_t* __restrict__ lo,
+              const uint64_t* __restrict__ offsets, uint64_t n_sets, uint8_t* __restrict__ cnt_rm,
+              uint64_t* __restrict__ bits_rm, int topbit) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const EncodeShared sh = encode_setup(g, smem);
+  const uint32_t lane = lane_id();
+  const uint32_t nw = blockDim.x / BVS_WAVE;
+  const uint32_t koff = g.s * 4096u;
+  constexpr int NC = (R + 3) / 4;
+  constexpr int NO = (R + 63) / 64;
+  for (uint64_t set = blockIdx.x * (uint64_t)nw + threadIdx.x / BVS_WAVE; set < n_sets;
+       set += (uint64_t)gridDim.x * nw) {
+    uint32_t cnt[NC];
+    uint64_t orb[NO];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) cnt[i] = 0;
+#pragma unroll
+    for (int i = 0; i < NO; ++i) orb[i] = 0;
+    const uint64_t o0 = offsets[set], o1 = offsets[set + 1];
+    for (uint64_t v = o0; v < o1; ++v) {
+      stage_vector(sh.av, hi, lo, v, g.dim_padded, lane);
+      wave_lds_sync();
+      uint32_t key[R];
+      hash_keys<R>(sh.av, sh.idx, g.SP, koff, g.lgL, g.L, lane, key);
+      const uint32_t th = kth_largest<R>(key, g.wta_k, topbit);
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const uint32_t b = key[t] >= th ? 1u : 0u;
+        cnt[t / 4] += b << (8 * (t % 4));   // a set has at most 255 members
+        orb[t / 64] |= (uint64_t)b << (t % 64);
+      }
+      wave_lds_sync();
+    }
+    uint8_t* cr = cnt_rm + set * g.L;
+#pragma unroll
+    for (int t = 0; t < R; ++t) cr[64u * t + lane] = (uint8_t)(cnt[t / 4] >> (8 * (t % 4)));
+    uint64_t w0 = 0, w1 = 0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const uint64_t wv = ballot((orb[t / 64] >> (t % 64)) & 1);
+      if (t < 64) { if (lane == (uint32_t)t) w0 = wv; }
+      else if (lane == (uint32_t)(t - 64)) w1 = wv;
+    }
+    if (lane < (uint32_t)R) bits_rm[set * R + lane] = w0;
+    if (R > 64 && lane + 64 < (uint32_t)R) bits_rm[set * R + lane + 64] = w1;
+  }
+}
+
+template <typename F>
+static hipError_t dispatch_R(uint32_t R, F&& f) {
+  switch (R) {
+    case 4: return f(std::integral_constant<int, 4>());
+    case 8: return f(std::integral_constant<int, 8>());
+    case 16: return f(std::integral_constant<int, 16>());
+    case 32: return f(std::integral_constant<int, 32>());
+    case 64: return f(std::integral_constant<int, 64>());
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static constexpr uint32_t kEncodeWaves = 8;
+
+hipError_t launch_encode_vectors(const HashGeom& g, const int8_t* hi, const uint8_t* lo, uint64_t n,
+                                 uint64_t* codes, int n_cu, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t lds = encode_lds_bytes(g, kEncodeWaves);
+  const int topbit = key_topbit(g);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kEncodeWaves - 1) / kEncodeWaves, (uint64_t)n_cu);
+  return dispatch_R(g.R, [&](auto rc) -> hipError_t {
+    constexpr int R = decltype(rc)::value;
+    hipError_t e = hipFuncSetAttribute((const void*)k_encode_vectors<R>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_encode_vectors<R>, dim3(grid), dim3(64 * kEncodeWaves), lds, st, g, hi, lo, n,
+                       codes, topbit);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_encode_sets(const HashGeom& g, const int8_t* hi, const uint8_t* lo,
+                              const uint64_t* offsets, uint64_t n_sets, uint8_t* cnt_rm,
+                              uint64_t* bits_rm, int n_cu, hipStream_t st) {
+  if (n_sets == 0) return hipSuccess;
+  const size_t lds = encode_lds_bytes(g, kEncodeWaves);
+  const int topbit = key_topbit(g);
+  const uint32_t grid =
+      (uint32_t)std::min<uint64_t>((n_sets + kEncodeWaves - 1) / kEncodeWaves, (uint64_t)n_cu);
+  return dispatch_R(g.R, [&](auto rc) -> hipError_t {
+    constexpr int R = decltype(rc)::value;
+    hipError_t e = hipFuncSetAttribute((const void*)k_encode_sets<R>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_encode_sets<R>, dim3(grid), dim3(64 * kEncodeWaves), lds, st, g, hi, lo,
+                       offsets, n_sets, cnt_rm, bits_rm, topbit);
+    return hipGetLastError();
+  });
+}
+
+// ---------------------------------------------------------------- transposes
+// counts [n][L] -> [L][ld]; tile = 128 sets x 256 positions.
+__global__ void __launch_bounds__(256)
+k_transpose_counts(const uint8_t* __restrict__ src, uint64_t n_sets, uint64_t ld, uint32_t L,
+                   uint8_t* __restrict__ dst) {
+  __shared__ uint8_t tile[128][256 + 4];
+  const uint32_t p0 = blockIdx.x * 256u;
+  const uint64_t s0 = (uint64_t)blockIdx.y * 128u;
+  const uint32_t t = threadIdx.x;
+  // read: 16 threads per set row (16 B each), 16 rows per pass
+  for (uint32_t r = t / 16; r < 128; r += 16) {
+    const uint64_t set = s0 + r;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (set < n_sets) v = *(const uint4*)(src + set * L + p0 + 16u * (t % 16));
+    uint32_t* dw = (uint32_t*)&tile[r][16u * (t % 16)];
+    dw[0] = v.x; dw[1] = v.y; dw[2] = v.z; dw[3] = v.w;
+  }
+  __syncthreads();
+  // write: 8 threads per position row (16 sets each), 32 rows per pass
+  for (uint32_t pr = t / 8; pr < 256; pr += 32) {
+    const uint32_t c0 = 16u * (t % 8);
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      w[q] = (uint32_t)tile[c0 + 4 * q + 0][pr] | ((uint32_t)tile[c0 + 4 * q + 1][pr] << 8) |
+             ((uint32_t)tile[c0 + 4 * q + 2][pr] << 16) | ((uint32_t)tile[c0 + 4 * q + 3][pr] << 24);
+    }
+    if (s0 + c0 < ld) *(uint4*)(dst + (uint64_t)(p0 + pr) * ld + s0 + c0) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// bits [n][R] u64 -> chunk-major [R/2][ld] of 16-byte chunks; tile = 64 sets.
+__global__ void __launch_bounds__(256)
+k_transpose_bits(const uint64_t* __restrict__ src, uint64_t n_sets, uint64_t ld, uint32_t R,
+                 uint64_t* __restrict__ dst) {
+  extern __shared__ __align__(16) uint4 tb[];   // [64][RC + 1]
+  const uint32_t RC = R / 2;
+  const uint64_t s0 = (uint64_t)blockIdx.x * 64u;
+  for (uint32_t i = threadIdx.x; i < 64u * RC; i += blockDim.x) {
+    const uint32_t r = i / RC, c = i % RC;
+    const uint64_t set = s0 + r;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (set < n_sets) v = ((const uint4*)(src + set * R))[c];
+    tb[r * (RC + 1) + c] = v;
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < 64u * RC; i += blockDim.x) {
+    const uint32_t c = i / 64, r = i % 64;
+    if (s0 + r < ld) ((uint4*)dst)[(uint64_t)c * ld + s0 + r] = tb[r * (RC + 1) + c];
+  }
+}
+
+hipError_t launch_transpose_sketches(const uint8_t* cnt_rm, const uint64_t* bits_rm, uint64_t n_sets,
+                                     uint64_t ld, uint32_t L, uint8_t* cnt, uint64_t* bits,
+                                     hipStream_t st) {
+  const uint32_t R = L / 64;
+  dim3 g1(L / 256 ? L / 256 : 1, (uint32_t)((ld + 127) / 128));
+  if (L % 256 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose_counts, g1, dim3(256), 0, st, cnt_rm, n_sets, ld, L, cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)64 * (R / 2 + 1) * 16;
+  e = hipFuncSetAttribute((const void*)k_transpose_bits, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_transpose_bits, dim3((uint32_t)((ld + 63) / 64)), dim3(256), lds, st, bits_rm,
+                     n_sets, ld, R, bits);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- query sketch
+// One wave per query.  Lane l owns code words t = l and l + 64.
+__global__ void __launch_bounds__(64)
+k_query_sketch(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ q_off, uint32_t L,
+               uint32_t R, uint32_t A, uint32_t lgL, uint16_t* __restrict__ cq, uint64_t* __restrict__ sq,
+               uint32_t* __restrict__ pos, uint64_t* __restrict__ gate, uint64_t* __restrict__ gate_chunks) {
+  const uint32_t q = blockIdx.x, lane = lane_id();
+  const uint64_t o0 = q_off[q], o1 = q_off[q + 1];
+  uint16_t* cqq = cq + (uint64_t)q * L;
+  for (uint32_t t = lane; t < R; t += BVS_WAVE) {
+    uint32_t c[64];
+#pragma unroll
+    for (int b = 0; b < 64; ++b) c[b] = 0;
+    uint64_t orw = 0;
+    for (uint64_t v = o0; v < o1; ++v) {
+      const uint64_t w = codes[v * R + t];
+      orw |= w;
+#pragma unroll
+      for (int b = 0; b < 64; ++b) c[b] += (uint32_t)((w >> b) & 1);
+    }
+    sq[(uint64_t)q * R + t] = orw;
+#pragma unroll
+    for (int b = 0; b < 64; b += 2)
+      *(uint32_t*)(cqq + 64u * t + b) = (c[b] & 0xFFFF) | ((c[b + 1] & 0xFFFF) << 16);
+  }
+  __syncthreads();
+  // The A largest (count, -position) keys, one per round.
+  uint32_t last = 0xFFFFFFFFu;
+  uint32_t p[8];
+  for (uint32_t a = 0; a < A; ++a) {
+    uint32_t best = 0;
+    bool found = false;
+    for (uint32_t i = lane; i < L; i += BVS_WAVE) {
+      const uint32_t key = ((uint32_t)cqq[i] << lgL) | (L - 1u - i);
+      if (key < last && (!found || key > best)) { best = key; found = true; }
+    }
+    // keys are unique and >= 0; a lane with no candidate contributes 0, which
+    // can only win when fewer than A positions exist (A <= L is checked).
+    last = wave_max_u32(best);
+    p[a] = L - 1u - (last & (L - 1u));
+    if (lane == 0) pos[(uint64_t)q * A + a] = p[a];
+  }
+  uint64_t chunks = 0;
+  for (uint32_t a = 0; a < A; ++a) chunks |= 1ull << (p[a] >> 7);
+  for (uint32_t t = lane; t < R; t += BVS_WAVE) {
+    uint64_t gw = 0;
+    for (uint32_t a = 0; a < A; ++a)
+      if ((p[a] >> 6) == t) gw |= 1ull << (p[a] & 63);
+    gate[(uint64_t)q * R + t] = gw;
+  }
+  if (lane == 0) gate_chunks[q] = chunks;
+}
+
+hipError_t launch_query_sketch(const uint64_t* codes, const uint64_t* q_off, uint32_t n_q, uint32_t L,
+                               uint32_t R, uint32_t A, uint16_t* cq, uint64_t* sq, uint32_t* pos,
+                               uint64_t* gate, uint64_t* gate_chunks, hipStream_t st) {
+  if (n_q == 0) return hipSuccess;
+  uint32_t lgL = 0;
+  while ((1u << lgL) < L) ++lgL;
+  hipLaunchKernelGGL(k_query_sketch, dim3(n_q), dim3(64), 0, st, codes, q_off, L, R, A, lgL, cq, sq, pos,
+                     gate, gate_chunks);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- fill
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace bvs

@@ -1,0 +1,92 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bvs {
+
+// Geometry of the hashing step shared by the encode kernels.
+struct HashGeom {
+  uint32_t dim, dim_padded;    // d and d rounded up to 64
+  uint32_t L, lgL, R;          // code bits, log2 L (L is a power of two) or 0, L / 64
+  uint32_t s, SP;              // fan-in and fan-in rounded up to 8 (row stride of idx)
+  uint32_t wta_k;
+  const uint16_t* idx;         // device [L][SP]; padding entries index the zero slot dim_padded
+};
+
+// float32 rows -> exact int8 planes a = 64 * hi + lo (a = 4096 x), squared
+// norms of a, and status bits.
+hipError_t launch_convert(const float* x, uint64_t n_rows, uint32_t d, uint32_t dp,
+                          int8_t* hi, uint8_t* lo, uint32_t* norms, uint32_t* status,
+                          int n_cu, hipStream_t st);
+
+// Codes of single vectors: codes [n][R] uint64.
+hipError_t launch_encode_vectors(const HashGeom& g, const int8_t* hi, const uint8_t* lo,
+                                 uint64_t n, uint64_t* codes, int n_cu, hipStream_t st);
+
+// Per-set sketches in row-major scratch: counts [n][L] u8, bits [n][R] u64.
+hipError_t launch_encode_sets(const HashGeom& g, const int8_t* hi, const uint8_t* lo,
+                              const uint64_t* offsets, uint64_t n_sets,
+                              uint8_t* cnt_rm, uint64_t* bits_rm, int n_cu, hipStream_t st);
+
+// Row-major scratch -> index layouts: counts [L][ld], bits chunk-major [R/2][ld][2].
+hipError_t launch_transpose_sketches(const uint8_t* cnt_rm, const uint64_t* bits_rm,
+                                     uint64_t n_sets, uint64_t ld, uint32_t L,
+                                     uint8_t* cnt, uint64_t* bits, hipStream_t st);
+
+// Query sketches from query codes: C_Q [n_q][L] u16, S_Q [n_q][R] u64,
+// top-A positions [n_q][A] u32, gate masks [n_q][R] u64 (bits of the A
+// positions) and the chunk mask of the gates [n_q] u64.
+hipError_t launch_query_sketch(const uint64_t* codes, const uint64_t* q_off, uint32_t n_q,
+                               uint32_t L, uint32_t R, uint32_t A,
+                               uint16_t* cq, uint64_t* sq, uint32_t* pos,
+                               uint64_t* gate, uint64_t* gate_chunks, hipStream_t st);
+
+// Second-layer scores: scores [n_q][ld] u16 (0xFFFF = not in F1).
+hipError_t launch_filter(const uint64_t* bits, const uint8_t* cnt, uint64_t ld, uint64_t n_sets,
+                         uint32_t L, const uint64_t* sq, const uint64_t* gate,
+                         const uint64_t* gate_chunks, const uint32_t* pos, uint32_t A,
+                         uint32_t M, uint32_t n_q, uint16_t* scores, hipStream_t st);
+
+// Top-T selection of the scores; writes F2 sorted by (score, id).
+struct SelectBufs {
+  uint32_t* hist;     // [n_q][L + 2]
+  uint32_t* sel;      // [n_q][4]: tau, count_below, need_eq, Tq
+  uint32_t* ctr;      // [n_q]
+  uint32_t* eqcnt;    // [n_q][nblk]
+  uint64_t* cand;     // [n_q][T]
+};
+uint32_t select_blocks(uint64_t ld);
+hipError_t launch_select(const uint16_t* scores, uint64_t ld, uint32_t L, uint32_t T, uint32_t n_q,
+                         const SelectBufs& b, uint32_t* f2_ids, uint16_t* f2_scores,
+                         uint32_t* f2_count, hipStream_t st);
+
+// Exact squared Hausdorff distances (scaled by 2^24).
+struct HausDb {
+  const int8_t* hi; const uint8_t* lo; const uint32_t* norms; const uint64_t* offsets;
+  uint64_t n_sets; uint32_t dp;
+};
+struct HausQ {
+  const int8_t* hi; const uint8_t* lo; const uint32_t* norms; const uint64_t* offsets;
+  uint32_t n_q; uint32_t max_rows;
+};
+// Candidate mode: items are ids[q][0 .. count[q]) with stride T.
+hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids,
+                            const uint32_t* count, uint32_t T, uint32_t* h2, hipStream_t st);
+// All sets: h2 [n_q][n_sets].
+hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipStream_t st);
+size_t haus_lds_bytes(uint32_t max_rows, uint32_t dp);
+uint32_t haus_max_rows_supported(uint32_t dp);
+
+// First k by (h2, id) of each query.  ids_in may be NULL (item index = id).
+// tmp must hold 2 * n_q * ceil(n_items / 4096) * k uint64.
+hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_t* count_in,
+                       uint64_t n_items, uint64_t stride, uint32_t n_q, uint32_t k,
+                       uint64_t* tmp, uint32_t* ids, float* dist, uint32_t* count,
+                       hipStream_t st);
+uint64_t topk_tmp_words(uint64_t n_items, uint32_t n_q, uint32_t k);
+
+// Fill a u32 buffer (used instead of hipMemsetAsync so work stays graph-safe).
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+
+}  // namespace bvs
