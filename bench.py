@@ -1,0 +1,310 @@
+#!/usr/bin/env python3
+"""Throughput of the cascade vector-set search on one MI355X.
+
+Workload (default "scale"): 1,000,000 synthetic sets with sizes uniform in
+5-100 (52.5M vectors), d = 384, 10,000 topics; FlyHash L = 4096, s = 16,
+wta_k = 64; A = 3, M = 1, T = 1000; 1,024 subset queries; top-10.  Data is
+drawn on the GPU by paper_2412_03301_amd.synth and stays resident in HBM.
+
+One step = one bvs_search call over the whole query batch: query
+conversion and encoding, query sketches, second-layer scores of every set,
+top-T selection, exact Hausdorff re-rank and top-k.  The timed region holds
+exactly `--steps` steps bracketed by device synchronisation.
+
+Also reported: recall@10 against the exact GPU brute force (on a sample of
+the queries), the brute-force throughput on that sample, per-stage times
+from HIP events recorded by the library on its stream, the roofline of the
+dominant kernel, and the CPU oracle timed on a bounded sample.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "queries/sec at recall@10>=0.95 on 1M sets vs GPU brute-force Hausdorff"
+HBM_PEAK_GBS = 8000.0
+# Integer VALU lanes: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s.
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="scale", choices=["scale", "tiny"])
+    ap.add_argument("--n-sets", type=int, default=None, help="override the set count (for quick runs)")
+    ap.add_argument("--queries", type=int, default=None)
+    ap.add_argument("--top-t", type=int, default=None)
+    ap.add_argument("--brute-queries", type=int, default=128)
+    ap.add_argument("--cpu-sample-sets", type=int, default=1000)
+    ap.add_argument("--cpu-sample-queries", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-brute", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration runs)")
+    return ap.parse_args()
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_file, kernel_prefix):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"pmc_{kernel_prefix}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        if d.get("source_sha") != source_sha(kernel_file):
+            return None
+        return d.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(db_cpu, offsets, q_cpu, q_off, cfg, n_sets_full, sample_sets, sample_queries):
+    """The oracle as it stands, on the host: a slice of the first sample_sets
+    sets (same generator and parameters) and a few queries.  Per query the
+    filter steps are timed on the slice and scaled to the full set count;
+    the exact re-rank is timed on the slice's F2 and scaled to T sets."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import filter as flt
+    from oracle import flyhash, hausdorff, prng, search
+
+    n_s = min(sample_sets, len(offsets) - 1)
+    X = db_cpu[: offsets[n_s]].astype(np.float64)
+    off = offsets[: n_s + 1]
+    idx = prng.projection_rows(cfg["seed"], cfg["dim"], cfg["code_bits"], cfg["fan_in"])
+    t0 = time.perf_counter()
+    ix = search.build_index(X, off, idx, cfg["wta_k"])
+    build_s = time.perf_counter() - t0
+    per_q = []
+    for i in range(sample_queries):
+        Q = q_cpu[q_off[i]:q_off[i + 1]].astype(np.float64)
+        t0 = time.perf_counter()
+        HQ = flyhash.codes(Q, idx, cfg["wta_k"])
+        C_Q, S_Q = flt.query_sketches(HQ)
+        P = flt.top_positions(C_Q, cfg["A"])
+        t1 = time.perf_counter()
+        member = flt.first_filter(ix.C, P, cfg["M"])
+        scores = flt.hamming(S_Q, ix.B)
+        f2, _ = flt.second_filter(member, scores, cfg["top_t"])
+        t2 = time.perf_counter()
+        h2 = np.array([hausdorff.hausdorff_sq(Q, ix.members(j)) for j in f2])
+        search.rank_by_distance(f2, h2, cfg["k"])
+        t3 = time.perf_counter()
+        scale_filter = n_sets_full / n_s
+        scale_rerank = cfg["top_t"] / max(1, len(f2))
+        per_q.append((t1 - t0) + (t2 - t1) * scale_filter + (t3 - t2) * scale_rerank)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {
+        "value": 1.0 / (sum(per_q) / len(per_q)),
+        "unit": "queries/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle search of {sample_queries} queries against the first {n_s} sets of the workload "
+                   f"(index of the slice built untimed in {build_s:.1f} s); filter steps scaled by "
+                   f"{n_sets_full}/{n_s}, re-rank scaled to T={cfg['top_t']} candidates; BLAS stages use "
+                   f"{threads} threads, the rest of numpy one"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build's path runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not an implementation).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2412_03301_amd import bvs, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bvs.lib()
+
+    w = dict(synth.WORKLOADS[args.workload])
+    if args.n_sets:
+        w["n_sets"] = args.n_sets
+    if args.queries:
+        w["n_queries"] = args.queries
+    if args.top_t:
+        w["top_t"] = args.top_t
+    cfg = dict(seed=0, dim=w["dim"], code_bits=w["code_bits"], fan_in=w["fan_in"], wta_k=w["wta_k"], A=3, M=1,
+               top_t=w["top_t"], k=w["k"])
+
+    log(f"generating {w['n_sets']} sets (d={w['dim']}) on the GPU")
+    t0 = time.perf_counter()
+    db = synth.make_database(w["n_sets"], w["size_lo"], w["size_hi"], w["dim"], w["n_topics"], seed=0, device=dev)
+    q, q_off, _ = synth.make_subset_queries(db, w["n_queries"], seed=1)
+    q = q.contiguous()
+    torch.cuda.synchronize()
+    n_vec = int(db.offsets[-1])
+    log(f"generated {n_vec} vectors in {time.perf_counter() - t0:.1f} s; {w['n_queries']} queries "
+        f"({int(q_off[-1])} vectors)")
+    cpu_db = None
+    if not args.no_cpu_baseline:
+        n_s = min(args.cpu_sample_sets, w["n_sets"])
+        cpu_db = db.vectors[: int(db.offsets[n_s])].cpu().numpy()
+
+    p = bvs.Params.make(dim=w["dim"], code_bits=w["code_bits"], fan_in=w["fan_in"], wta_k=w["wta_k"],
+                        access_lists=3, min_count=1, top_t=w["top_t"], seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = bvs.Index(p, db.vectors, db.offsets)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log(f"index built in {build_s:.2f} s ({ix.mem.numel() / 2**30:.1f} GiB)")
+    db.vectors = None
+    torch.cuda.empty_cache()
+
+    n_q = w["n_queries"]
+    k = w["k"]
+    NQ = int(q_off[-1])
+    ws = ix.search_workspace(n_q, NQ)
+    out = (torch.empty(n_q, k, dtype=torch.int32, device=dev), torch.empty(n_q, k, dtype=torch.float32, device=dev),
+           torch.empty(n_q, dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        ix.search(q, q_off, k, ws=ws, out=out)
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    bvs.profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        ix.search(q, q_off, k, ws=ws, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t_wall
+    gpu_ms = ev0.elapsed_time(ev1)
+    stages = bvs.profile_read()
+    bvs.profile_enable(False)
+    log(f"timed {args.steps} steps: {gpu_ms:.2f} ms (wall {wall_s * 1e3:.2f} ms)")
+    elapsed_s = max(wall_s, gpu_ms / 1e3)
+    qps = n_q * args.steps / elapsed_s
+    ids = out[0].cpu().numpy().view(np.uint32)
+
+    # Candidate sizes for the re-rank's algorithmic bytes (outside the timed region).
+    f2_ids, _, f2_cnt = ix.candidates(q, q_off)
+    f2_ids = f2_ids.cpu().numpy().view(np.uint32)
+    f2_cnt = f2_cnt.cpu().numpy()
+    sizes = np.diff(db.offsets)
+    rerank_vecs = int(sum(sizes[f2_ids[i, :f2_cnt[i]]].sum() for i in range(n_q)))
+    rerank_bytes = rerank_vecs * (ix.dim_padded * 2 + 4)
+    f1_note = float(f2_cnt.mean())
+
+    recall = None
+    brute_qps = None
+    if not args.no_brute:
+        nb = min(args.brute_queries, n_q)
+        qb = q[: int(q_off[nb])].contiguous()
+        ob = q_off[: nb + 1]
+        bws = ix.brute_workspace(nb, int(ob[-1]))
+        ix.bruteforce(q[: int(q_off[2])].contiguous(), q_off[:3], k)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bids, _, _ = ix.bruteforce(qb, ob, k, ws=bws)
+        torch.cuda.synchronize()
+        bt = time.perf_counter() - t0
+        brute_qps = nb / bt
+        bids = bids.cpu().numpy().view(np.uint32)
+        recall = float(np.mean([len(set(ids[i].tolist()) & set(bids[i].tolist())) / k for i in range(nb)]))
+        log(f"brute force on {nb} queries: {bt:.2f} s ({brute_qps:.1f} q/s); recall@10 {recall:.4f}")
+
+    per_step = {name: ms / max(1, calls) for name, (ms, calls) in stages.items() if calls}
+    dominant = max(per_step, key=per_step.get)
+    csrc = os.path.join(ROOT, "paper_2412_03301_amd", "csrc")
+    ld = ix.ld
+    L = w["code_bits"]
+    if dominant == "filter":
+        ops = n_q * ld * (L // 32) * 2           # xor + popcount per 32-bit word per (set, query)
+        ach = ops / (per_step["filter"] / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_TOPS, "unit": "Tops/s", "frac": ach / ALU_PEAK_TOPS,
+                "kernel": "k_filter", "algorithmic": f"{ops:.3e} int32 lane-ops per launch",
+                "traffic": traffic_from_profiles(os.path.join(csrc, "k_filter.hip"), "k_filter")}
+    else:
+        name = dominant
+        byts = rerank_bytes if name == "rerank" else None
+        if byts is None:
+            roof = {"bound": "unknown", "kernel": name}
+        else:
+            ach = byts / (per_step[name] / 1e3) / 1e9
+            roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                    "kernel": "k_haus_cand", "algorithmic": f"{byts} bytes per launch",
+                    "traffic": traffic_from_profiles(os.path.join(csrc, "k_haus.hip"), "k_haus_cand")}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        qc = q[: int(q_off[args.cpu_sample_queries])].cpu().numpy()
+        cpu = cpu_baseline(cpu_db, db.offsets, qc, q_off, cfg, w["n_sets"], args.cpu_sample_sets,
+                           args.cpu_sample_queries)
+
+    if args.copy_probe_mb:
+        a = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    res = {
+        "metric": METRIC,
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={w['dim']}, "
+                         f"{w['n_topics']} topics; FlyHash L={L}, s={w['fan_in']}, wta_k={w['wta_k']}; "
+                         f"A=3, M=1, T={w['top_t']}; {n_q} subset queries per step; top-{k}"),
+            "n_sets": w["n_sets"], "n_vectors": n_vec, "n_queries": n_q, "query_vectors": NQ,
+        },
+        "recall_at_10": recall,
+        "recall_sample_queries": None if args.no_brute else min(args.brute_queries, n_q),
+        "bruteforce_qps": brute_qps,
+        "speedup_vs_bruteforce": (qps / brute_qps) if brute_qps else None,
+        "stages_ms_per_step": per_step,
+        "mean_f2_size": f1_note,
+        "index_build_s": build_s,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

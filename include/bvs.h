@@ -212,6 +212,22 @@ bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q,
                              void* d_workspace, uint64_t workspace_bytes,
                              uint32_t* d_h2, void* stream);
 
+/* Stage timing.  When enabled, the library records a pair of HIP events on
+ * the call's stream around every stage it launches and, after the call's
+ * final synchronisation, adds the elapsed time to a process-wide table.
+ * Stages: 0 convert, 1 encode (query vectors), 2 query sketch, 3 filter
+ * (second-layer scores), 4 select (top-T), 5 re-rank (exact Hausdorff of
+ * the candidates), 6 top-k, 7 brute force (Hausdorff to every set).
+ * bvs_profile_enable resets the table. */
+#define BVS_N_STAGES 8
+typedef struct bvs_stage_times {
+  double ms[BVS_N_STAGES];
+  uint64_t calls[BVS_N_STAGES];
+} bvs_stage_times;
+bvs_status bvs_profile_enable(int on);
+bvs_status bvs_profile_read(bvs_stage_times* out);
+const char* bvs_stage_name(int stage);
+
 /* Thread-local message describing the last non-OK status ("" if none). */
 const char* bvs_last_error(void);
 

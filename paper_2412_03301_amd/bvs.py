@@ -26,8 +26,9 @@ EXPORTED = [
     "bvs_index_get_params", "bvs_sketch_views", "bvs_encode_workspace_bytes", "bvs_encode",
     "bvs_search_workspace_bytes", "bvs_query_sketch", "bvs_search_candidates", "bvs_search",
     "bvs_bruteforce_workspace_bytes", "bvs_bruteforce", "bvs_hausdorff_all", "bvs_last_error",
-    "bvs_version",
+    "bvs_version", "bvs_profile_enable", "bvs_profile_read", "bvs_stage_name",
 ]
+N_STAGES = 8
 
 
 class Params(C.Structure):
@@ -44,6 +45,10 @@ class Params(C.Structure):
 class IndexInfo(C.Structure):
     _fields_ = [("n_sets", C.c_uint64), ("n_vectors", C.c_uint64), ("ld_sets", C.c_uint64),
                 ("dim_padded", C.c_uint32), ("max_set_size", C.c_uint32)]
+
+
+class StageTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * N_STAGES), ("calls", C.c_uint64 * N_STAGES)]
 
 
 class BvsError(RuntimeError):
@@ -88,6 +93,9 @@ def lib():
             "bvs_hausdorff_all": (C.c_int, [P, P, P, U32, P, U64, P, P]),
             "bvs_last_error": (C.c_char_p, []),
             "bvs_version": (C.c_char_p, []),
+            "bvs_profile_enable": (C.c_int, [C.c_int]),
+            "bvs_profile_read": (C.c_int, [P]),
+            "bvs_stage_name": (C.c_char_p, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -126,6 +134,18 @@ def projection(params: Params) -> np.ndarray:
     out = np.zeros((L, s), np.uint16)
     check(lib().bvs_projection(C.byref(params), out.ctypes.data_as(C.c_void_p)))
     return out
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (and reset) or stop per-stage HIP-event timing inside the library."""
+    check(lib().bvs_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{stage name: (total ms, calls)} accumulated since profile_enable."""
+    t = StageTimes()
+    check(lib().bvs_profile_read(C.byref(t)))
+    return {lib().bvs_stage_name(i).decode(): (float(t.ms[i]), int(t.calls[i])) for i in range(N_STAGES)}
 
 
 def params_check(params: Params) -> None:

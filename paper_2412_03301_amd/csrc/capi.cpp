@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -160,6 +161,89 @@ bvs_status read_status(uint32_t* d_status, hipStream_t st, const char* what) {
   return BVS_OK;
 }
 
+// ------------------------------------------------------------------ stage timing
+const char* const kStageNames[BVS_N_STAGES] = {"convert", "encode", "query_sketch", "filter",
+                                               "select",  "rerank", "topk",         "bruteforce"};
+
+struct ProfTable {
+  std::mutex mu;
+  bool on = false;
+  double ms[BVS_N_STAGES] = {};
+  uint64_t calls[BVS_N_STAGES] = {};
+  std::vector<hipEvent_t> pool;
+};
+ProfTable g_prof;
+
+// Events recorded around the stages of one call, on the call's stream.
+struct CallProf {
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  hipStream_t st;
+  bool on;
+  explicit CallProf(hipStream_t s) : st(s) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    on = g_prof.on;
+  }
+  hipEvent_t take() {
+    {
+      std::lock_guard<std::mutex> g(g_prof.mu);
+      if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+      }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void begin(int stage) {
+    if (!on) return;
+    Rec r{stage, take(), take()};
+    if (r.a) hipEventRecord(r.a, st);
+    recs.push_back(r);
+  }
+  void end() {
+    if (on && !recs.empty() && recs.back().b) hipEventRecord(recs.back().b, st);
+  }
+  void release() {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    for (auto& r : recs) {
+      if (r.a) g_prof.pool.push_back(r.a);
+      if (r.b) g_prof.pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+  // Call after the stream has been synchronised.
+  void finish() {
+    if (!on) return;
+    std::vector<std::pair<int, float>> t;
+    for (auto& r : recs) {
+      float ms = 0.f;
+      if (r.a && r.b && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) t.emplace_back(r.stage, ms);
+    }
+    {
+      std::lock_guard<std::mutex> g(g_prof.mu);
+      for (auto& x : t) {
+        g_prof.ms[x.first] += x.second;
+        g_prof.calls[x.first] += 1;
+      }
+    }
+    release();
+  }
+  ~CallProf() { release(); }
+};
+
+template <class F>
+hipError_t staged(CallProf& p, int stage, F&& f) {
+  p.begin(stage);
+  const hipError_t e = f();
+  p.end();
+  return e;
+}
+
+enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE };
+
 }  // namespace
 
 struct bvs_index {
@@ -282,22 +366,38 @@ bvs_status check_queries(const bvs_index* ix, const float* d_q, const uint64_t* 
 
 // Upload offsets and convert the query vectors (status cleared first).
 bvs_status prepare_queries(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
-                           const QueryWs& w, hipStream_t st) {
+                           const QueryWs& w, hipStream_t st, CallProf& prof) {
   const uint64_t NQ = h_q_off[n_q];
   HIP_TRY(launch_fill_u32(w.status, 4, 0, st));
   HIP_TRY(hipMemcpyAsync(w.qoff, h_q_off, (n_q + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_convert(d_q, NQ, ix->g.d, ix->g.dp, w.qhi, w.qlo, w.qnorm, w.status, ix->n_cu, st));
+  HIP_TRY(staged(prof, S_CONVERT, [&] {
+    return launch_convert(d_q, NQ, ix->g.d, ix->g.dp, w.qhi, w.qlo, w.qnorm, w.status, ix->n_cu, st);
+  }));
   return BVS_OK;
 }
 
-bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const QueryWs& w, hipStream_t st) {
+bvs_status query_side(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const QueryWs& w, hipStream_t st,
+                      CallProf& prof) {
   const Geometry& g = ix->g;
   const HashGeom hg = hash_geom(ix);
-  HIP_TRY(launch_encode_vectors(hg, w.qhi, w.qlo, NQ, w.codes, ix->n_cu, st));
-  HIP_TRY(launch_query_sketch(w.codes, w.qoff, n_q, g.L, g.R, g.A, w.cq, w.sq, w.pos, w.gate, w.gate_chunks, st));
-  HIP_TRY(launch_filter(ix->bits, ix->cnt, ix->ld, ix->n, g.L, w.sq, w.gate, w.gate_chunks, w.pos, g.A, g.M, n_q,
-                        w.scores, st));
-  HIP_TRY(launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, w.f2_ids, w.f2_scores, w.f2_count, st));
+  HIP_TRY(staged(prof, S_ENCODE, [&] { return launch_encode_vectors(hg, w.qhi, w.qlo, NQ, w.codes, ix->n_cu, st); }));
+  HIP_TRY(staged(prof, S_QSKETCH, [&] {
+    return launch_query_sketch(w.codes, w.qoff, n_q, g.L, g.R, g.A, w.cq, w.sq, w.pos, w.gate, w.gate_chunks, st);
+  }));
+  return BVS_OK;
+}
+
+bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const QueryWs& w, uint32_t* f2_ids,
+                       uint16_t* f2_scores, uint32_t* f2_count, hipStream_t st, CallProf& prof) {
+  const Geometry& g = ix->g;
+  BVS_TRY(query_side(ix, n_q, NQ, w, st, prof));
+  HIP_TRY(staged(prof, S_FILTER, [&] {
+    return launch_filter(ix->bits, ix->cnt, ix->ld, ix->n, g.L, w.sq, w.gate, w.gate_chunks, w.pos, g.A, g.M, n_q,
+                         w.scores, st);
+  }));
+  HIP_TRY(staged(prof, S_SELECT, [&] {
+    return launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, f2_ids, f2_scores, f2_count, st);
+  }));
   return BVS_OK;
 }
 
@@ -337,6 +437,30 @@ extern "C" {
 
 const char* bvs_last_error(void) { return g_err.c_str(); }
 const char* bvs_version(void) { return "bvs 0.1 (gfx950)"; }
+
+bvs_status bvs_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  g_prof.on = on != 0;
+  for (int i = 0; i < BVS_N_STAGES; ++i) {
+    g_prof.ms[i] = 0;
+    g_prof.calls[i] = 0;
+  }
+  return BVS_OK;
+}
+
+bvs_status bvs_profile_read(bvs_stage_times* out) {
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  for (int i = 0; i < BVS_N_STAGES; ++i) {
+    out->ms[i] = g_prof.ms[i];
+    out->calls[i] = g_prof.calls[i];
+  }
+  return BVS_OK;
+}
+
+const char* bvs_stage_name(int stage) {
+  return (stage >= 0 && stage < BVS_N_STAGES) ? kStageNames[stage] : "";
+}
 
 void bvs_params_default(bvs_params* p) {
   if (!p) return;
@@ -535,14 +659,16 @@ bvs_status bvs_query_sketch(const bvs_index* ix, const float* d_q, const uint64_
   Carver c(d_ws);
   QueryWs w;
   layout_search(c, ix, n_q, NQ, &w);
-  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
   const Geometry& g = ix->g;
-  HIP_TRY(launch_encode_vectors(hash_geom(ix), w.qhi, w.qlo, NQ, w.codes, ix->n_cu, st));
-  HIP_TRY(launch_query_sketch(w.codes, w.qoff, n_q, g.L, g.R, g.A, w.cq, w.sq, w.pos, w.gate, w.gate_chunks, st));
+  BVS_TRY(query_side(ix, n_q, NQ, w, st, prof));
   if (d_cq) HIP_TRY(hipMemcpyAsync(d_cq, w.cq, (uint64_t)n_q * g.L * 2, hipMemcpyDeviceToDevice, st));
   if (d_sq) HIP_TRY(hipMemcpyAsync(d_sq, w.sq, (uint64_t)n_q * g.R * 8, hipMemcpyDeviceToDevice, st));
   if (d_pos) HIP_TRY(hipMemcpyAsync(d_pos, w.pos, (uint64_t)n_q * g.A * 4, hipMemcpyDeviceToDevice, st));
-  return read_status(w.status, st, "queries");
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish();
+  return s;
 }
 
 bvs_status bvs_search_candidates(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
@@ -559,15 +685,12 @@ bvs_status bvs_search_candidates(const bvs_index* ix, const float* d_q, const ui
   Carver c(d_ws);
   QueryWs w;
   layout_search(c, ix, n_q, NQ, &w);
-  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
-  const Geometry& g = ix->g;
-  const HashGeom hg = hash_geom(ix);
-  HIP_TRY(launch_encode_vectors(hg, w.qhi, w.qlo, NQ, w.codes, ix->n_cu, st));
-  HIP_TRY(launch_query_sketch(w.codes, w.qoff, n_q, g.L, g.R, g.A, w.cq, w.sq, w.pos, w.gate, w.gate_chunks, st));
-  HIP_TRY(launch_filter(ix->bits, ix->cnt, ix->ld, ix->n, g.L, w.sq, w.gate, w.gate_chunks, w.pos, g.A, g.M, n_q,
-                        w.scores, st));
-  HIP_TRY(launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, d_ids, d_scores, d_count, st));
-  return read_status(w.status, st, "queries");
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
+  BVS_TRY(run_filters(ix, n_q, NQ, w, d_ids, d_scores, d_count, st, prof));
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish();
+  return s;
 }
 
 bvs_status bvs_search(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
@@ -585,11 +708,18 @@ bvs_status bvs_search(const bvs_index* ix, const float* d_q, const uint64_t* h_q
   Carver c(d_ws);
   QueryWs w;
   layout_search(c, ix, n_q, NQ, &w);
-  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
-  BVS_TRY(run_filters(ix, n_q, NQ, w, st));
-  HIP_TRY(launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, w.h2, st));
-  HIP_TRY(launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st));
-  return read_status(w.status, st, "queries");
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
+  BVS_TRY(run_filters(ix, n_q, NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof));
+  HIP_TRY(staged(prof, S_RERANK, [&] {
+    return launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, w.h2, st);
+  }));
+  HIP_TRY(staged(prof, S_TOPK, [&] {
+    return launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
+  }));
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish();
+  return s;
 }
 
 bvs_status bvs_bruteforce(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
@@ -607,10 +737,15 @@ bvs_status bvs_bruteforce(const bvs_index* ix, const float* d_q, const uint64_t*
   Carver c(d_ws);
   QueryWs w;
   layout_brute(c, ix, n_q, NQ, &w);
-  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
-  HIP_TRY(launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), w.h2, st));
-  HIP_TRY(launch_topk(w.h2, nullptr, nullptr, ix->n, ix->n, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st));
-  return read_status(w.status, st, "queries");
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
+  HIP_TRY(staged(prof, S_BRUTE, [&] { return launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), w.h2, st); }));
+  HIP_TRY(staged(prof, S_TOPK, [&] {
+    return launch_topk(w.h2, nullptr, nullptr, ix->n, ix->n, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
+  }));
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish();
+  return s;
 }
 
 bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
@@ -626,9 +761,12 @@ bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q, const uint64
   Carver c(d_ws);
   QueryWs w;
   layout_brute(c, ix, n_q, NQ, &w);
-  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st));
-  HIP_TRY(launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), d_h2, st));
-  return read_status(w.status, st, "queries");
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
+  HIP_TRY(staged(prof, S_BRUTE, [&] { return launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), d_h2, st); }));
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish();
+  return s;
 }
 
 }  // extern "C"
