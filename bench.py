@@ -221,6 +221,13 @@ def main():
     rerank_bytes = rerank_vecs * (ix.dim_padded * 2 + 4)
     f1_note = float(f2_cnt.mean())
 
+    # First-layer selectivity on a few queries (diagnostic, outside the timed region).
+    cnt_view, _ = ix.sketch_views()
+    _, _, pos = ix.query_sketch(q[: int(q_off[16])].contiguous(), q_off[:17])
+    f1_frac = float(np.mean([((cnt_view[pos[i].long()] > 0).any(0)[: w["n_sets"]]).float().mean().item()
+                             for i in range(16)]))
+    log(f"mean first-layer fraction {f1_frac:.4f}")
+
     recall = None
     brute_qps = None
     if not args.no_brute:
@@ -299,6 +306,7 @@ def main():
         "speedup_vs_bruteforce": (qps / brute_qps) if brute_qps else None,
         "stages_ms_per_step": per_step,
         "mean_f2_size": f1_note,
+        "mean_f1_fraction": f1_frac,
         "index_build_s": build_s,
         "roofline": roof,
         "cpu_baseline": cpu,

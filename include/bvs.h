@@ -216,10 +216,13 @@ bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q,
  * the call's stream around every stage it launches and, after the call's
  * final synchronisation, adds the elapsed time to a process-wide table.
  * Stages: 0 convert, 1 encode (query vectors), 2 query sketch, 3 filter
- * (second-layer scores), 4 select (top-T), 5 re-rank (exact Hausdorff of
- * the candidates), 6 top-k, 7 brute force (Hausdorff to every set).
+ * (sampled cutoff and second-layer scores), 4 select (top-T of the
+ * appended candidates), 5 re-rank (exact Hausdorff of the candidates),
+ * 6 top-k, 7 brute force (Hausdorff to every set), 8 fallback (dense scores
+ * and histogram selection, used when the sampled cutoff did not hold T
+ * candidates or overflowed its buffer).
  * bvs_profile_enable resets the table. */
-#define BVS_N_STAGES 8
+#define BVS_N_STAGES 9
 typedef struct bvs_stage_times {
   double ms[BVS_N_STAGES];
   uint64_t calls[BVS_N_STAGES];

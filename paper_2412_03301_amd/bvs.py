@@ -28,7 +28,7 @@ EXPORTED = [
     "bvs_bruteforce_workspace_bytes", "bvs_bruteforce", "bvs_hausdorff_all", "bvs_last_error",
     "bvs_version", "bvs_profile_enable", "bvs_profile_read", "bvs_stage_name",
 ]
-N_STAGES = 8
+N_STAGES = 9
 
 
 class Params(C.Structure):

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -162,8 +163,8 @@ bvs_status read_status(uint32_t* d_status, hipStream_t st, const char* what) {
 }
 
 // ------------------------------------------------------------------ stage timing
-const char* const kStageNames[BVS_N_STAGES] = {"convert", "encode", "query_sketch", "filter",
-                                               "select",  "rerank", "topk",         "bruteforce"};
+const char* const kStageNames[BVS_N_STAGES] = {"convert", "encode", "query_sketch", "filter", "select",
+                                               "rerank",  "topk",   "bruteforce",   "fallback"};
 
 struct ProfTable {
   std::mutex mu;
@@ -200,11 +201,11 @@ struct CallProf {
   void begin(int stage) {
     if (!on) return;
     Rec r{stage, take(), take()};
-    if (r.a) hipEventRecord(r.a, st);
+    if (r.a) (void)hipEventRecord(r.a, st);
     recs.push_back(r);
   }
   void end() {
-    if (on && !recs.empty() && recs.back().b) hipEventRecord(recs.back().b, st);
+    if (on && !recs.empty() && recs.back().b) (void)hipEventRecord(recs.back().b, st);
   }
   void release() {
     std::lock_guard<std::mutex> g(g_prof.mu);
@@ -242,7 +243,7 @@ hipError_t staged(CallProf& p, int stage, F&& f) {
   return e;
 }
 
-enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE };
+enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE, S_FALLBACK };
 
 }  // namespace
 
@@ -259,6 +260,7 @@ struct bvs_index {
   uint32_t* norms;
   uint8_t* cnt;
   uint64_t* bits;
+  uint64_t* planes;   // [L][ld/64]: bit j of plane p set when C^(j)[p] >= 1
 };
 
 namespace {
@@ -272,6 +274,7 @@ void layout_index(Carver& c, const Geometry& g, uint64_t n, uint64_t N, bvs_inde
   ix->norms = c.take<uint32_t>(N);
   ix->cnt = c.take<uint8_t>((uint64_t)g.L * ld);
   ix->bits = c.take<uint64_t>((uint64_t)g.R * ld);
+  ix->planes = c.take<uint64_t>((uint64_t)g.L * (ld / 64));
   ix->ld = ld;
 }
 
@@ -305,6 +308,12 @@ struct QueryWs {
   uint64_t* gate_chunks;
   uint16_t* scores;
   SelectBufs sel;
+  uint16_t* sample;       // [n_q][kSampleBlocks * 256]
+  uint32_t* cutoff;       // [n_q]
+  uint32_t* cand_count;   // [n_q]
+  uint64_t* cand_app;     // [n_q][cap]
+  uint32_t cap;
+  uint64_t* f1;           // [n_q][ld/64] first-layer bitmaps
   uint32_t* f2_ids;
   uint16_t* f2_scores;
   uint32_t* f2_count;
@@ -313,6 +322,35 @@ struct QueryWs {
 };
 
 constexpr uint32_t kMaxK = 64;
+constexpr uint32_t kSampleBlocks = 64;   // blocks of 256 sets scored to pick the cutoff
+constexpr uint32_t kCutoffAlpha = 3;     // the cutoff aims at about 3 T appended sets
+
+// Capacity of the append buffer per query: 8 T rounded up to a power of two,
+// within 4096..16384 (it is sorted in LDS).  BVS_APPEND_CAP overrides it
+// (tests use a tiny value to exercise the dense fallback).
+uint32_t append_capacity(uint32_t T) {
+  uint32_t c = 4096;
+  while (c < 8 * T && c < 16384) c <<= 1;
+  if (const char* e = std::getenv("BVS_APPEND_CAP")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1 && v <= 16384) c = (uint32_t)v;
+  }
+  return c;
+}
+
+// Member-only scoring unless BVS_FILTER=dense, or M = 0 (every set is a
+// member, so the dense kernel does the same work with fewer steps).
+bool use_sparse_filter(uint32_t M) {
+  const char* e = std::getenv("BVS_FILTER");
+  if (e && std::strcmp(e, "dense") == 0) return false;
+  if (e && std::strcmp(e, "sparse") == 0) return true;
+  return M >= 1;
+}
+
+bool force_dense_select() {
+  const char* e = std::getenv("BVS_SELECT");
+  return e && std::strcmp(e, "dense") == 0;
+}
 
 void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, QueryWs* w) {
   const Geometry& g = ix->g;
@@ -333,6 +371,12 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->sel.ctr = c.take<uint32_t>(n_q);
   w->sel.eqcnt = c.take<uint32_t>((uint64_t)n_q * select_blocks(ix->ld));
   w->sel.cand = c.take<uint64_t>((uint64_t)n_q * g.T);
+  w->cap = append_capacity(g.T);
+  w->sample = c.take<uint16_t>((uint64_t)n_q * kSampleBlocks * 256);
+  w->cutoff = c.take<uint32_t>(n_q);
+  w->cand_count = c.take<uint32_t>(n_q);
+  w->cand_app = c.take<uint64_t>((uint64_t)n_q * w->cap);
+  w->f1 = c.take<uint64_t>((uint64_t)n_q * (ix->ld / 64));
   w->f2_ids = c.take<uint32_t>((uint64_t)n_q * g.T);
   w->f2_scores = c.take<uint16_t>((uint64_t)n_q * g.T);
   w->f2_count = c.take<uint32_t>(n_q);
@@ -387,15 +431,86 @@ bvs_status query_side(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Quer
   return BVS_OK;
 }
 
+FilterArgs filter_args(const bvs_index* ix, uint32_t n_q, const QueryWs& w) {
+  const Geometry& g = ix->g;
+  FilterArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.bits = (const uint4*)ix->bits;
+  a.cnt = ix->cnt;
+  a.ld = ix->ld;
+  a.n_sets = ix->n;
+  a.RC = g.L / 128;
+  a.sq = (const uint4*)w.sq;
+  a.gate = (const uint4*)w.gate;
+  a.gate_chunks = w.gate_chunks;
+  a.pos = w.pos;
+  a.A = g.A;
+  a.M = g.M;
+  a.n_q = n_q;
+  a.scores = w.scores;
+  a.cutoff = w.cutoff;
+  a.cand = w.cand_app;
+  a.cap = w.cap;
+  a.cand_count = w.cand_count;
+  a.planes = ix->planes;
+  a.f1 = w.f1;
+  return a;
+}
+
+// Both filter layers: F2 of every query into f2_ids / f2_scores / f2_count.
 bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const QueryWs& w, uint32_t* f2_ids,
                        uint16_t* f2_scores, uint32_t* f2_count, hipStream_t st, CallProf& prof) {
   const Geometry& g = ix->g;
   BVS_TRY(query_side(ix, n_q, NQ, w, st, prof));
-  HIP_TRY(staged(prof, S_FILTER, [&] {
-    return launch_filter(ix->bits, ix->cnt, ix->ld, ix->n, g.L, w.sq, w.gate, w.gate_chunks, w.pos, g.A, g.M, n_q,
-                         w.scores, st);
-  }));
-  HIP_TRY(staged(prof, S_SELECT, [&] {
+  FilterArgs a = filter_args(ix, n_q, w);
+  if (!force_dense_select()) {
+    const uint32_t n_blocks = (uint32_t)(ix->ld / 256);
+    const bool sparse = use_sparse_filter(g.M);
+    uint32_t* d_fail = w.status + 1;
+    HIP_TRY(launch_fill_u32(w.cand_count, n_q, 0, st));
+    HIP_TRY(launch_fill_u32(d_fail, 1, 0, st));
+    HIP_TRY(staged(prof, S_FILTER, [&]() -> hipError_t {
+      hipError_t e;
+      if (sparse && g.M == 1) {
+        e = launch_f1_bitmap(a, st);
+        if (e != hipSuccess) return e;
+      }
+      if (ix->n <= w.cap) {
+        // every member fits the buffer: admit them all
+        e = launch_fill_u32(w.cutoff, n_q, 0xFFFFFFFFu, st);
+      } else {
+        const uint32_t nsb = std::min(kSampleBlocks, n_blocks);
+        FilterArgs as = a;
+        as.scores = w.sample;
+        if (sparse) {
+          e = launch_fill_u32((uint32_t*)w.sample, (uint64_t)n_q * nsb * 128, 0xFFFFFFFFu, st);
+          if (e != hipSuccess) return e;
+          e = launch_filter_sparse_sample(as, nsb, st);
+        } else {
+          e = launch_filter_sample(as, nsb, st);
+        }
+        if (e != hipSuccess) return e;
+        const uint64_t S = (uint64_t)nsb * 256;
+        const uint64_t sampled = std::min<uint64_t>(S, ix->n);
+        const uint32_t r = (uint32_t)std::max<uint64_t>(
+            1, (kCutoffAlpha * (uint64_t)g.T * sampled + ix->n - 1) / ix->n);
+        e = launch_cutoff(w.sample, (uint32_t)S, g.L, r, n_q, w.cutoff, st);
+      }
+      if (e != hipSuccess) return e;
+      return sparse ? launch_filter_sparse_append(a, st) : launch_filter_append(a, st);
+    }));
+    HIP_TRY(staged(prof, S_SELECT, [&] {
+      return launch_sort_append(w.cand_app, w.cand_count, w.cutoff, w.cap, g.T, n_q, f2_ids, f2_scores, f2_count,
+                                d_fail, st);
+    }));
+    uint32_t h_fail = 0;
+    HIP_TRY(hipMemcpyAsync(&h_fail, d_fail, sizeof h_fail, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h_fail == 0) return BVS_OK;
+  }
+  HIP_TRY(staged(prof, S_FALLBACK, [&]() -> hipError_t {
+    hipError_t e = launch_filter_dense(a, st);
+    if (e != hipSuccess) return e;
     return launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, f2_ids, f2_scores, f2_count, st);
   }));
   return BVS_OK;
@@ -561,6 +676,7 @@ bvs_status bvs_build_index(const bvs_params* p, const float* d_vectors, const ui
     HIP_TRY(launch_convert(d_vectors, N, g.d, g.dp, ix->hi, ix->lo, ix->norms, status, ix->n_cu, st));
     HIP_TRY(launch_encode_sets(hash_geom(ix), ix->hi, ix->lo, ix->offsets, n_sets, cnt_rm, bits_rm, ix->n_cu, st));
     HIP_TRY(launch_transpose_sketches(cnt_rm, bits_rm, n_sets, ix->ld, g.L, ix->cnt, ix->bits, st));
+    HIP_TRY(launch_bitmap_planes(ix->cnt, ix->ld, g.L, ix->planes, st));
     return read_status(status, st, "database");
   };
   const bvs_status s = run();

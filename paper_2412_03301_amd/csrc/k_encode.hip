@@ -353,6 +353,35 @@ hipError_t launch_transpose_sketches(const uint8_t* cnt_rm, const uint64_t* bits
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- bitmap planes
+// Position-major membership bitmaps of the first layer with M = 1:
+// bit (j % 64) of word [p][j / 64] is set when C^(j)[p] >= 1, i.e. set j is
+// on the inverted list of position p (Def. 9).  One thread per word.
+__global__ void __launch_bounds__(256)
+k_bitmap_planes(const uint8_t* __restrict__ cnt, uint64_t ld, uint32_t L, uint64_t* __restrict__ planes) {
+  const uint64_t wpp = ld / 64;
+  const uint64_t i = blockIdx.x * 256ull + threadIdx.x;
+  if (i >= (uint64_t)L * wpp) return;
+  const uint64_t p = i / wpp, w = i % wpp;
+  const uint4* src = (const uint4*)(cnt + p * ld + w * 64);
+  uint64_t bits = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint4 v = src[k];
+    const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      if ((d[e / 4] >> (8 * (e % 4))) & 0xFF) bits |= 1ull << (16 * k + e);
+  }
+  planes[i] = bits;
+}
+
+hipError_t launch_bitmap_planes(const uint8_t* cnt, uint64_t ld, uint32_t L, uint64_t* planes, hipStream_t st) {
+  const uint64_t n = (uint64_t)L * (ld / 64);
+  hipLaunchKernelGGL(k_bitmap_planes, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, cnt, ld, L, planes);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- query sketch
 // One wave per query.  Lane l owns code words t = l and l + 64.
 __global__ void __launch_bounds__(64)

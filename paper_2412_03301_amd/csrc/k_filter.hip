@@ -8,44 +8,62 @@
 //            applies the first layer: with M = 1, C[p] >= 1 is the sketch bit p,
 //            tested in the chunk that holds p; with M >= 2 the count columns
 //            C[p][set] are read; M = 0 admits every set.
-// select     the first min(T, |F1|) sets by (score, id), in four passes:
-//            histogram of scores, threshold tau per query, unordered append of
-//            every score < tau plus a count of score == tau per block, then an
-//            ordered fill of the ties (lowest ids first); a final bitonic sort
-//            orders F2 by (score, id).  Every step is deterministic.
+// select     the first min(T, |F1|) sets by (score, id).  Main path: score a
+//            spread sample of 64 blocks of 256 sets, take per query the score
+//            whose sample rank corresponds to about 3 T sets of the whole
+//            database as a cutoff, then score every set once more, appending
+//            only members with score <= cutoff (bounded buffer), and sort the
+//            appended (score, id) keys.  The result is exact whenever the
+//            buffer did not overflow and it holds at least T sets (or the
+//            cutoff admitted every member); otherwise the caller runs the
+//            dense path: every score is written, a histogram gives the
+//            threshold tau, scores < tau are appended unordered, ties at tau
+//            are filled lowest ids first, and a bitonic sort orders F2.
+//            Both paths are deterministic and give identical F2.
 #include "device.h"
 #include "launch.h"
 
 namespace bvs {
 
-template <int QT>
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Scores of one block of 256 sets against QT queries.  Set block b of the
+// grid is blockIdx.x * block_stride.  Dense mode writes every score
+// (0xFFFF = not in F1) to scores[q][blockIdx.x * 256 + t]; append mode keeps
+// only F1 members with score <= cutoff[q], appending (score << 32 | id) to
+// cand[q][0 .. cap) and counting them in cand_count[q] (the count may exceed
+// cap; the entries beyond cap are dropped and the caller detects it).
+template <int QT, bool APPEND>
 __global__ void __launch_bounds__(256)
-k_filter(const uint4* __restrict__ bits, const uint8_t* __restrict__ cnt, uint64_t ld, uint64_t n_sets,
-         uint32_t RC, const uint4* __restrict__ sq, const uint4* __restrict__ gate,
-         const uint64_t* __restrict__ gate_chunks, const uint32_t* __restrict__ pos, uint32_t A, uint32_t M,
-         uint32_t n_q, uint16_t* __restrict__ scores) {
-  const uint64_t j = blockIdx.x * 256ull + threadIdx.x;
+k_filter(FilterArgs a) {
+  const uint64_t j = (uint64_t)blockIdx.x * a.block_stride * 256ull + threadIdx.x;
   const uint32_t q0 = blockIdx.y * QT;
-  const uint32_t nq = min((uint32_t)QT, n_q - q0);
+  const uint32_t nq = min((uint32_t)QT, a.n_q - q0);
+  const uint32_t lane = lane_id();
+  const uint32_t M = a.M;
   uint32_t acc[QT], hit[QT];
   uint64_t gcm[QT];
 #pragma unroll
   for (int i = 0; i < QT; ++i) {
     acc[i] = 0;
     hit[i] = 0;
-    gcm[i] = (M == 1 && (uint32_t)i < nq) ? gate_chunks[q0 + i] : 0;
+    gcm[i] = (M == 1 && (uint32_t)i < nq) ? a.gate_chunks[q0 + i] : 0;
   }
-  const uint4* col = bits + j;
+  const uint4* col = a.bits + j;
+  const uint32_t RC = a.RC;
+  const uint64_t ld = a.ld;
 #pragma unroll 4
   for (uint32_t c = 0; c < RC; ++c) {
     const uint4 x = col[(uint64_t)c * ld];
 #pragma unroll
     for (int i = 0; i < QT; ++i) {
       if ((uint32_t)i < nq) {
-        const uint4 s = sq[(uint64_t)(q0 + i) * RC + c];
+        const uint4 s = a.sq[(uint64_t)(q0 + i) * RC + c];
         acc[i] += popc32(x.x ^ s.x) + popc32(x.y ^ s.y) + popc32(x.z ^ s.z) + popc32(x.w ^ s.w);
         if ((gcm[i] >> c) & 1) {
-          const uint4 g = gate[(uint64_t)(q0 + i) * RC + c];
+          const uint4 g = a.gate[(uint64_t)(q0 + i) * RC + c];
           hit[i] |= (x.x & g.x) | (x.y & g.y) | (x.z & g.z) | (x.w & g.w);
         }
       }
@@ -54,6 +72,7 @@ k_filter(const uint4* __restrict__ bits, const uint8_t* __restrict__ cnt, uint64
 #pragma unroll
   for (int i = 0; i < QT; ++i) {
     if ((uint32_t)i < nq) {
+      const uint32_t q = q0 + i;
       bool member;
       if (M == 0) {
         member = true;
@@ -61,44 +80,224 @@ k_filter(const uint4* __restrict__ bits, const uint8_t* __restrict__ cnt, uint64
         member = hit[i] != 0;
       } else {
         member = false;
-        for (uint32_t a = 0; a < A; ++a) {
-          const uint32_t p = pos[(uint64_t)(q0 + i) * A + a];
-          member |= cnt[(uint64_t)p * ld + j] >= M;
+        for (uint32_t t = 0; t < a.A; ++t) {
+          const uint32_t p = a.pos[(uint64_t)q * a.A + t];
+          member |= a.cnt[(uint64_t)p * ld + j] >= M;
         }
       }
-      scores[(uint64_t)(q0 + i) * ld + j] = (j < n_sets && member) ? (uint16_t)acc[i] : (uint16_t)0xFFFF;
+      member = member && j < a.n_sets;
+      if (!APPEND) {
+        a.scores[(uint64_t)q * a.ld_out + (uint64_t)blockIdx.x * 256 + threadIdx.x] =
+            member ? (uint16_t)acc[i] : (uint16_t)0xFFFF;
+      } else {
+        const bool take = member && acc[i] <= a.cutoff[q];
+        const uint64_t tb = ballot(take);
+        if (tb) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&a.cand_count[q], popc64(tb));
+          base = (uint32_t)__shfl((int)base, 0, BVS_WAVE);
+          const uint32_t slot = base + mbcnt64(tb);
+          if (take && slot < a.cap) a.cand[(uint64_t)q * a.cap + slot] = ((uint64_t)acc[i] << 32) | (uint32_t)j;
+        }
+      }
     }
   }
 }
 
-hipError_t launch_filter(const uint64_t* bits, const uint8_t* cnt, uint64_t ld, uint64_t n_sets, uint32_t L,
-                         const uint64_t* sq, const uint64_t* gate, const uint64_t* gate_chunks,
-                         const uint32_t* pos, uint32_t A, uint32_t M, uint32_t n_q, uint16_t* scores,
-                         hipStream_t st) {
-  if (n_q == 0) return hipSuccess;
-  const uint32_t RC = L / 128;
-  const uint32_t gx = (uint32_t)(ld / 256);
+template <bool APPEND>
+static hipError_t go_filter(const FilterArgs& a, uint32_t n_blocks, hipStream_t st) {
   auto go = [&](auto qt) -> hipError_t {
     constexpr int QT = decltype(qt)::value;
-    dim3 grid(gx, (n_q + QT - 1) / QT);
-    hipLaunchKernelGGL(k_filter<QT>, grid, dim3(256), 0, st, (const uint4*)bits, cnt, ld, n_sets, RC,
-                       (const uint4*)sq, (const uint4*)gate, gate_chunks, pos, A, M, n_q, scores);
+    dim3 grid(n_blocks, (a.n_q + QT - 1) / QT);
+    hipLaunchKernelGGL((k_filter<QT, APPEND>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
   };
-  if (n_q >= 16) return go(std::integral_constant<int, 16>());
-  if (n_q >= 8) return go(std::integral_constant<int, 8>());
-  if (n_q >= 4) return go(std::integral_constant<int, 4>());
+  if (a.n_q >= 16) return go(std::integral_constant<int, 16>());
+  if (a.n_q >= 8) return go(std::integral_constant<int, 8>());
+  if (a.n_q >= 4) return go(std::integral_constant<int, 4>());
   return go(std::integral_constant<int, 1>());
 }
 
+hipError_t launch_filter_dense(FilterArgs a, hipStream_t st) {
+  if (a.n_q == 0) return hipSuccess;
+  a.block_stride = 1;
+  a.ld_out = a.ld;
+  return go_filter<false>(a, (uint32_t)(a.ld / 256), st);
+}
+
+hipError_t launch_filter_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st) {
+  if (a.n_q == 0) return hipSuccess;
+  const uint32_t nb = (uint32_t)(a.ld / 256);
+  a.block_stride = std::max(1u, nb / n_sample_blocks);
+  a.ld_out = (uint64_t)n_sample_blocks * 256;
+  return go_filter<false>(a, n_sample_blocks, st);
+}
+
+hipError_t launch_filter_append(FilterArgs a, hipStream_t st) {
+  if (a.n_q == 0) return hipSuccess;
+  a.block_stride = 1;
+  return go_filter<true>(a, (uint32_t)(a.ld / 256), st);
+}
+
+// ---------------------------------------------------------------- member-only scoring
+// First-layer bitmaps of each query: f1[q][w] = OR over its A positions p of
+// planes[p][w] (M = 1), so that set j is in F1 exactly when bit j is set.
+__global__ void __launch_bounds__(256)
+k_f1_bitmap(const uint64_t* __restrict__ planes, uint64_t wpp, const uint32_t* __restrict__ pos, uint32_t A,
+            uint64_t* __restrict__ f1) {
+  const uint32_t q = blockIdx.y;
+  const uint64_t w = blockIdx.x * 256ull + threadIdx.x;
+  if (w >= wpp) return;
+  uint64_t m = 0;
+  for (uint32_t t = 0; t < A; ++t) m |= planes[(uint64_t)pos[(uint64_t)q * A + t] * wpp + w];
+  f1[(uint64_t)q * wpp + w] = m;
+}
+
+hipError_t launch_f1_bitmap(const FilterArgs& a, hipStream_t st) {
+  const uint64_t wpp = a.ld / 64;
+  hipLaunchKernelGGL(k_f1_bitmap, dim3((uint32_t)((wpp + 255) / 256), a.n_q), dim3(256), 0, st, a.planes, wpp, a.pos,
+                     a.A, a.f1);
+  return hipGetLastError();
+}
+
+// First-layer membership of the 256 sets of a tile for query q, as four
+// 64-bit masks (uniform across the wave).
+__device__ __forceinline__ void tile_members(const FilterArgs& a, uint32_t q, uint64_t tile0, uint32_t lane,
+                                             const uint64_t (&vmask)[4], uint64_t (&m)[4]) {
+  if (a.M == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = vmask[i];
+  } else if (a.M == 1) {
+    const uint64_t* f = a.f1 + (uint64_t)q * (a.ld / 64) + tile0 / 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = f[i] & vmask[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bool mem = false;
+      for (uint32_t t = 0; t < a.A; ++t) {
+        const uint32_t p = a.pos[(uint64_t)q * a.A + t];
+        mem |= a.cnt[(uint64_t)p * a.ld + tile0 + 64u * i + lane] >= a.M;
+      }
+      m[i] = ballot(mem) & vmask[i];
+    }
+  }
+}
+
+// One workgroup (16 waves) per tile of 256 sets; the tile's binary Bloom
+// filters are staged in LDS chunk-major ([chunk][set], 16 B per entry).
+// Each wave takes whole queries: it reads the query's first-layer masks for
+// the tile (prefetched one query ahead), compacts the members into lanes
+// (ascending set order) and computes the Hamming distance only for them,
+// one LDS read and 8 VALU operations per 128-bit chunk and member; the
+// query sketch words are wave-uniform scalar loads.
+template <int RC, bool APPEND>
+__global__ void __launch_bounds__(1024)
+k_filter_sparse(FilterArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  constexpr uint32_t NW = 16;
+  uint4* tile = (uint4*)smem;                         // [RC][256]
+  uint8_t* lists = smem + (size_t)RC * 256 * 16;      // [NW][256]
+  const uint64_t tile0 = (uint64_t)blockIdx.x * a.block_stride * 256ull;
+  for (uint32_t i = threadIdx.x; i < RC * 256; i += blockDim.x) {
+    const uint32_t c = i / 256, s = i % 256;
+    tile[i] = a.bits[(uint64_t)c * a.ld + tile0 + s];
+  }
+  __syncthreads();
+  const uint32_t w = threadIdx.x / BVS_WAVE, lane = lane_id();
+  uint8_t* list = lists + w * 256;
+  uint64_t vmask[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint64_t b = tile0 + 64u * i;
+    vmask[i] = b >= a.n_sets ? 0ull : (a.n_sets - b >= 64 ? ~0ull : (1ull << (a.n_sets - b)) - 1);
+  }
+  uint64_t mn[4];
+  if (w < a.n_q) tile_members(a, w, tile0, lane, vmask, mn);
+  for (uint32_t q = w; q < a.n_q; q += NW) {
+    uint64_t m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = mn[i];
+    if (q + NW < a.n_q) tile_members(a, q + NW, tile0, lane, vmask, mn);
+    const uint32_t nm = popc64(m[0]) + popc64(m[1]) + popc64(m[2]) + popc64(m[3]);
+    if (nm == 0) continue;
+    uint32_t base = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if ((m[i] >> lane) & 1) list[base + mbcnt64(m[i])] = (uint8_t)(64 * i + lane);
+      base += popc64(m[i]);
+    }
+    wave_lds_sync();
+    const uint4* sqq = a.sq + (uint64_t)q * RC;
+    const uint32_t cut = APPEND ? a.cutoff[q] : 0u;
+    for (uint32_t g = 0; g < nm; g += 64) {
+      const uint32_t idx = g + lane;
+      const bool act = idx < nm;
+      const uint32_t sl = act ? list[idx] : 0u;
+      uint32_t acc = 0;
+#pragma unroll 8
+      for (int c = 0; c < RC; ++c) {
+        const uint4 x = tile[c * 256 + sl];
+        const uint4 sv = sqq[c];
+        acc += popc32(x.x ^ sv.x) + popc32(x.y ^ sv.y) + popc32(x.z ^ sv.z) + popc32(x.w ^ sv.w);
+      }
+      if (!APPEND) {
+        if (act) a.scores[(uint64_t)q * a.ld_out + (uint64_t)blockIdx.x * 256 + sl] = (uint16_t)acc;
+      } else {
+        const bool take = act && acc <= cut;
+        const uint64_t tb = ballot(take);
+        if (tb) {
+          uint32_t b0 = 0;
+          if (lane == 0) b0 = atomicAdd(&a.cand_count[q], popc64(tb));
+          b0 = (uint32_t)__shfl((int)b0, 0, BVS_WAVE);
+          const uint32_t slot = b0 + mbcnt64(tb);
+          if (take && slot < a.cap) a.cand[(uint64_t)q * a.cap + slot] = ((uint64_t)acc << 32) | (uint32_t)(tile0 + sl);
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+template <bool APPEND>
+static hipError_t go_sparse(const FilterArgs& a, uint32_t n_blocks, hipStream_t st) {
+  auto go = [&](auto rc) -> hipError_t {
+    constexpr int RC = decltype(rc)::value;
+    const size_t lds = (size_t)RC * 256 * 16 + 16 * 256;
+    hipError_t e = hipFuncSetAttribute((const void*)k_filter_sparse<RC, APPEND>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_filter_sparse<RC, APPEND>), dim3(n_blocks), dim3(1024), lds, st, a);
+    return hipGetLastError();
+  };
+  switch (a.RC) {
+    case 2: return go(std::integral_constant<int, 2>());
+    case 4: return go(std::integral_constant<int, 4>());
+    case 8: return go(std::integral_constant<int, 8>());
+    case 16: return go(std::integral_constant<int, 16>());
+    case 32: return go(std::integral_constant<int, 32>());
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_filter_sparse_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st) {
+  if (a.n_q == 0) return hipSuccess;
+  const uint32_t nb = (uint32_t)(a.ld / 256);
+  a.block_stride = std::max(1u, nb / n_sample_blocks);
+  a.ld_out = (uint64_t)n_sample_blocks * 256;
+  return go_sparse<false>(a, n_sample_blocks, st);
+}
+
+hipError_t launch_filter_sparse_append(FilterArgs a, hipStream_t st) {
+  if (a.n_q == 0) return hipSuccess;
+  a.block_stride = 1;
+  return go_sparse<true>(a, (uint32_t)(a.ld / 256), st);
+}
+
 // ---------------------------------------------------------------- select
-static constexpr uint32_t SEL_CH = 4096;   // sets per block in the select passes
+static constexpr uint32_t SEL_CH = 4096;   // sets per block in the dense select passes
 
 uint32_t select_blocks(uint64_t ld) { return (uint32_t)((ld + SEL_CH - 1) / SEL_CH); }
-
-__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 // Exclusive scan of one flag per thread over a 256-thread block.
 __device__ __forceinline__ uint32_t block_excl_scan_flag(bool f, uint32_t* wsum, uint32_t& total) {
@@ -303,6 +502,102 @@ hipError_t launch_select(const uint16_t* scores, uint64_t ld, uint32_t L, uint32
   if (NP < 2) NP = 2;
   hipLaunchKernelGGL(k_sort_f2, dim3(n_q), dim3(512), NP * sizeof(uint64_t), st, b.cand, b.sel, T, NP, f2_ids,
                      f2_scores, f2_count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- sampled cutoff
+// One block per query: histogram of the sampled scores; the cutoff is the
+// smallest score s with #{sample members with score <= s} >= r, or all ones
+// (admit every member) when the sample holds fewer than r members.
+__global__ void __launch_bounds__(256)
+k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r, uint32_t* __restrict__ cutoff) {
+  extern __shared__ uint32_t h[];
+  __shared__ uint32_t part[256];
+  __shared__ uint32_t total_s;
+  const uint32_t q = blockIdx.x, t = threadIdx.x;
+  const uint32_t nb = L + 1;
+  for (uint32_t i = t; i < nb; i += 256) h[i] = 0;
+  __syncthreads();
+  const uint16_t* sq = sample + (uint64_t)q * S;
+  for (uint32_t i = t; i < S; i += 256) {
+    const uint32_t v = sq[i];
+    if (v != 0xFFFFu) atomicAdd(&h[v], 1u);
+  }
+  __syncthreads();
+  const uint32_t per = (nb + 255) / 256;
+  const uint32_t b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+  uint32_t s = 0;
+  for (uint32_t b = b0; b < b1; ++b) s += h[b];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (uint32_t i = 0; i < 256; ++i) { const uint32_t v = part[i]; part[i] = run; run += v; }
+    total_s = run;
+  }
+  __syncthreads();
+  if (total_s < r) {
+    if (t == 0) cutoff[q] = 0xFFFFFFFFu;
+    return;
+  }
+  const uint32_t pre = part[t];
+  if (pre < r && pre + s >= r) {
+    uint32_t cum = pre;
+    for (uint32_t b = b0; b < b1; ++b) {
+      cum += h[b];
+      if (cum >= r) { cutoff[q] = b; break; }
+    }
+  }
+}
+
+hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_t r, uint32_t n_q,
+                         uint32_t* cutoff, hipStream_t st) {
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cutoff, dim3(n_q), dim3(256), (L + 1) * sizeof(uint32_t), st, sample, S, L, r, cutoff);
+  return hipGetLastError();
+}
+
+// One block per query: sort the appended keys and keep the first T as F2.
+// A query whose buffer overflowed, or that holds fewer than T sets although
+// its cutoff excluded some members, is counted in *fail and left untouched.
+__global__ void __launch_bounds__(1024)
+k_sort_append(const uint64_t* __restrict__ cand, const uint32_t* __restrict__ cand_count,
+              const uint32_t* __restrict__ cutoff, uint32_t cap, uint32_t T, uint32_t* __restrict__ f2_ids,
+              uint16_t* __restrict__ f2_scores, uint32_t* __restrict__ f2_count, uint32_t* __restrict__ fail) {
+  extern __shared__ uint64_t keys[];
+  const uint32_t q = blockIdx.x;
+  const uint32_t n = cand_count[q];
+  const bool ok = n <= cap && (n >= T || cutoff[q] == 0xFFFFFFFFu);
+  if (!ok) {
+    if (threadIdx.x == 0) atomicAdd(fail, 1u);
+    return;
+  }
+  uint32_t NP = 2;
+  while (NP < n) NP <<= 1;
+  for (uint32_t i = threadIdx.x; i < NP; i += blockDim.x) keys[i] = i < n ? cand[(uint64_t)q * cap + i] : ~0ull;
+  __syncthreads();
+  bitonic_sort_lds(keys, NP);
+  const uint32_t Tq = min(T, n);
+  for (uint32_t i = threadIdx.x; i < T; i += blockDim.x) {
+    const bool v = i < Tq;
+    const uint64_t key = v ? keys[i] : ~0ull;
+    f2_ids[(uint64_t)q * T + i] = v ? (uint32_t)key : 0xFFFFFFFFu;
+    if (f2_scores) f2_scores[(uint64_t)q * T + i] = v ? (uint16_t)(key >> 32) : (uint16_t)0xFFFF;
+  }
+  if (threadIdx.x == 0) f2_count[q] = Tq;
+}
+
+hipError_t launch_sort_append(const uint64_t* cand, const uint32_t* cand_count, const uint32_t* cutoff, uint32_t cap,
+                              uint32_t T, uint32_t n_q, uint32_t* f2_ids, uint16_t* f2_scores, uint32_t* f2_count,
+                              uint32_t* fail, hipStream_t st) {
+  if (n_q == 0) return hipSuccess;
+  uint32_t np = 2;
+  while (np < cap) np <<= 1;   // the sort pads n <= cap keys to a power of two
+  const size_t lds = (size_t)np * sizeof(uint64_t);
+  hipError_t e = hipFuncSetAttribute((const void*)k_sort_append, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_append, dim3(n_q), dim3(1024), lds, st, cand, cand_count, cutoff, cap, T, f2_ids, f2_scores,
+                     f2_count, fail);
   return hipGetLastError();
 }
 

@@ -34,6 +34,9 @@ hipError_t launch_transpose_sketches(const uint8_t* cnt_rm, const uint64_t* bits
                                      uint64_t n_sets, uint64_t ld, uint32_t L,
                                      uint8_t* cnt, uint64_t* bits, hipStream_t st);
 
+// Position-major bitmaps of C >= 1 from the count columns: planes [L][ld/64] u64.
+hipError_t launch_bitmap_planes(const uint8_t* cnt, uint64_t ld, uint32_t L, uint64_t* planes, hipStream_t st);
+
 // Query sketches from query codes: C_Q [n_q][L] u16, S_Q [n_q][R] u64,
 // top-A positions [n_q][A] u32, gate masks [n_q][R] u64 (bits of the A
 // positions) and the chunk mask of the gates [n_q] u64.
@@ -42,13 +45,43 @@ hipError_t launch_query_sketch(const uint64_t* codes, const uint64_t* q_off, uin
                                uint16_t* cq, uint64_t* sq, uint32_t* pos,
                                uint64_t* gate, uint64_t* gate_chunks, hipStream_t st);
 
-// Second-layer scores: scores [n_q][ld] u16 (0xFFFF = not in F1).
-hipError_t launch_filter(const uint64_t* bits, const uint8_t* cnt, uint64_t ld, uint64_t n_sets,
-                         uint32_t L, const uint64_t* sq, const uint64_t* gate,
-                         const uint64_t* gate_chunks, const uint32_t* pos, uint32_t A,
-                         uint32_t M, uint32_t n_q, uint16_t* scores, hipStream_t st);
+// Second-layer scoring (Alg. 6, sketch filter).
+struct FilterArgs {
+  const uint4* bits;           // chunk-major binary Bloom filters [L/128][ld]
+  const uint8_t* cnt;          // count Bloom filters [L][ld]
+  uint64_t ld, n_sets;
+  uint32_t RC;                 // L / 128
+  const uint4* sq;             // query sketches [n_q][RC]
+  const uint4* gate;           // gate masks [n_q][RC]
+  const uint64_t* gate_chunks; // [n_q]
+  const uint32_t* pos;         // [n_q][A]
+  uint32_t A, M, n_q;
+  uint32_t block_stride;       // set block of grid block b is b * block_stride
+  uint16_t* scores;            // dense / sample output [n_q][ld_out]
+  uint64_t ld_out;
+  const uint32_t* cutoff;      // append mode: [n_q]
+  uint64_t* cand;              // append mode: [n_q][cap] keys (score << 32 | id)
+  uint32_t cap;
+  uint32_t* cand_count;        // append mode: [n_q]
+  const uint64_t* planes;      // membership bitmaps [L][ld/64] (first layer, M = 1)
+  uint64_t* f1;                // per-query first-layer bitmaps [n_q][ld/64] (M = 1)
+};
+hipError_t launch_filter_dense(FilterArgs a, hipStream_t st);
+hipError_t launch_filter_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st);
+hipError_t launch_filter_append(FilterArgs a, hipStream_t st);
+// Member-only scoring: tiles of 256 sets in LDS, first-layer members
+// compacted into lanes.  Sample mode writes member scores (the caller
+// pre-fills the sample buffer with 0xFFFF); append mode as above.
+hipError_t launch_f1_bitmap(const FilterArgs& a, hipStream_t st);
+hipError_t launch_filter_sparse_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st);
+hipError_t launch_filter_sparse_append(FilterArgs a, hipStream_t st);
+hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_t r, uint32_t n_q,
+                         uint32_t* cutoff, hipStream_t st);
+hipError_t launch_sort_append(const uint64_t* cand, const uint32_t* cand_count, const uint32_t* cutoff, uint32_t cap,
+                              uint32_t T, uint32_t n_q, uint32_t* f2_ids, uint16_t* f2_scores, uint32_t* f2_count,
+                              uint32_t* fail, hipStream_t st);
 
-// Top-T selection of the scores; writes F2 sorted by (score, id).
+// Dense top-T selection of the scores; writes F2 sorted by (score, id).
 struct SelectBufs {
   uint32_t* hist;     // [n_q][L + 2]
   uint32_t* sel;      // [n_q][4]: tau, count_below, need_eq, Tq

@@ -58,8 +58,12 @@ def test_query_sketch_bit_exact(tiny):
 
 
 def _oracle_results(case, A, M, T, k):
-    return [search.search(case.ix_oracle, case.query(i), A=A, M=M, T=T, k=k)
-            for i in range(len(case.q_off) - 1)]
+    key = (A, M, T, k)
+    cache = case.__dict__.setdefault("_res", {})
+    if key not in cache:
+        cache[key] = [search.search(case.ix_oracle, case.query(i), A=A, M=M, T=T, k=k)
+                      for i in range(len(case.q_off) - 1)]
+    return cache[key]
 
 
 def _check_candidates(case, res, T):
@@ -93,6 +97,24 @@ def test_candidates_bit_exact(tiny):
 def test_search_matches_oracle(tiny):
     res = _oracle_results(tiny, 3, 1, 200, 10)
     _check_search(tiny, res, 10)
+
+
+@pytest.mark.parametrize("env,fallback", [({}, False), ({"BVS_SELECT": "dense"}, True),
+                                          ({"BVS_APPEND_CAP": "8"}, True), ({"BVS_APPEND_CAP": "300"}, None),
+                                          ({"BVS_FILTER": "dense"}, False),
+                                          ({"BVS_FILTER": "dense", "BVS_APPEND_CAP": "8"}, True)])
+def test_selection_paths_agree(tiny, monkeypatch, env, fallback):
+    from paper_2412_03301_amd import bvs
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    res = _oracle_results(tiny, 3, 1, 200, 10)
+    bvs.profile_enable(True)
+    _check_candidates(tiny, res, 200)
+    _check_search(tiny, res, 10)
+    used = bvs.profile_read()["fallback"][1] > 0
+    bvs.profile_enable(False)
+    if fallback is not None:
+        assert used == fallback
 
 
 def test_hausdorff_all_exact(tiny):
@@ -150,6 +172,7 @@ VARIANTS = {
     "d384_L4096": (1100, 5, 100, 384, 20, 4096, 16, 64, 500, 5, 3, 1, "subset"),
     "d768_fresh_queries": (600, 5, 60, 768, 10, 4096, 16, 64, 200, 6, 3, 1, 48),
     "big_queries": (500, 2, 30, 128, 6, 1024, 8, 32, 100, 4, 3, 1, 128),
+    "sampled_cutoff_30k": (30000, 2, 16, 64, 300, 512, 4, 16, 100, 6, 3, 1, "subset"),
 }
 
 
@@ -160,7 +183,10 @@ def variant(request):
     return build_case(n, lo, hi, d, top, L, s, k, T, nq, A=A, M=M, seed=3, queries=qk), (A, M, T)
 
 
-def test_variant_pipeline(variant):
+@pytest.mark.parametrize("filt", ["default", "dense", "sparse"])
+def test_variant_pipeline(variant, filt, monkeypatch):
+    if filt != "default":
+        monkeypatch.setenv("BVS_FILTER", filt)
     case, (A, M, T) = variant
     k = min(10, T)
     assert np.array_equal(to_np(case.ix_gpu.encode(case.db.vectors.cuda())).view(np.uint64),
