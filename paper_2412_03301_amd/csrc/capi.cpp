@@ -318,6 +318,7 @@ struct QueryWs {
   uint16_t* f2_scores;
   uint32_t* f2_count;
   uint32_t* h2;
+  uint32_t* thr;          // [n_q] shared re-rank bound
   uint64_t* topk_tmp;
 };
 
@@ -381,6 +382,7 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->f2_scores = c.take<uint16_t>((uint64_t)n_q * g.T);
   w->f2_count = c.take<uint32_t>(n_q);
   w->h2 = c.take<uint32_t>((uint64_t)n_q * g.T);
+  w->thr = c.take<uint32_t>(n_q);
   w->topk_tmp = c.take<uint64_t>(topk_tmp_words(g.T, n_q, kMaxK));
 }
 
@@ -828,7 +830,8 @@ bvs_status bvs_search(const bvs_index* ix, const float* d_q, const uint64_t* h_q
   BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
   BVS_TRY(run_filters(ix, n_q, NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof));
   HIP_TRY(staged(prof, S_RERANK, [&] {
-    return launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, w.h2, st);
+    return launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, k, w.thr, w.h2,
+                            st);
   }));
   HIP_TRY(staged(prof, S_TOPK, [&] {
     return launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);

@@ -36,10 +36,17 @@ size_t haus_lds_bytes(uint32_t max_rows, uint32_t dp) {
   return (size_t)rows * q_row_stride(dp) * 2 + (size_t)rows * 4;
 }
 
+// Squared Hausdorff distance (2^24-scaled) of one database set against the
+// staged query.  The item is abandoned, returning kAbandoned, as soon as the
+// largest completed column minimum (a lower bound of the result) exceeds
+// `bound`: such a set cannot be among the k nearest when `bound` is at least
+// the k-th smallest distance.
+static constexpr uint32_t kAbandoned = 0xFFFFFFFFu;
+
 template <int KS, int MAXQT>
 __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uint32_t m, const uint8_t* qh_s,
                                               const uint8_t* ql_s, const uint32_t* qn_s, uint32_t mq,
-                                              uint32_t nqt) {
+                                              uint32_t nqt, uint32_t bound = 0xFFFFFFFFu) {
   const uint32_t lane = lane_id();
   const uint32_t g = lane >> 4, c16 = lane & 15;
   const uint32_t dp = KS * 64;
@@ -104,6 +111,7 @@ __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uin
       const uint32_t cm = row16_min_u32(vmin[r]);
       if (vok[r]) colmax = max(colmax, cm);
     }
+    if (bound != 0xFFFFFFFFu && vt + 16 < m && wave_max_u32(colmax) > bound) return kAbandoned;
   }
   uint32_t rowmax = 0;
 #pragma unroll
@@ -141,18 +149,23 @@ __device__ __forceinline__ void stage_query(const HausQ& qs, uint32_t q, uint32_
   __syncthreads();
 }
 
-// Candidate mode: grid (G, n_q); block b of query q takes items
-// [b * per, min(count[q], (b + 1) * per)) of ids[q][.].
+// Candidate mode: grid (G, n_q).  Block b of query q takes the candidates
+// i0 + b * kCandPerBlock ... of ids[q][i0 .. i1), i1 = min(count[q], lim);
+// waves take them round-robin.  With bounds != nullptr, candidates whose
+// lower bound exceeds bounds[q] are abandoned (h2 = kAbandoned).
+static constexpr uint32_t kCandPerBlock = 64;
+
 template <int KS, int MAXQT>
 __global__ void __launch_bounds__(64 * kHausWaves)
 k_haus_cand(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ count, uint32_t T,
-            uint32_t per, uint32_t* __restrict__ h2) {
+            uint32_t i0, uint32_t lim, const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2) {
   extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t q = blockIdx.y;
-  const uint32_t cnt = count[q];
-  const uint32_t i0 = blockIdx.x * per;
-  if (i0 >= cnt) return;
-  const uint32_t i1 = min(cnt, i0 + per);
+  const uint32_t i1 = min(count[q], lim);
+  const uint32_t b0 = i0 + blockIdx.x * kCandPerBlock;
+  if (b0 >= i1) return;
+  const uint32_t b1 = min(i1, b0 + kCandPerBlock);
+  const uint32_t bound = bounds ? bounds[q] : 0xFFFFFFFFu;
   const uint32_t dp = KS * 64;
   const uint32_t rows_max = (qs.max_rows + 15) / 16 * 16;
   uint8_t* qh_s = smem;
@@ -161,13 +174,31 @@ k_haus_cand(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint32_
   uint32_t mq, nqt;
   stage_query(qs, q, dp, qh_s, ql_s, qn_s, mq, nqt);
   const uint32_t w = threadIdx.x / BVS_WAVE;
-  for (uint32_t it = i0 + w; it < i1; it += kHausWaves) {
+  for (uint32_t it = b0 + w; it < b1; it += kHausWaves) {
     const uint32_t j = ids[(uint64_t)q * T + it];
     const uint64_t o0 = db.offsets[j];
     const uint32_t m = (uint32_t)(db.offsets[j + 1] - o0);
-    const uint32_t hsq = haus_item<KS, MAXQT>(db, o0, m, qh_s, ql_s, qn_s, mq, nqt);
+    const uint32_t hsq = haus_item<KS, MAXQT>(db, o0, m, qh_s, ql_s, qn_s, mq, nqt, bound);
     if (lane_id() == 0) h2[(uint64_t)q * T + it] = hsq;
   }
+}
+
+// One wave per query: bounds[q] = k-th smallest of h2[q][0 .. min(count, n)),
+// n <= 64, or all ones when fewer than k are there.
+__global__ void __launch_bounds__(64)
+k_kth_bound(const uint32_t* __restrict__ h2, const uint32_t* __restrict__ count, uint32_t T, uint32_t n, uint32_t k,
+            uint32_t* __restrict__ bounds) {
+  const uint32_t q = blockIdx.x, lane = lane_id();
+  const uint32_t nv = min(count[q], n);
+  const uint32_t v = lane < nv ? h2[(uint64_t)q * T + lane] : 0xFFFFFFFFu;
+  uint32_t rank = 0;
+  for (uint32_t i = 0; i < nv; ++i) {
+    const uint32_t o = (uint32_t)__shfl((int)v, (int)i, BVS_WAVE);
+    rank += (o < v || (o == v && i < lane)) ? 1u : 0u;
+  }
+  const uint64_t hit = ballot(lane < nv && rank == k - 1);
+  const uint32_t kth = (uint32_t)__shfl((int)v, hit ? (int)__builtin_ctzll(hit) : 0, BVS_WAVE);
+  if (lane == 0) bounds[q] = (nv >= k && hit) ? kth : 0xFFFFFFFFu;
 }
 
 // All-sets mode.  Work units (query, chunk of kAllChunk sets) are numbered so
@@ -232,19 +263,28 @@ uint32_t haus_max_rows_supported(uint32_t dp) {
   return rows;
 }
 
+// Three exact phases: full distances for the first kCandPerBlock candidates
+// (the best by sketch distance), their k-th smallest as a bound per query,
+// then the remaining candidates with abandoning against that bound.
 hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids, const uint32_t* count,
-                            uint32_t T, uint32_t* h2, hipStream_t st) {
+                            uint32_t T, uint32_t k, uint32_t* thr, uint32_t* h2, hipStream_t st) {
   if (q.n_q == 0) return hipSuccess;
-  const uint32_t per = 64;
-  const uint32_t G = (T + per - 1) / per;
   const size_t lds = haus_lds_bytes(q.max_rows, db.dp);
+  const uint32_t n0 = std::min(T, kCandPerBlock);
   return dispatch_haus(db.dp, q.max_rows, [&](auto ks, auto mqt) -> hipError_t {
     constexpr int KS = decltype(ks)::value, MQ = decltype(mqt)::value;
     hipError_t e = hipFuncSetAttribute((const void*)k_haus_cand<KS, MQ>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_haus_cand<KS, MQ>), dim3(G, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, ids, count,
-                       T, per, h2);
+    hipLaunchKernelGGL((k_haus_cand<KS, MQ>), dim3(1, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, ids, count, T,
+                       0u, n0, (const uint32_t*)nullptr, h2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (T <= n0) return hipSuccess;
+    hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, n0, k, thr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint32_t G = (T - n0 + kCandPerBlock - 1) / kCandPerBlock;
+    hipLaunchKernelGGL((k_haus_cand<KS, MQ>), dim3(G, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, ids, count, T,
+                       n0, T, (const uint32_t*)thr, h2);
     return hipGetLastError();
   });
 }

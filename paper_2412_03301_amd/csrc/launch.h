@@ -103,9 +103,12 @@ struct HausQ {
   const int8_t* hi; const uint8_t* lo; const uint32_t* norms; const uint64_t* offsets;
   uint32_t n_q; uint32_t max_rows;
 };
-// Candidate mode: items are ids[q][0 .. count[q]) with stride T.
+// Candidate mode: items are ids[q][0 .. count[q]) with stride T.  Items that
+// provably cannot be among the k nearest may be abandoned (h2 = all ones);
+// thr [n_q] is scratch for the shared bound.
 hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids,
-                            const uint32_t* count, uint32_t T, uint32_t* h2, hipStream_t st);
+                            const uint32_t* count, uint32_t T, uint32_t k, uint32_t* thr,
+                            uint32_t* h2, hipStream_t st);
 // All sets: h2 [n_q][n_sets].
 hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipStream_t st);
 size_t haus_lds_bytes(uint32_t max_rows, uint32_t dp);
