@@ -215,19 +215,29 @@ bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q,
 /* Stage timing.  When enabled, the library records a pair of HIP events on
  * the call's stream around every stage it launches and, after the call's
  * final synchronisation, adds the elapsed time to a process-wide table.
- * Stages: 0 convert, 1 encode (query vectors), 2 query sketch, 3 filter
- * (sampled cutoff and second-layer scores), 4 select (top-T of the
- * appended candidates), 5 re-rank (exact Hausdorff of the candidates),
- * 6 top-k, 7 brute force (Hausdorff to every set), 8 fallback (dense scores
+ * Stages: 0 convert, 1 encode (query vectors), 2 query sketch, 3 cutoff
+ * (first-layer bitmaps, sampled scores and the per-query score cutoff),
+ * 4 filter (member-only scoring with bounded append), 5 select (top-T of the
+ * appended candidates), 6 re-rank (exact Hausdorff of the candidates), 7
+ * top-k, 8 brute force (Hausdorff to every set), 9 fallback (dense scores
  * and histogram selection, used when the sampled cutoff did not hold T
  * candidates or overflowed its buffer).
- * bvs_profile_enable resets the table. */
-#define BVS_N_STAGES 9
+ * Work counters (summed over calls): 0 first-layer member pairs scored by
+ * the filter stage, 1 database vectors read by the re-rank stage, 2 re-rank
+ * candidates abandoned early, 3 re-rank candidates.
+ * bvs_profile_enable(flags) resets the table; flags: BVS_PROFILE_TIMING
+ * records the stage events, BVS_PROFILE_COUNTERS collects the work counters
+ * (their atomics slow the counted kernels somewhat), 0 turns both off. */
+#define BVS_PROFILE_TIMING 1
+#define BVS_PROFILE_COUNTERS 2
+#define BVS_N_STAGES 10
+#define BVS_N_COUNTERS 4
 typedef struct bvs_stage_times {
   double ms[BVS_N_STAGES];
   uint64_t calls[BVS_N_STAGES];
+  uint64_t counters[BVS_N_COUNTERS];
 } bvs_stage_times;
-bvs_status bvs_profile_enable(int on);
+bvs_status bvs_profile_enable(int flags);
 bvs_status bvs_profile_read(bvs_stage_times* out);
 const char* bvs_stage_name(int stage);
 

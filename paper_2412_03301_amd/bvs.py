@@ -28,7 +28,9 @@ EXPORTED = [
     "bvs_bruteforce_workspace_bytes", "bvs_bruteforce", "bvs_hausdorff_all", "bvs_last_error",
     "bvs_version", "bvs_profile_enable", "bvs_profile_read", "bvs_stage_name",
 ]
-N_STAGES = 9
+N_STAGES = 10
+N_COUNTERS = 4
+COUNTER_NAMES = ("filter_pairs", "rerank_vectors", "rerank_abandoned", "rerank_candidates")
 
 
 class Params(C.Structure):
@@ -48,7 +50,8 @@ class IndexInfo(C.Structure):
 
 
 class StageTimes(C.Structure):
-    _fields_ = [("ms", C.c_double * N_STAGES), ("calls", C.c_uint64 * N_STAGES)]
+    _fields_ = [("ms", C.c_double * N_STAGES), ("calls", C.c_uint64 * N_STAGES),
+                ("counters", C.c_uint64 * N_COUNTERS)]
 
 
 class BvsError(RuntimeError):
@@ -136,9 +139,13 @@ def projection(params: Params) -> np.ndarray:
     return out
 
 
-def profile_enable(on: bool = True) -> None:
-    """Start (and reset) or stop per-stage HIP-event timing inside the library."""
-    check(lib().bvs_profile_enable(1 if on else 0))
+PROFILE_TIMING, PROFILE_COUNTERS = 1, 2
+
+
+def profile_enable(on: bool = True, counters: bool = False) -> None:
+    """Reset the table and start (or stop) per-stage HIP-event timing and,
+    separately, the work counters."""
+    check(lib().bvs_profile_enable((PROFILE_TIMING if on else 0) | (PROFILE_COUNTERS if counters else 0)))
 
 
 def profile_read() -> dict:
@@ -146,6 +153,13 @@ def profile_read() -> dict:
     t = StageTimes()
     check(lib().bvs_profile_read(C.byref(t)))
     return {lib().bvs_stage_name(i).decode(): (float(t.ms[i]), int(t.calls[i])) for i in range(N_STAGES)}
+
+
+def profile_counters() -> dict:
+    """Work counters accumulated since profile_enable."""
+    t = StageTimes()
+    check(lib().bvs_profile_read(C.byref(t)))
+    return {COUNTER_NAMES[i]: int(t.counters[i]) for i in range(N_COUNTERS)}
 
 
 def params_check(params: Params) -> None:

@@ -163,14 +163,16 @@ bvs_status read_status(uint32_t* d_status, hipStream_t st, const char* what) {
 }
 
 // ------------------------------------------------------------------ stage timing
-const char* const kStageNames[BVS_N_STAGES] = {"convert", "encode", "query_sketch", "filter", "select",
-                                               "rerank",  "topk",   "bruteforce",   "fallback"};
+const char* const kStageNames[BVS_N_STAGES] = {"convert", "encode", "query_sketch", "cutoff",     "filter",
+                                               "select",  "rerank", "topk",         "bruteforce", "fallback"};
 
 struct ProfTable {
   std::mutex mu;
-  bool on = false;
+  bool on = false;        // stage events
+  bool counters_on = false;
   double ms[BVS_N_STAGES] = {};
   uint64_t calls[BVS_N_STAGES] = {};
+  uint64_t counters[BVS_N_COUNTERS] = {};
   std::vector<hipEvent_t> pool;
 };
 ProfTable g_prof;
@@ -180,10 +182,12 @@ struct CallProf {
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> recs;
   hipStream_t st;
-  bool on;
+  bool on;          // record stage events
+  bool count;       // collect work counters
   explicit CallProf(hipStream_t s) : st(s) {
     std::lock_guard<std::mutex> g(g_prof.mu);
     on = g_prof.on;
+    count = g_prof.counters_on;
   }
   hipEvent_t take() {
     {
@@ -215,8 +219,17 @@ struct CallProf {
     }
     recs.clear();
   }
-  // Call after the stream has been synchronised.
-  void finish() {
+  // Call after the stream has been synchronised.  stats: device work
+  // counters of this call (may be null).
+  void finish(const unsigned long long* d_stats = nullptr) {
+    static_assert(BVS_N_COUNTERS == kStatCounters, "counter layout");
+    std::vector<unsigned long long> c((size_t)kStatSlots * kStatCounters);
+    if (count && d_stats &&
+        hipMemcpy(c.data(), d_stats, c.size() * sizeof(c[0]), hipMemcpyDeviceToHost) == hipSuccess) {
+      std::lock_guard<std::mutex> g(g_prof.mu);
+      for (uint32_t s = 0; s < kStatSlots; ++s)
+        for (int i = 0; i < BVS_N_COUNTERS; ++i) g_prof.counters[i] += c[(size_t)s * kStatCounters + i];
+    }
     if (!on) return;
     std::vector<std::pair<int, float>> t;
     for (auto& r : recs) {
@@ -243,7 +256,7 @@ hipError_t staged(CallProf& p, int stage, F&& f) {
   return e;
 }
 
-enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE, S_FALLBACK };
+enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_CUTOFF, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE, S_FALLBACK };
 
 }  // namespace
 
@@ -318,7 +331,8 @@ struct QueryWs {
   uint16_t* f2_scores;
   uint32_t* f2_count;
   uint32_t* h2;
-  uint32_t* thr;          // [n_q] shared re-rank bound
+  uint32_t* thr;          // [n_q] re-rank bound
+  unsigned long long* stats;   // [4] work counters
   uint64_t* topk_tmp;
 };
 
@@ -383,6 +397,7 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->f2_count = c.take<uint32_t>(n_q);
   w->h2 = c.take<uint32_t>((uint64_t)n_q * g.T);
   w->thr = c.take<uint32_t>(n_q);
+  w->stats = c.take<unsigned long long>((uint64_t)kStatSlots * kStatCounters);
   w->topk_tmp = c.take<uint64_t>(topk_tmp_words(g.T, n_q, kMaxK));
 }
 
@@ -456,6 +471,7 @@ FilterArgs filter_args(const bvs_index* ix, uint32_t n_q, const QueryWs& w) {
   a.cand_count = w.cand_count;
   a.planes = ix->planes;
   a.f1 = w.f1;
+  a.stats = nullptr;   // set by the caller when profiling
   return a;
 }
 
@@ -465,13 +481,17 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
   const Geometry& g = ix->g;
   BVS_TRY(query_side(ix, n_q, NQ, w, st, prof));
   FilterArgs a = filter_args(ix, n_q, w);
+  if (prof.count) {
+    HIP_TRY(launch_fill_u32((uint32_t*)w.stats, 2ull * kStatSlots * kStatCounters, 0, st));
+    a.stats = w.stats;
+  }
   if (!force_dense_select()) {
     const uint32_t n_blocks = (uint32_t)(ix->ld / 256);
     const bool sparse = use_sparse_filter(g.M);
     uint32_t* d_fail = w.status + 1;
     HIP_TRY(launch_fill_u32(w.cand_count, n_q, 0, st));
     HIP_TRY(launch_fill_u32(d_fail, 1, 0, st));
-    HIP_TRY(staged(prof, S_FILTER, [&]() -> hipError_t {
+    HIP_TRY(staged(prof, S_CUTOFF, [&]() -> hipError_t {
       hipError_t e;
       if (sparse && g.M == 1) {
         e = launch_f1_bitmap(a, st);
@@ -479,26 +499,26 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
       }
       if (ix->n <= w.cap) {
         // every member fits the buffer: admit them all
-        e = launch_fill_u32(w.cutoff, n_q, 0xFFFFFFFFu, st);
-      } else {
-        const uint32_t nsb = std::min(kSampleBlocks, n_blocks);
-        FilterArgs as = a;
-        as.scores = w.sample;
-        if (sparse) {
-          e = launch_fill_u32((uint32_t*)w.sample, (uint64_t)n_q * nsb * 128, 0xFFFFFFFFu, st);
-          if (e != hipSuccess) return e;
-          e = launch_filter_sparse_sample(as, nsb, st);
-        } else {
-          e = launch_filter_sample(as, nsb, st);
-        }
+        return launch_fill_u32(w.cutoff, n_q, 0xFFFFFFFFu, st);
+      }
+      const uint32_t nsb = std::min(kSampleBlocks, n_blocks);
+      FilterArgs as = a;
+      as.scores = w.sample;
+      if (sparse) {
+        e = launch_fill_u32((uint32_t*)w.sample, (uint64_t)n_q * nsb * 128, 0xFFFFFFFFu, st);
         if (e != hipSuccess) return e;
-        const uint64_t S = (uint64_t)nsb * 256;
-        const uint64_t sampled = std::min<uint64_t>(S, ix->n);
-        const uint32_t r = (uint32_t)std::max<uint64_t>(
-            1, (kCutoffAlpha * (uint64_t)g.T * sampled + ix->n - 1) / ix->n);
-        e = launch_cutoff(w.sample, (uint32_t)S, g.L, r, n_q, w.cutoff, st);
+        as.stats = nullptr;
+        e = launch_filter_sparse_sample(as, nsb, st);
+      } else {
+        e = launch_filter_sample(as, nsb, st);
       }
       if (e != hipSuccess) return e;
+      const uint64_t S = (uint64_t)nsb * 256;
+      const uint64_t sampled = std::min<uint64_t>(S, ix->n);
+      const uint32_t r = (uint32_t)std::max<uint64_t>(1, (kCutoffAlpha * (uint64_t)g.T * sampled + ix->n - 1) / ix->n);
+      return launch_cutoff(w.sample, (uint32_t)S, g.L, r, n_q, w.cutoff, st);
+    }));
+    HIP_TRY(staged(prof, S_FILTER, [&]() -> hipError_t {
       return sparse ? launch_filter_sparse_append(a, st) : launch_filter_append(a, st);
     }));
     HIP_TRY(staged(prof, S_SELECT, [&] {
@@ -555,13 +575,15 @@ extern "C" {
 const char* bvs_last_error(void) { return g_err.c_str(); }
 const char* bvs_version(void) { return "bvs 0.1 (gfx950)"; }
 
-bvs_status bvs_profile_enable(int on) {
+bvs_status bvs_profile_enable(int flags) {
   std::lock_guard<std::mutex> g(g_prof.mu);
-  g_prof.on = on != 0;
+  g_prof.on = (flags & BVS_PROFILE_TIMING) != 0;
+  g_prof.counters_on = (flags & BVS_PROFILE_COUNTERS) != 0;
   for (int i = 0; i < BVS_N_STAGES; ++i) {
     g_prof.ms[i] = 0;
     g_prof.calls[i] = 0;
   }
+  for (int i = 0; i < BVS_N_COUNTERS; ++i) g_prof.counters[i] = 0;
   return BVS_OK;
 }
 
@@ -572,6 +594,7 @@ bvs_status bvs_profile_read(bvs_stage_times* out) {
     out->ms[i] = g_prof.ms[i];
     out->calls[i] = g_prof.calls[i];
   }
+  for (int i = 0; i < BVS_N_COUNTERS; ++i) out->counters[i] = g_prof.counters[i];
   return BVS_OK;
 }
 
@@ -807,7 +830,7 @@ bvs_status bvs_search_candidates(const bvs_index* ix, const float* d_q, const ui
   BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
   BVS_TRY(run_filters(ix, n_q, NQ, w, d_ids, d_scores, d_count, st, prof));
   const bvs_status s = read_status(w.status, st, "queries");
-  prof.finish();
+  prof.finish(prof.count ? w.stats : nullptr);
   return s;
 }
 
@@ -831,13 +854,13 @@ bvs_status bvs_search(const bvs_index* ix, const float* d_q, const uint64_t* h_q
   BVS_TRY(run_filters(ix, n_q, NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof));
   HIP_TRY(staged(prof, S_RERANK, [&] {
     return launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, k, w.thr, w.h2,
-                            st);
+                            prof.count ? w.stats : nullptr, st);
   }));
   HIP_TRY(staged(prof, S_TOPK, [&] {
     return launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
   }));
   const bvs_status s = read_status(w.status, st, "queries");
-  prof.finish();
+  prof.finish(prof.count ? w.stats : nullptr);
   return s;
 }
 

@@ -77,6 +77,30 @@ __device__ __forceinline__ v4i mfma_i8(v4i a, v4i b, v4i c) {
 
 __host__ __device__ constexpr uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Work counters: kStatSlots slots of 4 counters; workgroups add their totals
+// to slot (linear block id % kStatSlots) so that no single address takes
+// every atomic.  The host sums the slots.
+constexpr uint32_t kStatSlots = 64;
+constexpr uint32_t kStatCounters = 4;
+
+// Block-wide sum of up to three per-wave counters (lane 0 of each wave holds
+// the wave's value; every wave must call), added to counters first, first+1,
+// first+2 of the block's slot.  Uses one LDS word per wave and counter.
+__device__ __forceinline__ void stats_add(unsigned long long* stats, uint32_t first, uint32_t a, uint32_t b = 0,
+                                          uint32_t c = 0) {
+  __shared__ uint32_t part[3][16];
+  const uint32_t w = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+  if ((threadIdx.x & 63) == 0) { part[0][w] = a; part[1][w] = b; part[2][w] = c; }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long t = 0;
+    for (uint32_t i = 0; i < nw; ++i) t += part[threadIdx.x][i];
+    const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    if (t && first + threadIdx.x < kStatCounters)
+      atomicAdd(&stats[(blk % kStatSlots) * kStatCounters + first + threadIdx.x], t);
+  }
+}
+
 // Status bits raised by kernels that validate data.
 enum : uint32_t {
   ST_OFF_GRID = 1u,     // a value is not a multiple of 2^-12 or |x| > 1 (or not finite)

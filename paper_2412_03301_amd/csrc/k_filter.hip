@@ -213,6 +213,7 @@ k_filter_sparse(FilterArgs a) {
     vmask[i] = b >= a.n_sets ? 0ull : (a.n_sets - b >= 64 ? ~0ull : (1ull << (a.n_sets - b)) - 1);
   }
   uint64_t mn[4];
+  uint64_t pairs = 0;
   if (w < a.n_q) tile_members(a, w, tile0, lane, vmask, mn);
   for (uint32_t q = w; q < a.n_q; q += NW) {
     uint64_t m[4];
@@ -220,6 +221,7 @@ k_filter_sparse(FilterArgs a) {
     for (int i = 0; i < 4; ++i) m[i] = mn[i];
     if (q + NW < a.n_q) tile_members(a, q + NW, tile0, lane, vmask, mn);
     const uint32_t nm = popc64(m[0]) + popc64(m[1]) + popc64(m[2]) + popc64(m[3]);
+    pairs += nm;
     if (nm == 0) continue;
     uint32_t base = 0;
 #pragma unroll
@@ -257,6 +259,7 @@ k_filter_sparse(FilterArgs a) {
     }
     wave_lds_sync();
   }
+  if (APPEND && a.stats) stats_add(a.stats, 0, (uint32_t)pairs);
 }
 
 template <bool APPEND>

@@ -46,7 +46,8 @@ static constexpr uint32_t kAbandoned = 0xFFFFFFFFu;
 template <int KS, int MAXQT>
 __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uint32_t m, const uint8_t* qh_s,
                                               const uint8_t* ql_s, const uint32_t* qn_s, uint32_t mq,
-                                              uint32_t nqt, uint32_t bound = 0xFFFFFFFFu) {
+                                              uint32_t nqt, uint32_t bound = 0xFFFFFFFFu,
+                                              uint32_t* rows_read = nullptr) {
   const uint32_t lane = lane_id();
   const uint32_t g = lane >> 4, c16 = lane & 15;
   const uint32_t dp = KS * 64;
@@ -56,6 +57,7 @@ __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uin
   for (int i = 0; i < MAXQT; ++i) qmin[i] = 0xFFFFFFFFu;
   uint32_t colmax = 0;
   for (uint32_t vt = 0; vt < m; vt += 16) {
+    if (rows_read) *rows_read += min(16u, m - vt);
     const uint32_t vrow = vt + c16;
     const bool vrow_ok = vrow < m;
     v4i ah[KS], al[KS];
@@ -158,7 +160,8 @@ static constexpr uint32_t kCandPerBlock = 64;
 template <int KS, int MAXQT>
 __global__ void __launch_bounds__(64 * kHausWaves)
 k_haus_cand(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ count, uint32_t T,
-            uint32_t i0, uint32_t lim, const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2) {
+            uint32_t i0, uint32_t lim, const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2,
+            unsigned long long* __restrict__ stats) {
   extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t q = blockIdx.y;
   const uint32_t i1 = min(count[q], lim);
@@ -174,13 +177,18 @@ k_haus_cand(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint32_
   uint32_t mq, nqt;
   stage_query(qs, q, dp, qh_s, ql_s, qn_s, mq, nqt);
   const uint32_t w = threadIdx.x / BVS_WAVE;
+  uint32_t rows = 0, abandoned = 0, items = 0;
   for (uint32_t it = b0 + w; it < b1; it += kHausWaves) {
     const uint32_t j = ids[(uint64_t)q * T + it];
     const uint64_t o0 = db.offsets[j];
     const uint32_t m = (uint32_t)(db.offsets[j + 1] - o0);
-    const uint32_t hsq = haus_item<KS, MAXQT>(db, o0, m, qh_s, ql_s, qn_s, mq, nqt, bound);
+    const uint32_t hsq = haus_item<KS, MAXQT>(db, o0, m, qh_s, ql_s, qn_s, mq, nqt, bound,
+                                              stats ? &rows : nullptr);
     if (lane_id() == 0) h2[(uint64_t)q * T + it] = hsq;
+    abandoned += hsq == kAbandoned ? 1u : 0u;
+    ++items;
   }
+  if (stats) stats_add(stats, 1, rows, abandoned, items);
 }
 
 // One wave per query: bounds[q] = k-th smallest of h2[q][0 .. min(count, n)),
@@ -267,7 +275,8 @@ uint32_t haus_max_rows_supported(uint32_t dp) {
 // (the best by sketch distance), their k-th smallest as a bound per query,
 // then the remaining candidates with abandoning against that bound.
 hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids, const uint32_t* count,
-                            uint32_t T, uint32_t k, uint32_t* thr, uint32_t* h2, hipStream_t st) {
+                            uint32_t T, uint32_t k, uint32_t* thr, uint32_t* h2, unsigned long long* stats,
+                            hipStream_t st) {
   if (q.n_q == 0) return hipSuccess;
   const size_t lds = haus_lds_bytes(q.max_rows, db.dp);
   const uint32_t n0 = std::min(T, kCandPerBlock);
@@ -277,14 +286,14 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_haus_cand<KS, MQ>), dim3(1, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, ids, count, T,
-                       0u, n0, (const uint32_t*)nullptr, h2);
+                       0u, n0, (const uint32_t*)nullptr, h2, stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (T <= n0) return hipSuccess;
     hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, n0, k, thr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const uint32_t G = (T - n0 + kCandPerBlock - 1) / kCandPerBlock;
     hipLaunchKernelGGL((k_haus_cand<KS, MQ>), dim3(G, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, ids, count, T,
-                       n0, T, (const uint32_t*)thr, h2);
+                       n0, T, (const uint32_t*)thr, h2, stats);
     return hipGetLastError();
   });
 }

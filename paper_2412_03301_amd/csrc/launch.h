@@ -65,6 +65,7 @@ struct FilterArgs {
   uint32_t* cand_count;        // append mode: [n_q]
   const uint64_t* planes;      // membership bitmaps [L][ld/64] (first layer, M = 1)
   uint64_t* f1;                // per-query first-layer bitmaps [n_q][ld/64] (M = 1)
+  unsigned long long* stats;   // work counters (see bvs_stage_times), may be null
 };
 hipError_t launch_filter_dense(FilterArgs a, hipStream_t st);
 hipError_t launch_filter_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st);
@@ -108,7 +109,7 @@ struct HausQ {
 // thr [n_q] is scratch for the shared bound.
 hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids,
                             const uint32_t* count, uint32_t T, uint32_t k, uint32_t* thr,
-                            uint32_t* h2, hipStream_t st);
+                            uint32_t* h2, unsigned long long* stats, hipStream_t st);
 // All sets: h2 [n_q][n_sets].
 hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipStream_t st);
 size_t haus_lds_bytes(uint32_t max_rows, uint32_t dp);
