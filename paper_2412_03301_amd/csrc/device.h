@@ -12,7 +12,29 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Index of the calling wave in its workgroup, marked wave-uniform so that
+// values derived from it live in scalar registers and drive scalar loads
+// and branches.
+__device__ __forceinline__ uint32_t wave_id() {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / BVS_WAVE));
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Read-only view of global data in the constant address space: uniform
+// loads through it become scalar loads.  Only for data that no kernel writes
+// while it is being read.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+#else
+template <typename T>
+using cptr = const T*;   // host pass of kernel bodies: plain pointer
+#endif
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
 
 __device__ __forceinline__ uint32_t popc32(uint32_t x) { return __builtin_popcount(x); }
 __device__ __forceinline__ uint32_t popc64(uint64_t x) { return __builtin_popcountll(x); }

@@ -136,7 +136,7 @@ __device__ __forceinline__ EncodeShared encode_setup(const HashGeom& g, uint8_t*
   EncodeShared sh;
   sh.idx = (uint16_t*)smem;
   const uint32_t tab_bytes = (uint32_t)align_up((uint64_t)g.L * g.SP * 2, 16);
-  const uint32_t w = threadIdx.x / BVS_WAVE;
+  const uint32_t w = wave_id();
   sh.av = (int16_t*)(smem + tab_bytes) + w * (g.dim_padded + 8);
   const uint32_t n16 = g.L * g.SP / 8;
   for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) ((uint4*)sh.idx)[i] = ((const uint4*)g.idx)[i];
@@ -165,7 +165,7 @@ k_encode_vectors(HashGeom g, const int8_t* __restrict__ hi, const uint8_t* __res
   const uint32_t lane = lane_id();
   const uint32_t nw = blockDim.x / BVS_WAVE;
   const uint32_t koff = g.s * 4096u;
-  for (uint64_t v = blockIdx.x * (uint64_t)nw + threadIdx.x / BVS_WAVE; v < n; v += (uint64_t)gridDim.x * nw) {
+  for (uint64_t v = blockIdx.x * (uint64_t)nw + wave_id(); v < n; v += (uint64_t)gridDim.x * nw) {
     stage_vector(sh.av, hi, lo, v, g.dim_padded, lane);
     wave_lds_sync();
     uint32_t key[R];
@@ -196,7 +196,7 @@ k_encode_sets(HashGeom g, const int8_t* __restrict__ hi, const uint8_t* __restri
   const uint32_t koff = g.s * 4096u;
   constexpr int NC = (R + 3) / 4;
   constexpr int NO = (R + 63) / 64;
-  for (uint64_t set = blockIdx.x * (uint64_t)nw + threadIdx.x / BVS_WAVE; set < n_sets;
+  for (uint64_t set = blockIdx.x * (uint64_t)nw + wave_id(); set < n_sets;
        set += (uint64_t)gridDim.x * nw) {
     uint32_t cnt[NC];
     uint64_t orb[NO];

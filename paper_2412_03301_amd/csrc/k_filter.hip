@@ -168,7 +168,7 @@ __device__ __forceinline__ void tile_members(const FilterArgs& a, uint32_t q, ui
 #pragma unroll
     for (int i = 0; i < 4; ++i) m[i] = vmask[i];
   } else if (a.M == 1) {
-    const uint64_t* f = a.f1 + (uint64_t)q * (a.ld / 64) + tile0 / 64;
+    const cptr<uint64_t> f = as_const(a.f1) + (uint64_t)q * (a.ld / 64) + tile0 / 64;
 #pragma unroll
     for (int i = 0; i < 4; ++i) m[i] = f[i] & vmask[i];
   } else {
@@ -188,14 +188,17 @@ __device__ __forceinline__ void tile_members(const FilterArgs& a, uint32_t q, ui
 // filters are staged in LDS chunk-major ([chunk][set], 16 B per entry).
 // Each wave takes whole queries: it reads the query's first-layer masks for
 // the tile (prefetched one query ahead), compacts the members into lanes
-// (ascending set order) and computes the Hamming distance only for them,
-// one LDS read and 8 VALU operations per 128-bit chunk and member; the
-// query sketch words are wave-uniform scalar loads.
+// (ascending set order) and computes the Hamming distance only for them.
+// Chunks are processed in groups of 8: the group's query words come through
+// scalar loads and its tile entries through LDS reads, then one wait covers
+// both (scalar and LDS loads share a completion counter), then 8 VALU
+// operations per chunk and member.
 template <int RC, bool APPEND>
 __global__ void __launch_bounds__(1024)
 k_filter_sparse(FilterArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   constexpr uint32_t NW = 16;
+  constexpr int G = RC < 8 ? RC : 8;
   uint4* tile = (uint4*)smem;                         // [RC][256]
   uint8_t* lists = smem + (size_t)RC * 256 * 16;      // [NW][256]
   const uint64_t tile0 = (uint64_t)blockIdx.x * a.block_stride * 256ull;
@@ -204,7 +207,7 @@ k_filter_sparse(FilterArgs a) {
     tile[i] = a.bits[(uint64_t)c * a.ld + tile0 + s];
   }
   __syncthreads();
-  const uint32_t w = threadIdx.x / BVS_WAVE, lane = lane_id();
+  const uint32_t w = wave_id(), lane = lane_id();
   uint8_t* list = lists + w * 256;
   uint64_t vmask[4];
 #pragma unroll
@@ -230,18 +233,25 @@ k_filter_sparse(FilterArgs a) {
       base += popc64(m[i]);
     }
     wave_lds_sync();
-    const uint4* sqq = a.sq + (uint64_t)q * RC;
-    const uint32_t cut = APPEND ? a.cutoff[q] : 0u;
+    const cptr<uint4> sqq = as_const(a.sq) + (uint64_t)q * RC;
+    const uint32_t cut = APPEND ? as_const(a.cutoff)[q] : 0u;
     for (uint32_t g = 0; g < nm; g += 64) {
       const uint32_t idx = g + lane;
       const bool act = idx < nm;
       const uint32_t sl = act ? list[idx] : 0u;
       uint32_t acc = 0;
-#pragma unroll 8
-      for (int c = 0; c < RC; ++c) {
-        const uint4 x = tile[c * 256 + sl];
-        const uint4 sv = sqq[c];
-        acc += popc32(x.x ^ sv.x) + popc32(x.y ^ sv.y) + popc32(x.z ^ sv.z) + popc32(x.w ^ sv.w);
+      for (int c0 = 0; c0 < RC; c0 += G) {
+        // keep the query words per group in scalar registers (not hoisted)
+        asm volatile("" ::: "memory");
+        uint4 sv[G], xv[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) sv[j] = sqq[c0 + j];
+#pragma unroll
+        for (int j = 0; j < G; ++j) xv[j] = tile[(c0 + j) * 256 + sl];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+          acc += popc32(xv[j].x ^ sv[j].x) + popc32(xv[j].y ^ sv[j].y) + popc32(xv[j].z ^ sv[j].z) +
+                 popc32(xv[j].w ^ sv[j].w);
       }
       if (!APPEND) {
         if (act) a.scores[(uint64_t)q * a.ld_out + (uint64_t)blockIdx.x * 256 + sl] = (uint16_t)acc;

@@ -176,7 +176,7 @@ k_haus_cand(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint32_
   uint32_t* qn_s = (uint32_t*)(smem + 2 * rows_max * q_row_stride(dp));
   uint32_t mq, nqt;
   stage_query(qs, q, dp, qh_s, ql_s, qn_s, mq, nqt);
-  const uint32_t w = threadIdx.x / BVS_WAVE;
+  const uint32_t w = wave_id();
   uint32_t rows = 0, abandoned = 0, items = 0;
   for (uint32_t it = b0 + w; it < b1; it += kHausWaves) {
     const uint32_t j = ids[(uint64_t)q * T + it];
@@ -233,7 +233,7 @@ k_haus_all(HausDb db, HausQ qs, uint32_t n_chunks, uint64_t n_units, uint32_t* _
   uint32_t* qn_s = (uint32_t*)(smem + 2 * rows_max * q_row_stride(dp));
   uint32_t mq, nqt;
   stage_query(qs, q, dp, qh_s, ql_s, qn_s, mq, nqt);
-  const uint32_t w = threadIdx.x / BVS_WAVE;
+  const uint32_t w = wave_id();
   for (uint64_t j = s0 + w; j < s1; j += kHausWaves) {
     const uint64_t o0 = db.offsets[j];
     const uint32_t m = (uint32_t)(db.offsets[j + 1] - o0);
