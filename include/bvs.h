@@ -40,7 +40,8 @@
  *   offsets[j] .. offsets[j+1]-1; offsets[0] = 0 and offsets must strictly
  *   increase (a set has at least one vector, Def. 2).  A set id is its
  *   position j.  Database sets hold at most 255 vectors, query sets at most
- *   65535 (BVS_ERANGE otherwise).
+ *   65535 (BVS_ERANGE otherwise); calls that compute Hausdorff distances
+ *   take query sets of at most 256 vectors (BVS_ENOTSUP otherwise).
  * - Results are sorted ascending by (distance, id); distances are Euclidean
  *   (not squared), float32.  With fewer than k results, count[q] says how
  *   many are valid and the rest are id = 0xFFFFFFFF, distance = +inf.
@@ -211,6 +212,82 @@ bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q,
                              const uint64_t* h_q_offsets, uint32_t n_q,
                              void* d_workspace, uint64_t workspace_bytes,
                              uint32_t* d_h2, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched search: many query sets of uneven size through the whole cascade
+ * (Alg. 6) with no host round trip.  The exact re-rank of every query runs
+ * in ONE persistent launch: resident workgroups take (query, 64-candidate
+ * chunk) items from a device counter, largest queries first.  Results are
+ * identical to bvs_search on the same queries (the cascade is exact given
+ * F2, and F2 is a function of the query alone).
+ *
+ * Life cycle: bvs_batch_create (host only: validates the offsets, orders the
+ * queries by size, sizes the workspace) -> bvs_batch_bind (uploads the
+ * offsets, runs the autotuner when asked, and with config.graph captures
+ * the whole launch sequence into a hipGraph; synchronises the stream) ->
+ * bvs_batch_launch any number of times (enqueues the graph, or the launch
+ * sequence; never synchronises) -> bvs_batch_status (synchronises and
+ * reports BVS_ERANGE for off-grid query data of the last launch) ->
+ * bvs_batch_destroy.  Between launches the caller may rewrite the query
+ * vectors in place (same offsets); the bound buffers must stay valid until
+ * the last launch has completed.  Graph capture needs a stream other than
+ * the null stream.
+ *
+ * Autotuner: with lds_rows or waves = 0, bind times every valid shape of the
+ * persistent re-rank, query rows staged in LDS in {32, 64, 128} x waves per
+ * workgroup (sets in flight against one staged query, one wave per set) in
+ * {2, 4, 8}, on the bound batch itself, after running the cascade up to F2
+ * once; shapes whose kernel spills registers or does not fit a CU are
+ * skipped.  The fastest shape is cached per process for the shape class
+ * (dim, T, k, largest query tile count, log2 n_q) and reused by later binds
+ * of the same class without timing.
+ */
+typedef struct bvs_batch bvs_batch;
+
+typedef struct bvs_batch_config {
+  uint32_t lds_rows;   /* 16..256, multiple of 16; 0 = autotune */
+  uint32_t waves;      /* 2, 4 or 8; 0 = autotune */
+  uint32_t graph;      /* nonzero: capture the launch sequence at bind */
+  uint32_t flags;      /* must be 0 */
+} bvs_batch_config;
+
+#define BVS_TUNE_MAX 16
+typedef struct bvs_batch_info {
+  uint32_t n_q, max_rows;          /* queries, vectors in the largest */
+  uint64_t n_q_vectors;            /* vectors over all queries */
+  uint64_t workspace_bytes;        /* needed by bvs_batch_bind */
+  uint32_t lds_rows, waves;        /* re-rank shape in use (0 before bind) */
+  uint32_t blocks;                 /* persistent workgroups launched */
+  uint32_t from_cache;             /* shape taken from the tuner cache */
+  uint32_t graph;                  /* launches replay a captured graph */
+  uint32_t n_tried;                /* shapes timed by the tuner */
+  uint32_t tried_lds_rows[BVS_TUNE_MAX];
+  uint32_t tried_waves[BVS_TUNE_MAX];
+  float tried_ms[BVS_TUNE_MAX];    /* re-rank time of each shape */
+} bvs_batch_info;
+
+/* Host only.  h_q_offsets [n_q + 1] is copied.  k as for bvs_search. */
+bvs_status bvs_batch_create(const bvs_index* ix, const uint64_t* h_q_offsets,
+                            uint32_t n_q, uint32_t k,
+                            const bvs_batch_config* config, bvs_batch** out);
+
+/* Binds device buffers: d_q float32 [n_q_vectors][dim], the workspace of
+ * bvs_batch_info.workspace_bytes, and outputs as for bvs_search.  May be
+ * called again to rebind (the previous graph is released). */
+bvs_status bvs_batch_bind(bvs_batch* b, const float* d_q, void* d_workspace,
+                          uint64_t workspace_bytes, uint32_t* d_ids,
+                          float* d_dist, uint32_t* d_count, void* stream);
+
+/* Enqueues one batched search on `stream`; BVS_ESTATE before bind. */
+bvs_status bvs_batch_launch(bvs_batch* b, void* stream);
+
+/* Synchronises `stream` and checks the last launch's query data. */
+bvs_status bvs_batch_status(bvs_batch* b, void* stream);
+
+bvs_status bvs_batch_get_info(const bvs_batch* b, bvs_batch_info* out);
+
+/* Frees the plan and its graph (not the caller's buffers). */
+void bvs_batch_destroy(bvs_batch* b);
 
 /* Stage timing.  When enabled, the library records a pair of HIP events on
  * the call's stream around every stage it launches and, after the call's

@@ -27,7 +27,10 @@ EXPORTED = [
     "bvs_search_workspace_bytes", "bvs_query_sketch", "bvs_search_candidates", "bvs_search",
     "bvs_bruteforce_workspace_bytes", "bvs_bruteforce", "bvs_hausdorff_all", "bvs_last_error",
     "bvs_version", "bvs_profile_enable", "bvs_profile_read", "bvs_stage_name",
+    "bvs_batch_create", "bvs_batch_bind", "bvs_batch_launch", "bvs_batch_status", "bvs_batch_get_info",
+    "bvs_batch_destroy",
 ]
+TUNE_MAX = 16
 N_STAGES = 10
 N_COUNTERS = 4
 COUNTER_NAMES = ("filter_pairs", "rerank_vectors", "rerank_abandoned", "rerank_candidates")
@@ -52,6 +55,18 @@ class IndexInfo(C.Structure):
 class StageTimes(C.Structure):
     _fields_ = [("ms", C.c_double * N_STAGES), ("calls", C.c_uint64 * N_STAGES),
                 ("counters", C.c_uint64 * N_COUNTERS)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("lds_rows", C.c_uint32), ("waves", C.c_uint32), ("graph", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("n_q", C.c_uint32), ("max_rows", C.c_uint32), ("n_q_vectors", C.c_uint64),
+                ("workspace_bytes", C.c_uint64), ("lds_rows", C.c_uint32), ("waves", C.c_uint32),
+                ("blocks", C.c_uint32), ("from_cache", C.c_uint32), ("graph", C.c_uint32),
+                ("n_tried", C.c_uint32), ("tried_lds_rows", C.c_uint32 * TUNE_MAX),
+                ("tried_waves", C.c_uint32 * TUNE_MAX), ("tried_ms", C.c_float * TUNE_MAX)]
 
 
 class BvsError(RuntimeError):
@@ -99,6 +114,12 @@ def lib():
             "bvs_profile_enable": (C.c_int, [C.c_int]),
             "bvs_profile_read": (C.c_int, [P]),
             "bvs_stage_name": (C.c_char_p, [C.c_int]),
+            "bvs_batch_create": (C.c_int, [P, P, U32, U32, P, C.POINTER(P)]),
+            "bvs_batch_bind": (C.c_int, [P, P, P, U64, P, P, P, P]),
+            "bvs_batch_launch": (C.c_int, [P, P]),
+            "bvs_batch_status": (C.c_int, [P, P]),
+            "bvs_batch_get_info": (C.c_int, [P, P]),
+            "bvs_batch_destroy": (None, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -318,3 +339,77 @@ def as_u32(t: torch.Tensor) -> np.ndarray:
 
 def as_u16(t: torch.Tensor) -> np.ndarray:
     return t.cpu().numpy().view(np.uint16)
+
+
+class Batch:
+    """A batched search plan over one index (bvs_batch_*): the whole cascade
+    for many query sets with one persistent re-rank launch, optionally
+    captured once in a hipGraph.  Outputs as for Index.search.  Graph capture
+    needs a non-default stream; by default the plan makes its own."""
+
+    def __init__(self, index: Index, q: torch.Tensor, q_offsets, k: int, lds_rows: int = 0, waves: int = 0,
+                 graph: bool = True, stream=None):
+        L = lib()
+        self.index = index
+        off, n_q, NQ = index._qargs(q, q_offsets)
+        self.n_q, self.k = n_q, k
+        self.q = q
+        cfg = BatchConfig(lds_rows, waves, 1 if graph else 0, 0)
+        h = C.c_void_p()
+        check(L.bvs_batch_create(index._h, _u64p(off), n_q, k, C.byref(cfg), C.byref(h)))
+        self._h = h
+        if stream is None and graph:
+            stream = torch.cuda.Stream(device=index.device)
+        self.stream = stream
+        info = self.info()
+        self.ws = _workspace(int(info["workspace_bytes"]), index.device)
+        dev = index.device
+        self.ids = torch.empty(n_q, k, dtype=torch.int32, device=dev)
+        self.dist = torch.empty(n_q, k, dtype=torch.float32, device=dev)
+        self.count = torch.empty(n_q, dtype=torch.int32, device=dev)
+        st = self._stream_obj()
+        st.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(st):
+            check(L.bvs_batch_bind(self._h, _ptr(q), _ptr(self.ws), self.ws.numel(), _ptr(self.ids),
+                                   _ptr(self.dist), _ptr(self.count), _stream(st)))
+
+    def _stream_obj(self):
+        return self.stream if self.stream is not None else torch.cuda.current_stream(self.index.device)
+
+    def launch(self):
+        """Enqueue one batched search (no synchronisation)."""
+        st = self._stream_obj()
+        st.wait_stream(torch.cuda.current_stream(self.index.device))
+        check(lib().bvs_batch_launch(self._h, _stream(st)))
+        torch.cuda.current_stream(self.index.device).wait_stream(st)
+
+    def status(self):
+        """Synchronise and raise BvsError on bad query data."""
+        check(lib().bvs_batch_status(self._h, _stream(self._stream_obj())))
+
+    def run(self):
+        """One launch, synchronised; returns (ids, dist, count)."""
+        self.launch()
+        self.status()
+        return self.ids, self.dist, self.count
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        check(lib().bvs_batch_get_info(self._h, C.byref(i)))
+        n = int(i.n_tried)
+        return dict(n_q=int(i.n_q), max_rows=int(i.max_rows), n_q_vectors=int(i.n_q_vectors),
+                    workspace_bytes=int(i.workspace_bytes), lds_rows=int(i.lds_rows), waves=int(i.waves),
+                    blocks=int(i.blocks), from_cache=bool(i.from_cache), graph=bool(i.graph),
+                    tried=[(int(i.tried_lds_rows[j]), int(i.tried_waves[j]), float(i.tried_ms[j]))
+                           for j in range(n)])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bvs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,7 +8,10 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -184,10 +187,10 @@ struct CallProf {
   hipStream_t st;
   bool on;          // record stage events
   bool count;       // collect work counters
-  explicit CallProf(hipStream_t s) : st(s) {
+  explicit CallProf(hipStream_t s, bool allowed = true) : st(s) {
     std::lock_guard<std::mutex> g(g_prof.mu);
-    on = g_prof.on;
-    count = g_prof.counters_on;
+    on = allowed && g_prof.on;
+    count = allowed && g_prof.counters_on;
   }
   hipEvent_t take() {
     {
@@ -476,8 +479,12 @@ FilterArgs filter_args(const bvs_index* ix, uint32_t n_q, const QueryWs& w) {
 }
 
 // Both filter layers: F2 of every query into f2_ids / f2_scores / f2_count.
+// host_sync: the dense fallback is chosen on the host after reading the
+// failure count; otherwise it is always enqueued and does nothing unless the
+// count on the device is nonzero (no host round trip, graph-safe).
 bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const QueryWs& w, uint32_t* f2_ids,
-                       uint16_t* f2_scores, uint32_t* f2_count, hipStream_t st, CallProf& prof) {
+                       uint16_t* f2_scores, uint32_t* f2_count, hipStream_t st, CallProf& prof,
+                       bool host_sync = true) {
   const Geometry& g = ix->g;
   BVS_TRY(query_side(ix, n_q, NQ, w, st, prof));
   FilterArgs a = filter_args(ix, n_q, w);
@@ -525,6 +532,16 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
       return launch_sort_append(w.cand_app, w.cand_count, w.cutoff, w.cap, g.T, n_q, f2_ids, f2_scores, f2_count,
                                 d_fail, st);
     }));
+    if (!host_sync) {
+      FilterArgs ag = a;
+      ag.run_if = d_fail;
+      HIP_TRY(staged(prof, S_FALLBACK, [&]() -> hipError_t {
+        hipError_t e = launch_filter_dense(ag, st);
+        if (e != hipSuccess) return e;
+        return launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, f2_ids, f2_scores, f2_count, d_fail, st);
+      }));
+      return BVS_OK;
+    }
     uint32_t h_fail = 0;
     HIP_TRY(hipMemcpyAsync(&h_fail, d_fail, sizeof h_fail, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -533,7 +550,7 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
   HIP_TRY(staged(prof, S_FALLBACK, [&]() -> hipError_t {
     hipError_t e = launch_filter_dense(a, st);
     if (e != hipSuccess) return e;
-    return launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, f2_ids, f2_scores, f2_count, st);
+    return launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, f2_ids, f2_scores, f2_count, nullptr, st);
   }));
   return BVS_OK;
 }
@@ -909,6 +926,362 @@ bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q, const uint64
   const bvs_status s = read_status(w.status, st, "queries");
   prof.finish();
   return s;
+}
+
+}  // extern "C"
+
+// ====================================================================== batch
+struct bvs_batch {
+  const bvs_index* ix = nullptr;
+  uint32_t n_q = 0, k = 0, max_rows = 0;
+  uint64_t NQ = 0;
+  std::vector<uint64_t> off;      // query offsets (host copy)
+  std::vector<uint32_t> order;    // queries by size, largest first
+  bvs_batch_config cfg{};
+  bvs_batch_info info{};
+  bool bound = false;
+  const float* d_q = nullptr;
+  uint32_t* d_ids = nullptr;
+  float* d_dist = nullptr;
+  uint32_t* d_count = nullptr;
+  QueryWs w{};
+  uint32_t* d_order = nullptr;
+  uint32_t* d_ctl = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::unique_ptr<CallProf> pending;   // stage events of an eager launch
+};
+
+namespace {
+
+// Largest LDS a persistent re-rank workgroup may stage (the kernel's own
+// static LDS is below 1 KB).
+constexpr size_t kQueueLdsLimit = 159 * 1024;
+
+const uint32_t kTuneRows[] = {32, 64, 128};
+const uint32_t kTuneWaves[] = {2, 4, 8};
+
+// Tuner cache: shape class -> (lds_rows, waves).
+struct TuneKey {
+  uint32_t dp, T, k, nqt, lgq;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dp, T, k, nqt, lgq) < std::tie(o.dp, o.T, o.k, o.nqt, o.lgq);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<uint32_t, uint32_t>> g_tune;
+
+TuneKey tune_key(const bvs_batch* b) {
+  uint32_t lg = 0;
+  while ((1u << lg) < b->n_q) ++lg;
+  return TuneKey{b->ix->g.dp, b->ix->g.T, b->k, (b->max_rows + 15) / 16, lg};
+}
+
+void layout_batch(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, bvs_batch* b) {
+  layout_search(c, ix, n_q, NQ, &b->w);
+  b->d_order = c.take<uint32_t>(n_q);
+  b->d_ctl = c.take<uint32_t>(1ull + n_q);
+}
+
+QueueArgs queue_args(const bvs_batch* b) {
+  QueueArgs a;
+  a.ids = b->w.f2_ids;
+  a.count = b->w.f2_count;
+  a.T = b->ix->g.T;
+  a.k = b->k;
+  a.order = b->d_order;
+  a.nch = (a.T + kCandPerItem - 1) / kCandPerItem;
+  a.lds_rows = b->info.lds_rows;
+  a.ctl = b->d_ctl;
+  a.h2 = b->w.h2;
+  a.stats = nullptr;
+  return a;
+}
+
+// Query conversion and the cascade up to F2, with the fallback decided on
+// the device.
+bvs_status batch_filters(bvs_batch* b, hipStream_t st, CallProf& prof) {
+  const bvs_index* ix = b->ix;
+  QueryWs& w = b->w;
+  HIP_TRY(launch_fill_u32(w.status, 4, 0, st));
+  HIP_TRY(staged(prof, S_CONVERT, [&] {
+    return launch_convert(b->d_q, b->NQ, ix->g.d, ix->g.dp, w.qhi, w.qlo, w.qnorm, w.status, ix->n_cu, st);
+  }));
+  return run_filters(ix, b->n_q, b->NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof, false);
+}
+
+bvs_status batch_rerank(bvs_batch* b, hipStream_t st, CallProf& prof) {
+  QueueArgs a = queue_args(b);
+  if (prof.count) a.stats = b->w.stats;
+  HIP_TRY(staged(prof, S_RERANK, [&] {
+    return launch_haus_queue(haus_db(b->ix), haus_q(b->w, b->n_q, b->max_rows), a, b->info.waves, b->info.blocks, st);
+  }));
+  return BVS_OK;
+}
+
+bvs_status batch_enqueue(bvs_batch* b, hipStream_t st, CallProf& prof) {
+  BVS_TRY(batch_filters(b, st, prof));
+  BVS_TRY(batch_rerank(b, st, prof));
+  const uint32_t T = b->ix->g.T;
+  HIP_TRY(staged(prof, S_TOPK, [&] {
+    return launch_topk(b->w.h2, b->w.f2_ids, b->w.f2_count, T, T, b->n_q, b->k, b->w.topk_tmp, b->d_ids, b->d_dist,
+                       b->d_count, st);
+  }));
+  return BVS_OK;
+}
+
+// Persistent grid of a shape, or 0 when the shape spills or does not fit.
+uint32_t shape_blocks(const bvs_batch* b, uint32_t rows, uint32_t waves) {
+  if (haus_queue_lds_bytes(rows, b->ix->g.dp) > kQueueLdsLimit) return 0;
+  uint32_t bpc = 0, spill = 0;
+  if (haus_queue_occupancy(b->ix->g.dp, rows, waves, &bpc, &spill) != hipSuccess) return 0;
+  if (bpc == 0 || spill > 8) return 0;   // 8 bytes: the work-counter slot
+  return bpc * (uint32_t)b->ix->n_cu;
+}
+
+// Times every candidate shape on the bound batch (F2 computed once first)
+// and keeps the fastest.
+bvs_status batch_tune(bvs_batch* b, hipStream_t st) {
+  CallProf off(st, false);
+  BVS_TRY(batch_filters(b, st, off));
+  HIP_TRY(hipStreamSynchronize(st));
+  const uint32_t rows_needed = (b->max_rows + 15) / 16 * 16;
+  std::vector<uint32_t> rows_c, waves_c;
+  if (b->cfg.lds_rows) {
+    rows_c.push_back(b->cfg.lds_rows);
+  } else {
+    for (uint32_t r : kTuneRows) {
+      const uint32_t rr = std::min(r, rows_needed);
+      if (std::find(rows_c.begin(), rows_c.end(), rr) == rows_c.end()) rows_c.push_back(rr);
+    }
+  }
+  if (b->cfg.waves) waves_c.push_back(b->cfg.waves);
+  else waves_c.assign(std::begin(kTuneWaves), std::end(kTuneWaves));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(BVS_EDEVICE, "hipEventCreate failed");
+  }
+  bvs_status status = BVS_OK;
+  float best = 0.f;
+  b->info.n_tried = 0;
+  for (uint32_t r : rows_c) {
+    for (uint32_t wv : waves_c) {
+      const uint32_t blocks = shape_blocks(b, r, wv);
+      if (!blocks || b->info.n_tried >= BVS_TUNE_MAX) continue;
+      b->info.lds_rows = r;
+      b->info.waves = wv;
+      b->info.blocks = blocks;
+      float ms = 0.f;
+      status = [&]() -> bvs_status {
+        BVS_TRY(batch_rerank(b, st, off));   // warm-up
+        HIP_TRY(hipEventRecord(e0, st));
+        BVS_TRY(batch_rerank(b, st, off));
+        BVS_TRY(batch_rerank(b, st, off));
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        return BVS_OK;
+      }();
+      if (status != BVS_OK) break;
+      ms *= 0.5f;
+      const uint32_t i = b->info.n_tried++;
+      b->info.tried_lds_rows[i] = r;
+      b->info.tried_waves[i] = wv;
+      b->info.tried_ms[i] = ms;
+      if (i == 0 || ms < best) best = ms;
+    }
+    if (status != BVS_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != BVS_OK) return status;
+  if (b->info.n_tried == 0) return fail(BVS_ENOTSUP, "no re-rank shape fits dim %u", b->ix->g.d);
+  for (uint32_t i = 0; i < b->info.n_tried; ++i) {
+    if (b->info.tried_ms[i] == best) {
+      b->info.lds_rows = b->info.tried_lds_rows[i];
+      b->info.waves = b->info.tried_waves[i];
+      break;
+    }
+  }
+  b->info.blocks = shape_blocks(b, b->info.lds_rows, b->info.waves);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[tune_key(b)] = {b->info.lds_rows, b->info.waves};
+  return BVS_OK;
+}
+
+bvs_status batch_capture(bvs_batch* b, hipStream_t st) {
+  if (!st) return fail(BVS_EINVAL, "graph capture needs a stream other than the null stream");
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  CallProf off(st, false);
+  const bvs_status s = batch_enqueue(b, st, off);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &graph);
+  if (s != BVS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  HIP_TRY(e);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIP_TRY(ei);
+  b->exec = exec;
+  return BVS_OK;
+}
+
+void batch_release(bvs_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  if (b->pending) b->pending->release();
+  b->pending.reset();
+  b->bound = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+bvs_status bvs_batch_create(const bvs_index* ix, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
+                            const bvs_batch_config* cfg, bvs_batch** out) {
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (n_q == 0) return fail(BVS_EINVAL, "n_q must be positive");
+  uint32_t max_rows = 0;
+  BVS_TRY(check_offsets(h_q_off, n_q, 65535, "query", &max_rows));
+  if (max_rows > haus_max_rows_supported(ix->g.dp))
+    return fail(BVS_ENOTSUP, "query set of %u vectors exceeds the %u supported", max_rows,
+                haus_max_rows_supported(ix->g.dp));
+  if (k < 1 || k > kMaxK || k > ix->g.T) return fail(BVS_EINVAL, "k %u outside 1..min(64, top_t)", k);
+  bvs_batch_config c{};
+  if (cfg) c = *cfg;
+  if (c.flags != 0) return fail(BVS_EINVAL, "config.flags must be 0");
+  if (c.lds_rows && (c.lds_rows % 16 != 0 || c.lds_rows > 256))
+    return fail(BVS_EINVAL, "config.lds_rows %u is not a multiple of 16 in 16..256", c.lds_rows);
+  if (c.lds_rows && haus_queue_lds_bytes(c.lds_rows, ix->g.dp) > kQueueLdsLimit)
+    return fail(BVS_ENOTSUP, "config.lds_rows %u does not fit in LDS at dim %u", c.lds_rows, ix->g.d);
+  if (c.waves && c.waves != 2 && c.waves != 4 && c.waves != 8)
+    return fail(BVS_EINVAL, "config.waves %u is not 2, 4 or 8", c.waves);
+  std::unique_ptr<bvs_batch> b(new (std::nothrow) bvs_batch());
+  if (!b) return fail(BVS_ENOSPC, "out of host memory");
+  b->ix = ix;
+  b->n_q = n_q;
+  b->k = k;
+  b->max_rows = max_rows;
+  b->NQ = h_q_off[n_q];
+  b->off.assign(h_q_off, h_q_off + n_q + 1);
+  b->order.resize(n_q);
+  for (uint32_t i = 0; i < n_q; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](uint32_t x, uint32_t y) {
+    return h_q_off[x + 1] - h_q_off[x] > h_q_off[y + 1] - h_q_off[y];
+  });
+  b->cfg = c;
+  Carver cv(nullptr);
+  bvs_batch tmp;
+  layout_batch(cv, ix, n_q, b->NQ, &tmp);
+  b->info.n_q = n_q;
+  b->info.max_rows = max_rows;
+  b->info.n_q_vectors = b->NQ;
+  b->info.workspace_bytes = align_up(cv.off, 256);
+  *out = b.release();
+  return BVS_OK;
+}
+
+bvs_status bvs_batch_bind(bvs_batch* b, const float* d_q, void* d_ws, uint64_t ws_bytes, uint32_t* d_ids,
+                          float* d_dist, uint32_t* d_count, void* stream) {
+  if (!b) return fail(BVS_EINVAL, "batch is NULL");
+  if (!d_q) return fail(BVS_EINVAL, "query vectors are NULL");
+  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
+  BVS_TRY(need_ws(ws_bytes, b->info.workspace_bytes, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  batch_release(b);
+  b->d_q = d_q;
+  b->d_ids = d_ids;
+  b->d_dist = d_dist;
+  b->d_count = d_count;
+  Carver c(d_ws);
+  layout_batch(c, b->ix, b->n_q, b->NQ, b);
+  HIP_TRY(hipMemcpyAsync(b->w.qoff, b->off.data(), b->off.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b->d_order, b->order.data(), b->order.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  // re-rank shape: given, cached, or tuned now
+  b->info.from_cache = 0;
+  b->info.n_tried = 0;
+  if (b->cfg.lds_rows && b->cfg.waves) {
+    b->info.lds_rows = b->cfg.lds_rows;
+    b->info.waves = b->cfg.waves;
+  } else {
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune.find(tune_key(b));
+      if (it != g_tune.end() && (!b->cfg.lds_rows || it->second.first == b->cfg.lds_rows) &&
+          (!b->cfg.waves || it->second.second == b->cfg.waves)) {
+        b->info.lds_rows = it->second.first;
+        b->info.waves = it->second.second;
+        hit = true;
+      }
+    }
+    if (hit) b->info.from_cache = 1;
+    else BVS_TRY(batch_tune(b, st));
+  }
+  b->info.blocks = shape_blocks(b, b->info.lds_rows, b->info.waves);
+  if (!b->info.blocks)
+    return fail(BVS_ENOTSUP, "re-rank shape lds_rows %u, waves %u does not fit a CU", b->info.lds_rows,
+                b->info.waves);
+  b->info.graph = 0;
+  if (b->cfg.graph) {
+    BVS_TRY(batch_capture(b, st));
+    b->info.graph = 1;
+  }
+  b->bound = true;
+  return BVS_OK;
+}
+
+bvs_status bvs_batch_launch(bvs_batch* b, void* stream) {
+  if (!b) return fail(BVS_EINVAL, "batch is NULL");
+  if (!b->bound) return fail(BVS_ESTATE, "batch is not bound");
+  hipStream_t st = (hipStream_t)stream;
+  if (b->exec) {
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+    return BVS_OK;
+  }
+  if (b->pending) {
+    // stage events of the previous launch: finish them first
+    HIP_TRY(hipStreamSynchronize(st));
+    b->pending->finish(b->pending->count ? b->w.stats : nullptr);
+    b->pending->release();
+    b->pending.reset();
+  }
+  std::unique_ptr<CallProf> prof(new CallProf(st));
+  BVS_TRY(batch_enqueue(b, st, *prof));
+  if (prof->on || prof->count) b->pending = std::move(prof);
+  return BVS_OK;
+}
+
+bvs_status bvs_batch_status(bvs_batch* b, void* stream) {
+  if (!b) return fail(BVS_EINVAL, "batch is NULL");
+  if (!b->bound) return fail(BVS_ESTATE, "batch is not bound");
+  const bvs_status s = read_status(b->w.status, (hipStream_t)stream, "queries");
+  if (b->pending) {
+    b->pending->finish(b->pending->count ? b->w.stats : nullptr);
+    b->pending->release();
+    b->pending.reset();
+  }
+  return s;
+}
+
+bvs_status bvs_batch_get_info(const bvs_batch* b, bvs_batch_info* out) {
+  if (!b || !out) return fail(BVS_EINVAL, "NULL argument");
+  *out = b->info;
+  return BVS_OK;
+}
+
+void bvs_batch_destroy(bvs_batch* b) {
+  if (!b) return;
+  batch_release(b);
+  delete b;
 }
 
 }  // extern "C"

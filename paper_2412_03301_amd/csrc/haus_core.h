@@ -1,0 +1,223 @@
+// Exact Hausdorff distance (Def. 4) of one database set against a query, on
+// the gfx950 int8 matrix cores; shared by the per-launch and the persistent
+// re-rank kernels.
+//
+// Exactness.  On the 2^-12 grid a = 4096 x is an integer with |a| <= 4096; it
+// is stored split as a = 64 hi + lo with hi in [-64, 64] and lo in [0, 63],
+// both int8.  Then
+//   a . b = 4096 (hi_a . hi_b) + 64 (hi_a . lo_b + lo_a . hi_b) + lo_a . lo_b
+// is four int8 x int8 -> int32 matrix-core products, and
+//   D2 = |a|^2 + |b|^2 - 2 a . b = 2^24 |x - y|^2
+// is an exact integer below 2^28 when both norms are at most 2 (checked when
+// the data are converted), so every comparison is exact and the ranking
+// matches a float64 evaluation bit for bit.
+//
+// One wave computes one set.  For each 16-vector tile of the set it keeps the
+// tile's planes for all of d in registers (the A operand: 16 rows x 64 k per
+// lane group) and loops over the query's 16-row tiles (the B operand).  The
+// first query tiles come from LDS, where the workgroup staged them; tiles
+// beyond the staged rows are read from global memory, where a query read by
+// every wave of the chip stays in L2.  The 16x16 int32 output has database
+// vectors on rows and query vectors on columns:
+//   column minimum over q (per database vector) -> DPP row-16 reduction;
+//   row minimum over v (per query vector) -> carried per lane across tiles,
+//   reduced over the four lane groups at the end of the set.
+// Hausdorff^2 = max(max_v min_q D2, max_q min_v D2).
+#pragma once
+#include "device.h"
+#include "launch.h"
+
+namespace bvs {
+
+// Query tiles a wave keeps row minima for: queries of up to 256 vectors.
+static constexpr int kMaxQueryTiles = 16;
+
+// Result of a set abandoned against its bound.
+static constexpr uint32_t kAbandoned = 0xFFFFFFFFu;
+
+static constexpr uint32_t kCandPerBlock = kCandPerItem;
+
+__host__ __device__ constexpr uint32_t q_row_stride(uint32_t dp) { return dp + 16; }
+
+// Bytes of LDS that staging `rows` query rows takes (planes with a 16-byte
+// row pad against bank conflicts, and the norms).
+__host__ __device__ constexpr size_t haus_stage_bytes(uint32_t rows, uint32_t dp) {
+  return (size_t)rows * q_row_stride(dp) * 2 + (size_t)rows * 4;
+}
+
+// Where a wave reads the query: rows [0, 16 nqt_s) staged in LDS (row stride
+// dp + 16, zero padded), the rest from global memory (row stride dp).
+struct QView {
+  const uint8_t* hs;
+  const uint8_t* ls;
+  const uint32_t* ns;
+  const uint8_t* hg;
+  const uint8_t* lg;
+  const uint32_t* ng;
+  uint32_t mq, nqt, nqt_s;
+};
+
+template <int KS>
+__device__ __forceinline__ void tile_products(const v4i (&ah)[KS], const v4i (&al)[KS], const uint8_t* bh,
+                                              const uint8_t* bl, v4i& hh, v4i& hl, v4i& lh, v4i& ll) {
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const v4i b_h = *(const v4i*)(bh + 64 * k);
+    const v4i b_l = *(const v4i*)(bl + 64 * k);
+    hh = mfma_i8(ah[k], b_h, hh);
+    hl = mfma_i8(ah[k], b_l, hl);
+    lh = mfma_i8(al[k], b_h, lh);
+    ll = mfma_i8(al[k], b_l, ll);
+  }
+}
+
+// Squared Hausdorff distance (2^24-scaled) of database set [o0, o0 + m)
+// against the query (HASG: some query tiles may come from global memory).
+// The set is abandoned, returning kAbandoned, as soon as the largest
+// completed column minimum (a lower bound of the result) exceeds `bound`:
+// such a set cannot be among the k nearest when `bound` is at least the k-th
+// smallest distance.
+template <int KS, int MAXQT, bool HASG>
+__device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uint32_t m, const QView& q,
+                                              uint32_t bound = 0xFFFFFFFFu, uint32_t* rows_read = nullptr) {
+  const uint32_t lane = lane_id();
+  const uint32_t g = lane >> 4, c16 = lane & 15;
+  const uint32_t dp = KS * 64;
+  const uint32_t QS = q_row_stride(dp);
+  uint32_t qmin[MAXQT];
+#pragma unroll
+  for (int i = 0; i < MAXQT; ++i) qmin[i] = 0xFFFFFFFFu;
+  uint32_t colmax = 0;
+  for (uint32_t vt = 0; vt < m; vt += 16) {
+    if (rows_read) *rows_read += min(16u, m - vt);
+    const uint32_t vrow = vt + c16;
+    const bool vrow_ok = vrow < m;
+    v4i ah[KS], al[KS];
+    {
+      const v4i* ph = (const v4i*)(db.hi + (o0 + (vrow_ok ? vrow : 0)) * dp + 16 * g);
+      const v4i* pl = (const v4i*)(db.lo + (o0 + (vrow_ok ? vrow : 0)) * dp + 16 * g);
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const v4i z = {0, 0, 0, 0};
+        ah[k] = vrow_ok ? __builtin_nontemporal_load(ph + 4 * k) : z;
+        al[k] = vrow_ok ? __builtin_nontemporal_load(pl + 4 * k) : z;
+      }
+    }
+    uint32_t nv[4], vmin[4];
+    bool vok[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t v = vt + 4 * g + r;
+      vok[r] = v < m;
+      nv[r] = vok[r] ? db.norms[o0 + v] : 0u;
+      vmin[r] = 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int qt = 0; qt < MAXQT; ++qt) {
+      if ((uint32_t)qt < q.nqt) {
+        v4i hh = {0, 0, 0, 0}, hl = {0, 0, 0, 0}, lh = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
+        const uint32_t qi = qt * 16 + c16;
+        uint32_t qn;
+        if (!HASG || (uint32_t)qt < q.nqt_s) {
+          tile_products<KS>(ah, al, q.hs + qi * QS + 16 * g, q.ls + qi * QS + 16 * g, hh, hl, lh, ll);
+          qn = q.ns[qi];
+        } else {
+          // Global tiles one at a time, with addresses rebuilt per database
+          // tile from a uniform base and a 32-bit lane offset: otherwise the
+          // compiler hoists 16 tiles' addresses and loads into registers.
+          // Rows past the query's end repeat its last row; they are masked
+          // below.
+          asm volatile("" ::: "memory");
+          const uint8_t* hg = uniform_ptr(q.hg);
+          const uint8_t* lg = uniform_ptr(q.lg);
+          uint32_t cl = c16;
+          asm volatile("" : "+s"(hg), "+s"(lg), "+v"(cl));
+          const uint32_t r = min(qt * 16 + cl, q.mq - 1);
+          const uint32_t off = r * dp + 16 * g;
+          tile_products<KS>(ah, al, hg + off, lg + off, hh, hl, lh, ll);
+          qn = q.ng[r];
+        }
+        const bool qok = qi < q.mq;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t dot = (uint32_t)hh[r] * 4096u + ((uint32_t)hl[r] + (uint32_t)lh[r]) * 64u + (uint32_t)ll[r];
+          uint32_t d2 = nv[r] + qn - 2u * dot;
+          d2 = (qok && vok[r]) ? d2 : 0xFFFFFFFFu;
+          vmin[r] = min(vmin[r], d2);
+          qmin[qt] = min(qmin[qt], d2);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t cm = row16_min_u32(vmin[r]);
+      if (vok[r]) colmax = max(colmax, cm);
+    }
+    if (bound != 0xFFFFFFFFu && vt + 16 < m && wave_max_u32(colmax) > bound) return kAbandoned;
+  }
+  uint32_t rowmax = 0;
+#pragma unroll
+  for (int qt = 0; qt < MAXQT; ++qt) {
+    if ((uint32_t)qt < q.nqt) {
+      uint32_t rm = qmin[qt];
+      rm = min(rm, shfl_xor_u32(rm, 16));
+      rm = min(rm, shfl_xor_u32(rm, 32));
+      if ((uint32_t)qt * 16 + c16 < q.mq) rowmax = max(rowmax, rm);
+    }
+  }
+  return wave_max_u32(max(colmax, rowmax));
+}
+
+// Stage the first min(16 ceil(m_q / 16), lds_rows) rows of query q into LDS
+// (rows past the query zero filled) and describe where the rest is read.
+// lds_rows is a multiple of 16.  Ends with a workgroup barrier.
+__device__ __forceinline__ QView stage_query(const HausQ& qs, uint32_t q, uint32_t dp, uint32_t lds_rows,
+                                             uint8_t* smem) {
+  QView v;
+  const uint64_t o0 = qs.offsets[q];
+  v.mq = (uint32_t)(qs.offsets[q + 1] - o0);
+  v.nqt = (v.mq + 15) / 16;
+  v.nqt_s = min(v.nqt, lds_rows / 16);
+  const uint32_t rows = v.nqt_s * 16;
+  const uint32_t QS = q_row_stride(dp);
+  uint8_t* qh_s = smem;
+  uint8_t* ql_s = smem + (size_t)lds_rows * QS;
+  uint32_t* qn_s = (uint32_t*)(smem + (size_t)2 * lds_rows * QS);
+  const uint32_t c16n = dp / 16;
+  for (uint32_t i = threadIdx.x; i < rows * c16n; i += blockDim.x) {
+    const uint32_t r = i / c16n, c = i % c16n;
+    uint4 h = make_uint4(0, 0, 0, 0), l = make_uint4(0, 0, 0, 0);
+    if (r < v.mq) {
+      h = *(const uint4*)(qs.hi + (o0 + r) * dp + 16 * c);
+      l = *(const uint4*)(qs.lo + (o0 + r) * dp + 16 * c);
+    }
+    *(uint4*)(qh_s + r * QS + 16 * c) = h;
+    *(uint4*)(ql_s + r * QS + 16 * c) = l;
+  }
+  for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x) qn_s[r] = r < v.mq ? qs.norms[o0 + r] : 0u;
+  v.hs = qh_s;
+  v.ls = ql_s;
+  v.ns = qn_s;
+  v.hg = (const uint8_t*)qs.hi + o0 * dp;
+  v.lg = qs.lo + o0 * dp;
+  v.ng = qs.norms + o0;
+  __syncthreads();
+  return v;
+}
+
+// k-th smallest of vals[0 .. nv), nv <= 64, computed by one whole wave (every
+// lane gets it), or all ones when nv < k.
+__device__ __forceinline__ uint32_t wave_kth_smallest(uint32_t v_lane, uint32_t nv, uint32_t k) {
+  const uint32_t lane = lane_id();
+  const uint32_t v = lane < nv ? v_lane : 0xFFFFFFFFu;
+  uint32_t rank = 0;
+  for (uint32_t i = 0; i < nv; ++i) {
+    const uint32_t o = (uint32_t)__shfl((int)v, (int)i, BVS_WAVE);
+    rank += (o < v || (o == v && i < lane)) ? 1u : 0u;
+  }
+  const uint64_t hit = ballot(lane < nv && rank == k - 1);
+  const uint32_t kth = (uint32_t)__shfl((int)v, hit ? (int)__builtin_ctzll(hit) : 0, BVS_WAVE);
+  return (nv >= k && hit) ? kth : 0xFFFFFFFFu;
+}
+
+}  // namespace bvs

@@ -447,15 +447,16 @@ hipError_t launch_query_sketch(const uint64_t* codes, const uint64_t* q_off, uin
 }
 
 // ---------------------------------------------------------------- fill
-__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v, const uint32_t* run_if) {
+  if (run_if && *run_if == 0) return;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
 
-hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st, const uint32_t* run_if) {
   if (n == 0) return hipSuccess;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, p, n, v);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, p, n, v, run_if);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
 template <int QT, bool APPEND>
 __global__ void __launch_bounds__(256)
 k_filter(FilterArgs a) {
+  if (!APPEND && a.run_if && *a.run_if == 0) return;
   const uint64_t j = (uint64_t)blockIdx.x * a.block_stride * 256ull + threadIdx.x;
   const uint32_t q0 = blockIdx.y * QT;
   const uint32_t nq = min((uint32_t)QT, a.n_q - q0);
@@ -331,7 +332,9 @@ __device__ __forceinline__ uint32_t block_excl_scan_flag(bool f, uint32_t* wsum,
 }
 
 __global__ void __launch_bounds__(256)
-k_hist(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t L, uint32_t* __restrict__ hist) {
+k_hist(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t L, uint32_t* __restrict__ hist,
+       const uint32_t* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
   extern __shared__ uint32_t h[];
   const uint32_t q = blockIdx.y;
   const uint32_t nb = L + 2;
@@ -360,7 +363,8 @@ k_hist(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t L, uint32_t* _
 // Tq = min(T, |F1|).
 __global__ void __launch_bounds__(256)
 k_threshold(const uint32_t* __restrict__ hist, uint32_t L, uint32_t T, uint32_t* __restrict__ sel,
-            uint32_t* __restrict__ ctr) {
+            uint32_t* __restrict__ ctr, const uint32_t* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
   __shared__ uint32_t part[256];
   __shared__ uint32_t total_s;
   const uint32_t q = blockIdx.x, t = threadIdx.x;
@@ -402,7 +406,8 @@ k_threshold(const uint32_t* __restrict__ hist, uint32_t L, uint32_t T, uint32_t*
 __global__ void __launch_bounds__(256)
 k_compact(const uint16_t* __restrict__ scores, uint64_t ld, const uint32_t* __restrict__ sel,
           uint32_t* __restrict__ ctr, uint32_t* __restrict__ eqcnt, uint32_t nblk, uint64_t* __restrict__ cand,
-          uint32_t T) {
+          uint32_t T, const uint32_t* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
   __shared__ uint32_t wsum[4];
   const uint32_t q = blockIdx.y, blk = blockIdx.x, lane = lane_id();
   const uint32_t tau = sel[(uint64_t)q * 4], Tq = sel[(uint64_t)q * 4 + 3];
@@ -432,7 +437,9 @@ k_compact(const uint16_t* __restrict__ scores, uint64_t ld, const uint32_t* __re
 
 __global__ void __launch_bounds__(256)
 k_ties(const uint16_t* __restrict__ scores, uint64_t ld, const uint32_t* __restrict__ sel,
-       const uint32_t* __restrict__ eqcnt, uint32_t nblk, uint64_t* __restrict__ cand, uint32_t T) {
+       const uint32_t* __restrict__ eqcnt, uint32_t nblk, uint64_t* __restrict__ cand, uint32_t T,
+       const uint32_t* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
   __shared__ uint32_t wsum[4];
   __shared__ uint32_t red[4];
   const uint32_t q = blockIdx.y, blk = blockIdx.x;
@@ -477,7 +484,9 @@ __device__ void bitonic_sort_lds(uint64_t* k, uint32_t NP) {
 
 __global__ void __launch_bounds__(512)
 k_sort_f2(const uint64_t* __restrict__ cand, const uint32_t* __restrict__ sel, uint32_t T, uint32_t NP,
-          uint32_t* __restrict__ f2_ids, uint16_t* __restrict__ f2_scores, uint32_t* __restrict__ f2_count) {
+          uint32_t* __restrict__ f2_ids, uint16_t* __restrict__ f2_scores, uint32_t* __restrict__ f2_count,
+          const uint32_t* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
   extern __shared__ uint64_t keys[];
   const uint32_t q = blockIdx.x;
   const uint32_t Tq = sel[(uint64_t)q * 4 + 3];
@@ -496,25 +505,26 @@ k_sort_f2(const uint64_t* __restrict__ cand, const uint32_t* __restrict__ sel, u
 
 hipError_t launch_select(const uint16_t* scores, uint64_t ld, uint32_t L, uint32_t T, uint32_t n_q,
                          const SelectBufs& b, uint32_t* f2_ids, uint16_t* f2_scores, uint32_t* f2_count,
-                         hipStream_t st) {
+                         const uint32_t* run_if, hipStream_t st) {
   if (n_q == 0) return hipSuccess;
   const uint32_t nblk = select_blocks(ld);
-  hipError_t e = launch_fill_u32(b.hist, (uint64_t)n_q * (L + 2), 0, st);
+  hipError_t e = launch_fill_u32(b.hist, (uint64_t)n_q * (L + 2), 0, st, run_if);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_hist, dim3(nblk, n_q), dim3(256), (L + 2) * sizeof(uint32_t), st, scores, ld, L, b.hist);
+  hipLaunchKernelGGL(k_hist, dim3(nblk, n_q), dim3(256), (L + 2) * sizeof(uint32_t), st, scores, ld, L, b.hist,
+                     run_if);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_threshold, dim3(n_q), dim3(256), 0, st, b.hist, L, T, b.sel, b.ctr);
+  hipLaunchKernelGGL(k_threshold, dim3(n_q), dim3(256), 0, st, b.hist, L, T, b.sel, b.ctr, run_if);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_compact, dim3(nblk, n_q), dim3(256), 0, st, scores, ld, b.sel, b.ctr, b.eqcnt, nblk,
-                     b.cand, T);
+                     b.cand, T, run_if);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ties, dim3(nblk, n_q), dim3(256), 0, st, scores, ld, b.sel, b.eqcnt, nblk, b.cand, T);
+  hipLaunchKernelGGL(k_ties, dim3(nblk, n_q), dim3(256), 0, st, scores, ld, b.sel, b.eqcnt, nblk, b.cand, T, run_if);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   uint32_t NP = 1;
   while (NP < T) NP <<= 1;
   if (NP < 2) NP = 2;
   hipLaunchKernelGGL(k_sort_f2, dim3(n_q), dim3(512), NP * sizeof(uint64_t), st, b.cand, b.sel, T, NP, f2_ids,
-                     f2_scores, f2_count);
+                     f2_scores, f2_count, run_if);
   return hipGetLastError();
 }
 

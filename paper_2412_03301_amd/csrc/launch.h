@@ -66,6 +66,7 @@ struct FilterArgs {
   const uint64_t* planes;      // membership bitmaps [L][ld/64] (first layer, M = 1)
   uint64_t* f1;                // per-query first-layer bitmaps [n_q][ld/64] (M = 1)
   unsigned long long* stats;   // work counters (see bvs_stage_times), may be null
+  const uint32_t* run_if;      // dense mode: skip all work unless *run_if != 0 (may be null)
 };
 hipError_t launch_filter_dense(FilterArgs a, hipStream_t st);
 hipError_t launch_filter_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st);
@@ -91,9 +92,11 @@ struct SelectBufs {
   uint64_t* cand;     // [n_q][T]
 };
 uint32_t select_blocks(uint64_t ld);
+// With run_if != null every kernel does nothing unless *run_if != 0 (a
+// decision taken on the device, so the launches can sit in a graph).
 hipError_t launch_select(const uint16_t* scores, uint64_t ld, uint32_t L, uint32_t T, uint32_t n_q,
                          const SelectBufs& b, uint32_t* f2_ids, uint16_t* f2_scores,
-                         uint32_t* f2_count, hipStream_t st);
+                         uint32_t* f2_count, const uint32_t* run_if, hipStream_t st);
 
 // Exact squared Hausdorff distances (scaled by 2^24).
 struct HausDb {
@@ -113,7 +116,33 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
 // All sets: h2 [n_q][n_sets].
 hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipStream_t st);
 size_t haus_lds_bytes(uint32_t max_rows, uint32_t dp);
+uint32_t haus_lds_rows(uint32_t max_rows, uint32_t dp);
 uint32_t haus_max_rows_supported(uint32_t dp);
+
+// Candidates per re-rank work item (and the size of the first, unbounded
+// phase of the candidate re-rank).
+static constexpr uint32_t kCandPerItem = 64;
+
+// Persistent re-rank of a whole batch (one launch): candidates as for
+// launch_haus_cand; queries are taken in `order` (largest first).
+struct QueueArgs {
+  const uint32_t* ids;       // [n_q][T] candidate ids
+  const uint32_t* count;     // [n_q] candidates per query
+  uint32_t T, k;
+  const uint32_t* order;     // [n_q] queries, largest first
+  uint32_t nch;              // items per query: ceil(T / 64)
+  uint32_t lds_rows;         // query rows staged in LDS (multiple of 16)
+  uint32_t* ctl;             // [1 + n_q]: item counter, then per-query bounds
+  uint32_t* h2;              // [n_q][T] out
+  unsigned long long* stats; // work counters, may be null
+};
+size_t haus_queue_lds_bytes(uint32_t lds_rows, uint32_t dp);
+// Resident workgroups per CU and scratch bytes per lane of a queue kernel.
+hipError_t haus_queue_occupancy(uint32_t dp, uint32_t lds_rows, uint32_t waves, uint32_t* blocks_per_cu,
+                                uint32_t* spill_bytes);
+// Clears ctl, then launches `blocks` workgroups of `waves` waves.
+hipError_t launch_haus_queue(const HausDb& db, const HausQ& q, const QueueArgs& a, uint32_t waves,
+                             uint32_t blocks, hipStream_t st);
 
 // First k by (h2, id) of each query.  ids_in may be NULL (item index = id).
 // tmp must hold 2 * n_q * ceil(n_items / 4096) * k uint64.
@@ -124,6 +153,7 @@ hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_
 uint64_t topk_tmp_words(uint64_t n_items, uint32_t n_q, uint32_t k);
 
 // Fill a u32 buffer (used instead of hipMemsetAsync so work stays graph-safe).
-hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st,
+                           const uint32_t* run_if = nullptr);
 
 }  // namespace bvs

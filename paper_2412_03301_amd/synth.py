@@ -126,12 +126,17 @@ def make_subset_queries(db: Database, n_queries: int, seed: int = 0,
 
 
 def make_fresh_queries(n_queries: int, max_size: int, dim: int, n_topics: int,
-                       db_seed: int, seed: int = 0, device="cpu"):
-    """Queries around new entities, sizes log-uniform in [1, max_size]."""
+                       db_seed: int, seed: int = 0, device="cpu", sizes=None):
+    """Queries around new entities, sizes log-uniform in [1, max_size]
+    (or the given sizes)."""
     device = torch.device(device)
     g = _gen("cpu", seed, 20)
     u = torch.rand(n_queries, generator=g, dtype=torch.float64).numpy()
-    sizes = np.clip(np.floor(np.exp(u * math.log(max_size + 1))), 1, max_size).astype(np.int64)
+    if sizes is None:
+        sizes = np.clip(np.floor(np.exp(u * math.log(max_size + 1))), 1, max_size).astype(np.int64)
+    else:
+        sizes = np.asarray(sizes, dtype=np.int64)
+        assert sizes.shape == (n_queries,) and (sizes >= 1).all()
     topic = torch.randint(0, n_topics, (n_queries,), generator=g).numpy()
     centres = torch.randn(n_topics, dim, generator=_gen(device, db_seed, 3), device=device)
     gd = _gen(device, seed, 21)
@@ -151,4 +156,7 @@ WORKLOADS = {
                  code_bits=1024, fan_in=8, wta_k=32, n_queries=16, top_t=200, k=10),
     "scale": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
                   code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10),
+    # the scale database, searched by fresh-entity queries of 1-256 vectors
+    "batched": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
+                    code_bits=4096, fan_in=16, wta_k=64, n_queries=4096, max_query=256, top_t=1000, k=10),
 }

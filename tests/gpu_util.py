@@ -38,6 +38,9 @@ def build_case(n_sets, size_lo, size_hi, dim, n_topics, code_bits, fan_in, wta_k
     ix_g = bvs.Index(p, db.vectors.cuda(), db.offsets)
     if queries == "subset":
         q, q_off, _ = synth.make_subset_queries(db, n_queries, seed=seed + 1)
+    elif isinstance(queries, (list, tuple)):
+        q, q_off = synth.make_fresh_queries(n_queries, max(queries), dim, n_topics, db_seed=seed, seed=seed + 1,
+                                            sizes=queries)
     else:
         q, q_off = synth.make_fresh_queries(n_queries, queries, dim, n_topics, db_seed=seed, seed=seed + 1)
     q_np = q.numpy().astype(np.float64)

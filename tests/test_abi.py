@@ -126,3 +126,19 @@ def test_calls_reject_null_index(bvs):
     assert L.bvs_bruteforce(None, fake, off.ctypes.data_as(bvs.PU64), 1, 10, fake, 1 << 20, fake, fake, fake,
                             None) == bvs.BVS_EINVAL
     assert L.bvs_sketch_views(None, None, None) == bvs.BVS_EINVAL
+
+
+def test_batch_calls_reject_null_handles(bvs):
+    L = bvs.lib()
+    off = np.array([0, 3, 5], np.uint64)
+    h = C.c_void_p()
+    assert L.bvs_batch_create(None, off.ctypes.data_as(bvs.PU64), 2, 10, None, C.byref(h)) == bvs.BVS_EINVAL
+    assert h.value is None
+    assert L.bvs_batch_create(None, off.ctypes.data_as(bvs.PU64), 2, 10, None, None) == bvs.BVS_EINVAL
+    fake = C.c_void_p(0x1000)
+    assert L.bvs_batch_bind(None, fake, fake, 1 << 20, fake, fake, fake, None) == bvs.BVS_EINVAL
+    assert L.bvs_batch_launch(None, None) == bvs.BVS_EINVAL
+    assert L.bvs_batch_status(None, None) == bvs.BVS_EINVAL
+    info = bvs.BatchInfo()
+    assert L.bvs_batch_get_info(None, C.byref(info)) == bvs.BVS_EINVAL
+    L.bvs_batch_destroy(None)
