@@ -45,7 +45,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scale", choices=["scale", "tiny"])
+    ap.add_argument("--workload", default="scale", choices=["scale", "tiny", "batched"])
+    ap.add_argument("--per-query-sample", type=int, default=1024,
+                    help="batched workload: queries searched one call each for the comparison")
     ap.add_argument("--n-sets", type=int, default=None, help="override the set count (for quick runs)")
     ap.add_argument("--queries", type=int, default=None)
     ap.add_argument("--top-t", type=int, default=None)
@@ -128,6 +130,193 @@ def cpu_baseline(db_cpu, offsets, q_cpu, q_off, cfg, n_sets_full, sample_sets, s
     }
 
 
+def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file):
+    """Roofline of the dominant stage (filter or re-rank) from its
+    algorithmic work per launch and its measured time per launch."""
+    csrc = os.path.join(ROOT, "paper_2412_03301_amd", "csrc")
+    dominant = max(("filter", "rerank"), key=lambda s2: per_step.get(s2, 0.0))
+    rer_bytes = work["rerank_vectors"] * (dim_padded * 2 + 4)
+    if dominant == "filter":
+        # member-only scoring: per (member set, query) pair, one XOR and one
+        # popcount per 32-bit word of the L-bit sketches
+        ops = work["filter_pairs"] * (L // 32) * 2
+        ach = ops / (per_step["filter"] / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_TOPS, "unit": "Tops/s", "frac": ach / ALU_PEAK_TOPS,
+                "kernel": "k_filter_sparse<32,true>",
+                "algorithmic": f"{work['filter_pairs']:.4g} member pairs x {L // 32} words x 2 int32 ops per launch",
+                "traffic": traffic_from_profiles(os.path.join(csrc, "k_filter.hip"), "k_filter_sparse")}
+    else:
+        ach = rer_bytes / (per_step["rerank"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "kernel": rerank_kernel,
+                "algorithmic": f"{rer_bytes:.4g} bytes per launch (vectors read x (2 dp + 4))",
+                "traffic": traffic_from_profiles(os.path.join(csrc, rerank_file), rerank_kernel)}
+    rerank_roof = {"achieved_gbs": rer_bytes / (per_step["rerank"] / 1e3) / 1e9 if per_step.get("rerank") else None,
+                   "vectors_read": work["rerank_vectors"], "candidates": work["rerank_candidates"],
+                   "abandoned": work["rerank_abandoned"]}
+    return roof, rerank_roof
+
+
+def brute_recall(ix, q, q_off, ids, k, nb):
+    """Recall@k of `ids` against the exact brute force on the first nb
+    queries, and the brute-force throughput on them."""
+    import numpy as np
+    import torch
+    qb = q[: int(q_off[nb])].contiguous()
+    ob = q_off[: nb + 1]
+    bws = ix.brute_workspace(nb, int(ob[-1]))
+    ix.bruteforce(q[: int(q_off[2])].contiguous(), q_off[:3], k)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bids, _, _ = ix.bruteforce(qb, ob, k, ws=bws)
+    torch.cuda.synchronize()
+    bt = time.perf_counter() - t0
+    bids = bids.cpu().numpy().view(np.uint32)
+    recall = float(np.mean([len(set(ids[i].tolist()) & set(bids[i].tolist())) / k for i in range(nb)]))
+    return recall, nb / bt
+
+
+def batched(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
+    """Uneven query batch through the batched entry points: one hipGraph
+    replay per step (persistent re-rank inside), autotuned re-rank shape,
+    compared with one search call per query and with one multi-launch
+    search call over the whole batch."""
+    import numpy as np
+    import torch
+
+    from paper_2412_03301_amd import bvs
+
+    dev = q.device
+    n_q, k = w["n_queries"], w["k"]
+    NQ = int(q_off[-1])
+    sizes = np.diff(q_off)
+    log(f"batched: {n_q} queries, sizes {sizes.min()}-{sizes.max()} (mean {sizes.mean():.1f})")
+    t0 = time.perf_counter()
+    b = bvs.Batch(ix, q, q_off, k, graph=True)
+    info = b.info()
+    log(f"plan bound in {time.perf_counter() - t0:.2f} s: lds_rows={info['lds_rows']} waves={info['waves']} "
+        f"blocks={info['blocks']} tried={info['tried']}")
+    for i in range(args.warmup):
+        b.run()
+    torch.cuda.synchronize()
+    st = b.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    ev0.record(st)
+    for i in range(args.steps):
+        lib_status = bvs.lib().bvs_batch_launch(b._h, bvs._stream(st))
+        bvs.check(lib_status)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t_wall
+    gpu_ms = ev0.elapsed_time(ev1)
+    b.status()
+    elapsed_s = max(wall_s, gpu_ms / 1e3)
+    qps = n_q * args.steps / elapsed_s
+    log(f"timed {args.steps} graph replays: {gpu_ms:.2f} ms (wall {wall_s * 1e3:.2f} ms) -> {qps:.0f} q/s")
+    ids = b.ids.cpu().numpy().view(np.uint32)
+
+    # stage times and work: the same plan shape launched eagerly with events
+    e = bvs.Batch(ix, q, q_off, k, lds_rows=info["lds_rows"], waves=info["waves"], graph=False)
+    e.run()
+    bvs.profile_enable(True)
+    for i in range(args.steps):
+        e.run()
+    stages = bvs.profile_read()
+    bvs.profile_enable(False, counters=True)
+    e.run()
+    work = dict(bvs.profile_counters())
+    bvs.profile_enable(False)
+    same = np.array_equal(e.ids.cpu().numpy(), b.ids.cpu().numpy())
+    e.close()
+    per_step = {name: ms / max(1, calls) for name, (ms, calls) in stages.items() if calls}
+
+    # one multi-launch search call over the whole batch
+    ws = ix.search_workspace(n_q, NQ)
+    out = (torch.empty(n_q, k, dtype=torch.int32, device=dev), torch.empty(n_q, k, dtype=torch.float32, device=dev),
+           torch.empty(n_q, dtype=torch.int32, device=dev))
+    ix.search(q, q_off, k, ws=ws, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ix.search(q, q_off, k, ws=ws, out=out)
+    torch.cuda.synchronize()
+    call_qps = n_q * args.steps / (time.perf_counter() - t0)
+    same_call = np.array_equal(out[0].cpu().numpy(), b.ids.cpu().numpy())
+    del ws
+
+    # one search call per query (each call: its own launches and host sync)
+    nper = min(args.per_query_sample, n_q)
+    ws1 = ix.search_workspace(1, int(sizes.max()))
+    out1 = (torch.empty(1, k, dtype=torch.int32, device=dev), torch.empty(1, k, dtype=torch.float32, device=dev),
+            torch.empty(1, dtype=torch.int32, device=dev))
+    qs = [q[int(q_off[i]):int(q_off[i + 1])].contiguous() for i in range(nper)]
+    ix.search(qs[0], [0, qs[0].shape[0]], k, ws=ws1, out=out1)
+    mism = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nper):
+        ix.search(qs[i], [0, qs[i].shape[0]], k, ws=ws1, out=out1)
+    torch.cuda.synchronize()
+    per_query_qps = nper / (time.perf_counter() - t0)
+    for i in range(0, nper, max(1, nper // 16)):
+        ix.search(qs[i], [0, qs[i].shape[0]], k, ws=ws1, out=out1)
+        mism += int(not np.array_equal(out1[0].cpu().numpy()[0].view(np.uint32), ids[i]))
+    log(f"per-query calls: {per_query_qps:.0f} q/s on {nper}; one search call: {call_qps:.0f} q/s; "
+        f"identical results: eager {same}, call {same_call}, per-query mismatches {mism}")
+
+    recall = brute_qps = None
+    if not args.no_brute:
+        nb = min(args.brute_queries, n_q)
+        recall, brute_qps = brute_recall(ix, q, q_off, ids, k, nb)
+        log(f"brute force on {nb} queries: {brute_qps:.1f} q/s; recall@10 {recall:.4f}")
+
+    roof, rerank_roof = rooflines(per_step, work, w["code_bits"], ix.dim_padded, "k_haus_queue", "k_batch.hip")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        qc = q[: int(q_off[args.cpu_sample_queries])].cpu().numpy()
+        cpu = cpu_baseline(cpu_db, db_offsets, qc, q_off, cfg, w["n_sets"], args.cpu_sample_sets,
+                           args.cpu_sample_queries)
+    L = w["code_bits"]
+    return {
+        "metric": METRIC,
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={w['dim']}, "
+                         f"{w['n_topics']} topics; FlyHash L={L}, s={w['fan_in']}, wta_k={w['wta_k']}; "
+                         f"A=3, M=1, T={w['top_t']}; {n_q} fresh-entity queries of 1-{w['max_query']} vectors "
+                         f"(log-uniform) per step, one hipGraph replay; top-{k}"),
+            "n_sets": w["n_sets"], "n_vectors": n_vec, "n_queries": n_q, "query_vectors": NQ,
+        },
+        "batch_plan": {k2: info[k2] for k2 in ("lds_rows", "waves", "blocks", "from_cache", "graph", "tried")},
+        "per_query_calls_qps": per_query_qps,
+        "per_query_sample": nper,
+        "single_call_qps": call_qps,
+        "identical_to_single_call": bool(same_call and same and mism == 0),
+        "recall_at_10": recall,
+        "recall_sample_queries": None if args.no_brute else min(args.brute_queries, n_q),
+        "bruteforce_qps": brute_qps,
+        "speedup_vs_bruteforce": (qps / brute_qps) if brute_qps else None,
+        "stages_ms_per_step": per_step,
+        "work_per_step": work,
+        "rerank": rerank_roof,
+        "index_build_s": build_s,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -160,7 +349,11 @@ def main():
     log(f"generating {w['n_sets']} sets (d={w['dim']}) on the GPU")
     t0 = time.perf_counter()
     db = synth.make_database(w["n_sets"], w["size_lo"], w["size_hi"], w["dim"], w["n_topics"], seed=0, device=dev)
-    q, q_off, _ = synth.make_subset_queries(db, w["n_queries"], seed=1)
+    if args.workload == "batched":
+        q, q_off = synth.make_fresh_queries(w["n_queries"], w["max_query"], w["dim"], w["n_topics"], db_seed=0,
+                                            seed=1, device=dev)
+    else:
+        q, q_off, _ = synth.make_subset_queries(db, w["n_queries"], seed=1)
     q = q.contiguous()
     torch.cuda.synchronize()
     n_vec = int(db.offsets[-1])
@@ -181,6 +374,11 @@ def main():
     log(f"index built in {build_s:.2f} s ({ix.mem.numel() / 2**30:.1f} GiB)")
     db.vectors = None
     torch.cuda.empty_cache()
+
+    if args.workload == "batched":
+        res = batched(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db.offsets)
+        print(json.dumps(res), flush=True)
+        return
 
     n_q = w["n_queries"]
     k = w["k"]
@@ -231,44 +429,13 @@ def main():
     brute_qps = None
     if not args.no_brute:
         nb = min(args.brute_queries, n_q)
-        qb = q[: int(q_off[nb])].contiguous()
-        ob = q_off[: nb + 1]
-        bws = ix.brute_workspace(nb, int(ob[-1]))
-        ix.bruteforce(q[: int(q_off[2])].contiguous(), q_off[:3], k)   # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        bids, _, _ = ix.bruteforce(qb, ob, k, ws=bws)
-        torch.cuda.synchronize()
-        bt = time.perf_counter() - t0
-        brute_qps = nb / bt
-        bids = bids.cpu().numpy().view(np.uint32)
-        recall = float(np.mean([len(set(ids[i].tolist()) & set(bids[i].tolist())) / k for i in range(nb)]))
-        log(f"brute force on {nb} queries: {bt:.2f} s ({brute_qps:.1f} q/s); recall@10 {recall:.4f}")
+        recall, brute_qps = brute_recall(ix, q, q_off, ids, k, nb)
+        log(f"brute force on {nb} queries: {brute_qps:.1f} q/s; recall@10 {recall:.4f}")
 
     per_step = {name: ms / max(1, calls) for name, (ms, calls) in stages.items() if calls}
     work = {k2: v / args.steps for k2, v in counters.items()}
-    csrc = os.path.join(ROOT, "paper_2412_03301_amd", "csrc")
     L = w["code_bits"]
-    dominant = max(("filter", "rerank"), key=lambda s2: per_step.get(s2, 0.0))
-    if dominant == "filter":
-        # member-only scoring: per (member set, query) pair, one XOR and one
-        # popcount per 32-bit word of the L-bit sketches
-        ops = work["filter_pairs"] * (L // 32) * 2
-        ach = ops / (per_step["filter"] / 1e3) / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_TOPS, "unit": "Tops/s", "frac": ach / ALU_PEAK_TOPS,
-                "kernel": "k_filter_sparse<32,true>",
-                "algorithmic": f"{work['filter_pairs']:.4g} member pairs x {L // 32} words x 2 int32 ops per launch",
-                "traffic": traffic_from_profiles(os.path.join(csrc, "k_filter.hip"), "k_filter_sparse")}
-    else:
-        byts = work["rerank_vectors"] * (ix.dim_padded * 2 + 4)
-        ach = byts / (per_step["rerank"] / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "kernel": "k_haus_cand", "algorithmic": f"{byts:.4g} bytes per launch (vectors read x (2 dp + 4))",
-                "traffic": traffic_from_profiles(os.path.join(csrc, "k_haus.hip"), "k_haus_cand")}
-    rer_bytes = work["rerank_vectors"] * (ix.dim_padded * 2 + 4)
-    rerank_roof = {"achieved_gbs": rer_bytes / (per_step["rerank"] / 1e3) / 1e9 if per_step.get("rerank") else None,
-                   "vectors_read": work["rerank_vectors"], "candidates": work["rerank_candidates"],
-                   "abandoned": work["rerank_abandoned"]}
+    roof, rerank_roof = rooflines(per_step, work, L, ix.dim_padded, "k_haus_cand", "k_haus.hip")
 
     cpu = None
     if not args.no_cpu_baseline:

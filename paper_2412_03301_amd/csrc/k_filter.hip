@@ -25,6 +25,9 @@
 
 namespace bvs {
 
+// Grid rows of a launch gated on a device flag (see FilterArgs::run_if).
+static constexpr uint32_t kGatedRows = 8;
+
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -36,11 +39,8 @@ __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
 // cand[q][0 .. cap) and counting them in cand_count[q] (the count may exceed
 // cap; the entries beyond cap are dropped and the caller detects it).
 template <int QT, bool APPEND>
-__global__ void __launch_bounds__(256)
-k_filter(FilterArgs a) {
-  if (!APPEND && a.run_if && *a.run_if == 0) return;
+__device__ __forceinline__ void filter_tile(const FilterArgs& a, uint32_t q0) {
   const uint64_t j = (uint64_t)blockIdx.x * a.block_stride * 256ull + threadIdx.x;
-  const uint32_t q0 = blockIdx.y * QT;
   const uint32_t nq = min((uint32_t)QT, a.n_q - q0);
   const uint32_t lane = lane_id();
   const uint32_t M = a.M;
@@ -105,11 +105,21 @@ k_filter(FilterArgs a) {
   }
 }
 
+// Grid (set blocks, y): block y takes query tiles y, y + gridDim.y, ...
+template <int QT, bool APPEND>
+__global__ void __launch_bounds__(256)
+k_filter(FilterArgs a) {
+  if (!APPEND && a.run_if && *a.run_if == 0) return;
+  for (uint32_t q0 = blockIdx.y * QT; q0 < a.n_q; q0 += gridDim.y * QT) filter_tile<QT, APPEND>(a, q0);
+}
+
 template <bool APPEND>
 static hipError_t go_filter(const FilterArgs& a, uint32_t n_blocks, hipStream_t st) {
   auto go = [&](auto qt) -> hipError_t {
     constexpr int QT = decltype(qt)::value;
-    dim3 grid(n_blocks, (a.n_q + QT - 1) / QT);
+    // a gated launch usually does nothing: few blocks, each looping over tiles
+    const uint32_t tiles = (a.n_q + QT - 1) / QT;
+    dim3 grid(n_blocks, a.run_if ? std::min(tiles, kGatedRows) : tiles);
     hipLaunchKernelGGL((k_filter<QT, APPEND>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
   };
@@ -331,12 +341,8 @@ __device__ __forceinline__ uint32_t block_excl_scan_flag(bool f, uint32_t* wsum,
   return base + r;
 }
 
-__global__ void __launch_bounds__(256)
-k_hist(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t L, uint32_t* __restrict__ hist,
-       const uint32_t* __restrict__ run_if) {
-  if (run_if && *run_if == 0) return;
-  extern __shared__ uint32_t h[];
-  const uint32_t q = blockIdx.y;
+__device__ __forceinline__ void hist_query(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t L,
+                                           uint32_t* __restrict__ hist, uint32_t q, uint32_t* h) {
   const uint32_t nb = L + 2;
   for (uint32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0;
   __syncthreads();
@@ -357,6 +363,16 @@ k_hist(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t L, uint32_t* _
   uint32_t* gh = hist + (uint64_t)q * nb;
   for (uint32_t i = threadIdx.x; i < nb; i += 256)
     if (h[i]) atomicAdd(&gh[i], h[i]);
+  __syncthreads();   // h is cleared again for the next query
+}
+
+// Grid (blocks of SEL_CH sets, y): block y takes queries y, y + gridDim.y, ...
+__global__ void __launch_bounds__(256)
+k_hist(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t L, uint32_t n_q, uint32_t* __restrict__ hist,
+       const uint32_t* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
+  extern __shared__ uint32_t h[];
+  for (uint32_t q = blockIdx.y; q < n_q; q += gridDim.y) hist_query(scores, ld, L, hist, q, h);
 }
 
 // One block per query: tau = smallest score s with #{score <= s} >= Tq,
@@ -403,13 +419,11 @@ k_threshold(const uint32_t* __restrict__ hist, uint32_t L, uint32_t T, uint32_t*
   }
 }
 
-__global__ void __launch_bounds__(256)
-k_compact(const uint16_t* __restrict__ scores, uint64_t ld, const uint32_t* __restrict__ sel,
-          uint32_t* __restrict__ ctr, uint32_t* __restrict__ eqcnt, uint32_t nblk, uint64_t* __restrict__ cand,
-          uint32_t T, const uint32_t* __restrict__ run_if) {
-  if (run_if && *run_if == 0) return;
-  __shared__ uint32_t wsum[4];
-  const uint32_t q = blockIdx.y, blk = blockIdx.x, lane = lane_id();
+__device__ __forceinline__ void compact_query(const uint16_t* __restrict__ scores, uint64_t ld,
+                                              const uint32_t* __restrict__ sel, uint32_t* __restrict__ ctr,
+                                              uint32_t* __restrict__ eqcnt, uint32_t nblk,
+                                              uint64_t* __restrict__ cand, uint32_t T, uint32_t q, uint32_t* wsum) {
+  const uint32_t blk = blockIdx.x, lane = lane_id();
   const uint32_t tau = sel[(uint64_t)q * 4], Tq = sel[(uint64_t)q * 4 + 3];
   uint32_t eq = 0;
   if (Tq != 0) {
@@ -433,16 +447,24 @@ k_compact(const uint16_t* __restrict__ scores, uint64_t ld, const uint32_t* __re
   if (lane == 0) wsum[threadIdx.x / BVS_WAVE] = eq;
   __syncthreads();
   if (threadIdx.x == 0) eqcnt[(uint64_t)q * nblk + blk] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();   // wsum is rewritten for the next query
 }
 
 __global__ void __launch_bounds__(256)
-k_ties(const uint16_t* __restrict__ scores, uint64_t ld, const uint32_t* __restrict__ sel,
-       const uint32_t* __restrict__ eqcnt, uint32_t nblk, uint64_t* __restrict__ cand, uint32_t T,
-       const uint32_t* __restrict__ run_if) {
+k_compact(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t n_q, const uint32_t* __restrict__ sel,
+          uint32_t* __restrict__ ctr, uint32_t* __restrict__ eqcnt, uint32_t nblk, uint64_t* __restrict__ cand,
+          uint32_t T, const uint32_t* __restrict__ run_if) {
   if (run_if && *run_if == 0) return;
   __shared__ uint32_t wsum[4];
-  __shared__ uint32_t red[4];
-  const uint32_t q = blockIdx.y, blk = blockIdx.x;
+  for (uint32_t q = blockIdx.y; q < n_q; q += gridDim.y) compact_query(scores, ld, sel, ctr, eqcnt, nblk, cand, T, q, wsum);
+}
+
+// Every early return is uniform over the block.
+__device__ __forceinline__ void ties_query(const uint16_t* __restrict__ scores, uint64_t ld,
+                                           const uint32_t* __restrict__ sel, const uint32_t* __restrict__ eqcnt,
+                                           uint32_t nblk, uint64_t* __restrict__ cand, uint32_t T, uint32_t q,
+                                           uint32_t* wsum, uint32_t* red) {
+  const uint32_t blk = blockIdx.x;
   const uint32_t tau = sel[(uint64_t)q * 4], cb = sel[(uint64_t)q * 4 + 1], ne = sel[(uint64_t)q * 4 + 2];
   if (ne == 0) return;
   const uint32_t* ec = eqcnt + (uint64_t)q * nblk;
@@ -463,6 +485,19 @@ k_ties(const uint16_t* __restrict__ scores, uint64_t ld, const uint32_t* __restr
     const uint32_t r = block_excl_scan_flag(f, wsum, tot);
     if (f && prefix + r < ne) cand[(uint64_t)q * T + cb + prefix + r] = ((uint64_t)tau << 32) | (uint32_t)jj;
     prefix += tot;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_ties(const uint16_t* __restrict__ scores, uint64_t ld, uint32_t n_q, const uint32_t* __restrict__ sel,
+       const uint32_t* __restrict__ eqcnt, uint32_t nblk, uint64_t* __restrict__ cand, uint32_t T,
+       const uint32_t* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t red[4];
+  for (uint32_t q = blockIdx.y; q < n_q; q += gridDim.y) {
+    ties_query(scores, ld, sel, eqcnt, nblk, cand, T, q, wsum, red);
+    __syncthreads();   // red and wsum are rewritten for the next query
   }
 }
 
@@ -508,17 +543,20 @@ hipError_t launch_select(const uint16_t* scores, uint64_t ld, uint32_t L, uint32
                          const uint32_t* run_if, hipStream_t st) {
   if (n_q == 0) return hipSuccess;
   const uint32_t nblk = select_blocks(ld);
+  // a gated launch usually does nothing: few blocks, each looping over queries
+  const uint32_t gy = run_if ? std::min(n_q, kGatedRows) : n_q;
   hipError_t e = launch_fill_u32(b.hist, (uint64_t)n_q * (L + 2), 0, st, run_if);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_hist, dim3(nblk, n_q), dim3(256), (L + 2) * sizeof(uint32_t), st, scores, ld, L, b.hist,
+  hipLaunchKernelGGL(k_hist, dim3(nblk, gy), dim3(256), (L + 2) * sizeof(uint32_t), st, scores, ld, L, n_q, b.hist,
                      run_if);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_threshold, dim3(n_q), dim3(256), 0, st, b.hist, L, T, b.sel, b.ctr, run_if);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compact, dim3(nblk, n_q), dim3(256), 0, st, scores, ld, b.sel, b.ctr, b.eqcnt, nblk,
+  hipLaunchKernelGGL(k_compact, dim3(nblk, gy), dim3(256), 0, st, scores, ld, n_q, b.sel, b.ctr, b.eqcnt, nblk,
                      b.cand, T, run_if);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ties, dim3(nblk, n_q), dim3(256), 0, st, scores, ld, b.sel, b.eqcnt, nblk, b.cand, T, run_if);
+  hipLaunchKernelGGL(k_ties, dim3(nblk, gy), dim3(256), 0, st, scores, ld, n_q, b.sel, b.eqcnt, nblk, b.cand, T,
+                     run_if);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   uint32_t NP = 1;
   while (NP < T) NP <<= 1;
