@@ -20,6 +20,9 @@ text by eye:
              (Alg. 6 end to end, Def. 5)
   index      literal inverted index and max-heap forms (Def. 9, Alg. 4,
              and the heap of Alg. 6), used only to cross-check `filter`
+  lowp       the precision form of the re-rank: bfloat16 / OCP E4M3
+             quantisation, approximate Hausdorff values, and the exact
+             re-check of candidates within a margin of the k-th
 
 Parity status: every function is pinned by tests under tests/ (worked
 examples printed in the paper, closed forms, invariants, brute force on
@@ -27,4 +30,4 @@ tiny inputs).  `prng.projection_rows` follows a construction the paper
 leaves open (it only says W is random); it is pinned by a published
 splitmix64 test vector and by distribution invariants.
 """
-from . import prng, flyhash, sketch, filter, hausdorff, search, index  # noqa: F401
+from . import prng, flyhash, sketch, filter, hausdorff, search, index, lowp  # noqa: F401
