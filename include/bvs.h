@@ -289,6 +289,63 @@ bvs_status bvs_batch_get_info(const bvs_batch* b, bvs_batch_info* out);
 /* Frees the plan and its graph (not the caller's buffers). */
 void bvs_batch_destroy(bvs_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Precision form of the re-rank.  The exact re-rank reads two int8 planes
+ * per element and does four int8 matrix-core products per tile.  This form
+ * first ranks F2 by approximate Hausdorff values computed from a BF16 or an
+ * OCP FP8 E4M3 copy of the vectors (one matrix-core product per tile, FP32
+ * accumulation), then re-checks exactly (the exact re-rank, which equals a
+ * float64 evaluation) every candidate whose approximate distance is within
+ * a relative margin of the k-th approximate distance, and returns the
+ * first k of the re-checked candidates by exact distance.  Reported
+ * distances are therefore exact; a true neighbour is missed only if its
+ * approximate distance exceeds the k-th one by more than the margin.
+ *
+ * Encodings: BF16 = float32 rounded to nearest even to 16 bits; E4M3 = OCP
+ * 8-bit float (bias 7, 3 mantissa bits, largest 448), rounded to nearest
+ * even, with a float32 scale per set s = max|x| / 448 and components
+ * e4m3(clamp(x / s, +-448)).  Approximate squared distances use the exact
+ * norms: |x|^2 + |y|^2 - 2 s_x s_y (x~ . y~), clamped at 0.
+ */
+#define BVS_LOWP_BF16 1
+#define BVS_LOWP_FP8 2
+
+/* Device bytes of the fmt copy of the database: N rows of 2 dp (BF16) or dp
+ * rounded up to 128 (FP8) bytes, plus FP8 scales. */
+bvs_status bvs_lowp_bytes(const bvs_index* ix, int fmt, uint64_t* out_bytes);
+
+/* Builds the fmt copy from the index's exact planes into d_mem (caller
+ * owned, at least bvs_lowp_bytes) and attaches it to the index; the memory
+ * must outlive the index's use of that format.  Synchronises `stream`.
+ * Attaching again replaces the previous copy of that format. */
+bvs_status bvs_lowp_attach(bvs_index* ix, int fmt, void* d_mem, uint64_t bytes, void* stream);
+
+/* Workspace bytes for bvs_search_lowp and bvs_hausdorff_lowp. */
+bvs_status bvs_lowp_workspace_bytes(const bvs_index* ix, uint32_t n_q, uint64_t n_q_vectors,
+                                    uint64_t* out_bytes);
+
+/* Cascade search with the precision form of the re-rank: F2 as in
+ * bvs_search, approximate values in fmt, exact re-check of the candidates
+ * with approximate squared value <= v_k * f, f = float32(1 + margin)^2 in
+ * float32 arithmetic, v_k the k-th smallest approximate value (all of F2
+ * when |F2| < k), then the first k by (exact distance, id).  Outputs as
+ * for bvs_search; d_rechecked (uint32 [n_q], may be NULL) receives the
+ * number of re-checked candidates.  BVS_ESTATE if fmt is not attached;
+ * margin must be finite and >= 0. */
+bvs_status bvs_search_lowp(const bvs_index* ix, int fmt, float margin, const float* d_q,
+                           const uint64_t* h_q_offsets, uint32_t n_q, uint32_t k,
+                           void* d_workspace, uint64_t workspace_bytes,
+                           uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                           uint32_t* d_rechecked, void* stream);
+
+/* Approximate squared Hausdorff values in fmt of query q against the sets
+ * d_ids [n_q][m] (uint32), into d_h2 float32 [n_q][m]. */
+bvs_status bvs_hausdorff_lowp(const bvs_index* ix, int fmt, const float* d_q,
+                              const uint64_t* h_q_offsets, uint32_t n_q,
+                              const uint32_t* d_ids, uint32_t m,
+                              void* d_workspace, uint64_t workspace_bytes,
+                              float* d_h2, void* stream);
+
 /* Stage timing.  When enabled, the library records a pair of HIP events on
  * the call's stream around every stage it launches and, after the call's
  * final synchronisation, adds the elapsed time to a process-wide table.
@@ -298,7 +355,9 @@ void bvs_batch_destroy(bvs_batch* b);
  * appended candidates), 6 re-rank (exact Hausdorff of the candidates), 7
  * top-k, 8 brute force (Hausdorff to every set), 9 fallback (dense scores
  * and histogram selection, used when the sampled cutoff did not hold T
- * candidates or overflowed its buffer).
+ * candidates or overflowed its buffer), 10 approximate re-rank of the
+ * precision form (encoding of the queries, approximate values, selection
+ * of the candidates to re-check), 11 exact re-check of the precision form.
  * Work counters (summed over calls): 0 first-layer member pairs scored by
  * the filter stage, 1 database vectors read by the re-rank stage, 2 re-rank
  * candidates abandoned early, 3 re-rank candidates.
@@ -307,7 +366,7 @@ void bvs_batch_destroy(bvs_batch* b);
  * (their atomics slow the counted kernels somewhat), 0 turns both off. */
 #define BVS_PROFILE_TIMING 1
 #define BVS_PROFILE_COUNTERS 2
-#define BVS_N_STAGES 10
+#define BVS_N_STAGES 12
 #define BVS_N_COUNTERS 4
 typedef struct bvs_stage_times {
   double ms[BVS_N_STAGES];

@@ -121,10 +121,10 @@ def approx_hausdorff_sq(Q, V, fmt: str) -> float:
 
 
 def recheck_threshold(h2_kth: float, margin: float) -> np.float32:
-    """Squared-distance threshold of the re-check, in float32 as on the GPU:
+    """Squared-distance threshold of the re-check, every step in float32:
     distances within (1 + margin) of the k-th approximate distance."""
-    f = np.float32((1.0 + margin) * (1.0 + margin))
-    return np.float32(np.float32(h2_kth) * f)
+    f1 = np.float32(1.0) + np.float32(margin)
+    return np.float32(np.float32(h2_kth) * np.float32(f1 * f1))
 
 
 def search_lowp(index, Q, A: int, M: int, T: int, k: int, fmt: str, margin: float) -> dict:

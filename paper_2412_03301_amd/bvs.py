@@ -28,10 +28,12 @@ EXPORTED = [
     "bvs_bruteforce_workspace_bytes", "bvs_bruteforce", "bvs_hausdorff_all", "bvs_last_error",
     "bvs_version", "bvs_profile_enable", "bvs_profile_read", "bvs_stage_name",
     "bvs_batch_create", "bvs_batch_bind", "bvs_batch_launch", "bvs_batch_status", "bvs_batch_get_info",
-    "bvs_batch_destroy",
+    "bvs_batch_destroy", "bvs_lowp_bytes", "bvs_lowp_attach", "bvs_lowp_workspace_bytes", "bvs_search_lowp",
+    "bvs_hausdorff_lowp",
 ]
+LOWP = {"bf16": 1, "fp8": 2}
 TUNE_MAX = 16
-N_STAGES = 10
+N_STAGES = 12
 N_COUNTERS = 4
 COUNTER_NAMES = ("filter_pairs", "rerank_vectors", "rerank_abandoned", "rerank_candidates")
 
@@ -120,6 +122,11 @@ def lib():
             "bvs_batch_status": (C.c_int, [P, P]),
             "bvs_batch_get_info": (C.c_int, [P, P]),
             "bvs_batch_destroy": (None, [P]),
+            "bvs_lowp_bytes": (C.c_int, [P, C.c_int, PU64]),
+            "bvs_lowp_attach": (C.c_int, [P, C.c_int, P, U64, P]),
+            "bvs_lowp_workspace_bytes": (C.c_int, [P, U32, U64, PU64]),
+            "bvs_search_lowp": (C.c_int, [P, C.c_int, C.c_float, P, P, U32, U32, P, U64, P, P, P, P, P]),
+            "bvs_hausdorff_lowp": (C.c_int, [P, C.c_int, P, P, U32, P, U32, P, U64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -305,6 +312,46 @@ class Index:
         check(lib().bvs_search(self._h, _ptr(q), _u64p(off), n_q, k, _ptr(ws), ws.numel(), _ptr(ids),
                                _ptr(dist), _ptr(cnt), _stream(stream)))
         return ids, dist, cnt
+
+    # -- precision form
+    def attach_lowp(self, fmt: str, stream=None):
+        """Build and attach the BF16 ("bf16") or FP8 E4M3 ("fp8") copy of the vectors."""
+        f = LOWP[fmt]
+        nbytes = _bytes(lib().bvs_lowp_bytes, self._h, f)
+        mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        check(lib().bvs_lowp_attach(self._h, f, _ptr(mem), nbytes, _stream(stream)))
+        self.__dict__.setdefault("_lowp", {})[fmt] = mem
+        return nbytes
+
+    def lowp_workspace(self, n_q: int, n_q_vectors: int) -> torch.Tensor:
+        return _workspace(_bytes(lib().bvs_lowp_workspace_bytes, self._h, n_q, n_q_vectors), self.device)
+
+    def search_lowp(self, q, q_offsets, k: int, fmt: str, margin: float = 0.02, ws: torch.Tensor | None = None,
+                    out=None, stream=None):
+        """(ids, dist, count, rechecked) of the precision form."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        if ws is None:
+            ws = self.lowp_workspace(n_q, NQ)
+        if out is None:
+            out = (torch.empty(n_q, k, dtype=torch.int32, device=self.device),
+                   torch.empty(n_q, k, dtype=torch.float32, device=self.device),
+                   torch.empty(n_q, dtype=torch.int32, device=self.device),
+                   torch.empty(n_q, dtype=torch.int32, device=self.device))
+        ids, dist, cnt, rech = out
+        check(lib().bvs_search_lowp(self._h, LOWP[fmt], margin, _ptr(q), _u64p(off), n_q, k, _ptr(ws), ws.numel(),
+                                    _ptr(ids), _ptr(dist), _ptr(cnt), _ptr(rech), _stream(stream)))
+        return ids, dist, cnt, rech
+
+    def hausdorff_lowp(self, q, q_offsets, ids: torch.Tensor, fmt: str, stream=None) -> torch.Tensor:
+        """Approximate squared Hausdorff values float32 [n_q, m] against ids int32 [n_q, m]."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        ids = ids.to(torch.int32).contiguous()
+        m = ids.shape[1]
+        out = torch.empty(n_q, m, dtype=torch.float32, device=self.device)
+        ws = self.lowp_workspace(n_q, NQ)
+        check(lib().bvs_hausdorff_lowp(self._h, LOWP[fmt], _ptr(q), _u64p(off), n_q, _ptr(ids), m, _ptr(ws),
+                                       ws.numel(), _ptr(out), _stream(stream)))
+        return out
 
     def bruteforce(self, q, q_offsets, k: int, ws: torch.Tensor | None = None, out=None, stream=None):
         off, n_q, NQ = self._qargs(q, q_offsets)

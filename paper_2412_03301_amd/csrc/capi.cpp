@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdlib>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -166,8 +167,9 @@ bvs_status read_status(uint32_t* d_status, hipStream_t st, const char* what) {
 }
 
 // ------------------------------------------------------------------ stage timing
-const char* const kStageNames[BVS_N_STAGES] = {"convert", "encode", "query_sketch", "cutoff",     "filter",
-                                               "select",  "rerank", "topk",         "bruteforce", "fallback"};
+const char* const kStageNames[BVS_N_STAGES] = {"convert",  "encode",   "query_sketch", "cutoff",
+                                               "filter",   "select",   "rerank",       "topk",
+                                               "bruteforce", "fallback", "approx",     "recheck"};
 
 struct ProfTable {
   std::mutex mu;
@@ -259,7 +261,8 @@ hipError_t staged(CallProf& p, int stage, F&& f) {
   return e;
 }
 
-enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_CUTOFF, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE, S_FALLBACK };
+enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_CUTOFF, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE, S_FALLBACK,
+       S_APPROX, S_RECHECK };
 
 }  // namespace
 
@@ -277,6 +280,9 @@ struct bvs_index {
   uint8_t* cnt;
   uint64_t* bits;
   uint64_t* planes;   // [L][ld/64]: bit j of plane p set when C^(j)[p] >= 1
+  // attached precision copies, by format (BVS_LOWP_BF16, BVS_LOWP_FP8)
+  uint8_t* lowp[3] = {nullptr, nullptr, nullptr};
+  float* lowp_scale[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -1282,6 +1288,173 @@ void bvs_batch_destroy(bvs_batch* b) {
   if (!b) return;
   batch_release(b);
   delete b;
+}
+
+}  // extern "C"
+
+// ====================================================================== precision form
+namespace {
+
+struct LowpWs {
+  QueryWs w;
+  uint8_t* q_rows;      // [NQ][2 dp]
+  float* q_scale;       // [n_q]
+  uint32_t* approx;     // [n_q][T] float bits
+  uint32_t* r_ids;      // [n_q][T]
+  uint32_t* r_count;    // [n_q]
+};
+
+void layout_lowp(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, LowpWs* l) {
+  layout_search(c, ix, n_q, NQ, &l->w);
+  l->q_rows = c.take<uint8_t>(NQ * 2 * ix->g.dp);
+  l->q_scale = c.take<float>(n_q);
+  l->approx = c.take<uint32_t>((uint64_t)n_q * ix->g.T);
+  l->r_ids = c.take<uint32_t>((uint64_t)n_q * ix->g.T);
+  l->r_count = c.take<uint32_t>(n_q);
+}
+
+bool lowp_fmt_ok(int fmt) { return fmt == BVS_LOWP_BF16 || fmt == BVS_LOWP_FP8; }
+
+LowpDb lowp_db(const bvs_index* ix, int fmt) {
+  LowpDb d;
+  d.rows = ix->lowp[fmt];
+  d.scale = fmt == BVS_LOWP_FP8 ? ix->lowp_scale[fmt] : nullptr;
+  d.norms = ix->norms;
+  d.offsets = ix->offsets;
+  d.n_sets = ix->n;
+  d.row_bytes = lowp_row_bytes(fmt, ix->g.dp);
+  return d;
+}
+
+// Encode the converted query planes of the workspace in fmt.
+bvs_status lowp_queries(const bvs_index* ix, int fmt, uint32_t n_q, uint32_t max_rows, LowpWs& l, hipStream_t st,
+                        LowpQ* q) {
+  const uint32_t rb = lowp_row_bytes(fmt, ix->g.dp);
+  HIP_TRY(launch_lowp_encode(l.w.qhi, l.w.qlo, ix->g.dp, l.w.qoff, n_q, fmt, rb, l.q_rows, l.q_scale, st));
+  q->rows = l.q_rows;
+  q->scale = fmt == BVS_LOWP_FP8 ? l.q_scale : nullptr;
+  q->norms = l.w.qnorm;
+  q->offsets = l.w.qoff;
+  q->n_q = n_q;
+  q->max_rows = max_rows;
+  q->row_bytes = rb;
+  return BVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bvs_status bvs_lowp_bytes(const bvs_index* ix, int fmt, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  if (!lowp_fmt_ok(fmt)) return fail(BVS_EINVAL, "unknown precision format %d", fmt);
+  Carver c(nullptr);
+  c.take<uint8_t>(ix->N * lowp_row_bytes(fmt, ix->g.dp));
+  if (fmt == BVS_LOWP_FP8) c.take<float>(ix->n);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_lowp_attach(bvs_index* ix, int fmt, void* d_mem, uint64_t bytes, void* stream) {
+  uint64_t need = 0;
+  BVS_TRY(bvs_lowp_bytes(ix, fmt, &need));
+  if (!d_mem) return fail(BVS_EINVAL, "memory is NULL");
+  if (bytes < need) return fail(BVS_ENOSPC, "%llu bytes given, %llu needed", (unsigned long long)bytes,
+                                (unsigned long long)need);
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_mem);
+  const uint32_t rb = lowp_row_bytes(fmt, ix->g.dp);
+  uint8_t* rows = c.take<uint8_t>(ix->N * rb);
+  float* scale = fmt == BVS_LOWP_FP8 ? c.take<float>(ix->n) : nullptr;
+  HIP_TRY(launch_lowp_encode(ix->hi, ix->lo, ix->g.dp, ix->offsets, ix->n, fmt, rb, rows, scale, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  ix->lowp[fmt] = rows;
+  ix->lowp_scale[fmt] = scale;
+  return BVS_OK;
+}
+
+bvs_status bvs_lowp_workspace_bytes(const bvs_index* ix, uint32_t n_q, uint64_t n_q_vectors, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  Carver c(nullptr);
+  LowpWs l;
+  layout_lowp(c, ix, n_q, n_q_vectors, &l);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_search_lowp(const bvs_index* ix, int fmt, float margin, const float* d_q, const uint64_t* h_q_off,
+                           uint32_t n_q, uint32_t k, void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist,
+                           uint32_t* d_count, uint32_t* d_rechecked, void* stream) {
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  if (!lowp_fmt_ok(fmt)) return fail(BVS_EINVAL, "unknown precision format %d", fmt);
+  if (!ix->lowp[fmt]) return fail(BVS_ESTATE, "precision format %d is not attached", fmt);
+  if (!(margin >= 0.0f) || !std::isfinite(margin)) return fail(BVS_EINVAL, "margin must be finite and >= 0");
+  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
+  if (k < 1 || k > kMaxK || k > ix->g.T) return fail(BVS_EINVAL, "k %u outside 1..min(64, top_t)", k);
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_lowp_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  LowpWs l;
+  layout_lowp(c, ix, n_q, NQ, &l);
+  QueryWs& w = l.w;
+  const uint32_t T = ix->g.T;
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
+  BVS_TRY(run_filters(ix, n_q, NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof));
+  const float f1 = 1.0f + margin;
+  const float factor = f1 * f1;
+  LowpQ lq;
+  bvs_status ls = BVS_OK;
+  HIP_TRY(staged(prof, S_APPROX, [&]() -> hipError_t {
+    ls = lowp_queries(ix, fmt, n_q, max_rows, l, st, &lq);
+    if (ls != BVS_OK) return hipSuccess;
+    hipError_t e = launch_haus_lowp(fmt, lowp_db(ix, fmt), lq, w.f2_ids, w.f2_count, T, T, l.approx, st);
+    if (e != hipSuccess) return e;
+    return launch_lowp_select(l.approx, w.f2_ids, w.f2_count, T, n_q, k, factor, l.r_ids, l.r_count, st);
+  }));
+  BVS_TRY(ls);
+  HIP_TRY(staged(prof, S_RECHECK, [&]() -> hipError_t {
+    hipError_t e = launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), l.r_ids, l.r_count, T, k, w.thr, w.h2,
+                                    prof.count ? w.stats : nullptr, st);
+    if (e != hipSuccess) return e;
+    return launch_topk(w.h2, l.r_ids, l.r_count, T, T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
+  }));
+  if (d_rechecked)
+    HIP_TRY(hipMemcpyAsync(d_rechecked, l.r_count, (uint64_t)n_q * 4, hipMemcpyDeviceToDevice, st));
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish(prof.count ? w.stats : nullptr);
+  return s;
+}
+
+bvs_status bvs_hausdorff_lowp(const bvs_index* ix, int fmt, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                              const uint32_t* d_ids, uint32_t m, void* d_ws, uint64_t ws_bytes, float* d_h2,
+                              void* stream) {
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  if (!lowp_fmt_ok(fmt)) return fail(BVS_EINVAL, "unknown precision format %d", fmt);
+  if (!ix->lowp[fmt]) return fail(BVS_ESTATE, "precision format %d is not attached", fmt);
+  if (!d_ids || !d_h2) return fail(BVS_EINVAL, "NULL argument");
+  if (m == 0) return BVS_OK;
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_lowp_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  LowpWs l;
+  layout_lowp(c, ix, n_q, NQ, &l);
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, l.w, st, prof));
+  LowpQ lq;
+  BVS_TRY(lowp_queries(ix, fmt, n_q, max_rows, l, st, &lq));
+  HIP_TRY(launch_haus_lowp(fmt, lowp_db(ix, fmt), lq, d_ids, nullptr, m, m, (uint32_t*)d_h2, st));
+  const bvs_status s = read_status(l.w.status, st, "queries");
+  prof.finish();
+  return s;
 }
 
 }  // extern "C"

@@ -1,6 +1,8 @@
 // Host-side launchers of the gfx950 kernels (internal to the library).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "bvs.h"
 #include <stdint.h>
 
 namespace bvs {
@@ -151,6 +153,28 @@ hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_
                        uint64_t* tmp, uint32_t* ids, float* dist, uint32_t* count,
                        hipStream_t st);
 uint64_t topk_tmp_words(uint64_t n_items, uint32_t n_q, uint32_t k);
+
+// Precision form (BVS_LOWP_BF16 / BVS_LOWP_FP8 copies of the vectors).
+struct LowpDb {
+  const uint8_t* rows; const float* scale; const uint32_t* norms; const uint64_t* offsets;
+  uint64_t n_sets; uint32_t row_bytes;
+};
+struct LowpQ {
+  const uint8_t* rows; const float* scale; const uint32_t* norms; const uint64_t* offsets;
+  uint32_t n_q, max_rows, row_bytes;
+};
+uint32_t lowp_row_bytes(int fmt, uint32_t dp);
+// Encode the sets [offsets] of the int8 planes into fmt rows (and FP8 scales).
+hipError_t launch_lowp_encode(const int8_t* hi, const uint8_t* lo, uint32_t dp, const uint64_t* offsets,
+                              uint64_t n_sets, int fmt, uint32_t row_bytes, uint8_t* out, float* scale,
+                              hipStream_t st);
+// Approximate squared Hausdorff values (float bits) of ids[q][0 .. min(count[q], lim)).
+hipError_t launch_haus_lowp(int fmt, const LowpDb& db, const LowpQ& q, const uint32_t* ids, const uint32_t* count,
+                            uint32_t stride, uint32_t lim, uint32_t* out, hipStream_t st);
+// Candidates to re-check: the prefix of (value, id) order within factor of the k-th value.
+hipError_t launch_lowp_select(const uint32_t* approx, const uint32_t* ids, const uint32_t* count, uint32_t T,
+                              uint32_t n_q, uint32_t k, float factor, uint32_t* r_ids, uint32_t* r_count,
+                              hipStream_t st);
 
 // Fill a u32 buffer (used instead of hipMemsetAsync so work stays graph-safe).
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st,
