@@ -148,50 +148,63 @@ struct LpView {
 
 constexpr float kInv2p24 = 1.0f / 16777216.0f;
 
-// Approximate squared Hausdorff value of set [o0, o0 + m) (scale sv), as
-// float bits (non-negative, so they order like the values).
-template <int FMT, int KC, int MAXQT, bool HASG>
-__device__ __forceinline__ uint32_t lp_item(const LowpDb& db, uint64_t o0, uint32_t m, float sv, const LpView& q) {
+// Approximate squared Hausdorff values of NS sets at once (float bits;
+// non-negative, so they order like the values).  Set s is [o0[s], o0[s] +
+// m[s]) with scale sv[s]; m[s] = 0 marks an absent set.  With NS = 2 every
+// query tile read from LDS feeds both sets' matrix products, which halves
+// the LDS traffic per product.
+template <int FMT, int KC, int MAXQT, bool HASG, int NS>
+__device__ __forceinline__ void lp_items(const LowpDb& db, const uint64_t (&o0)[NS], const uint32_t (&m)[NS],
+                                         const float (&sv)[NS], const LpView& q, uint32_t (&res)[NS]) {
   using Op = LpOp<FMT>;
   constexpr uint32_t LB = Op::LB;
   const uint32_t lane = lane_id();
   const uint32_t g = lane >> 4, c16 = lane & 15;
   const uint32_t RB = db.row_bytes;
   const uint32_t SS = RB + 16;
-  const float svq = sv * q.q_scale;
-  uint32_t qmin[MAXQT];
+  uint32_t mmax = 0;
+  float svq[NS];
+  uint32_t qmin[NS][MAXQT], colmax[NS];
 #pragma unroll
-  for (int i = 0; i < MAXQT; ++i) qmin[i] = 0xFFFFFFFFu;
-  uint32_t colmax = 0;
-  for (uint32_t vt = 0; vt < m; vt += 16) {
-    const uint32_t vrow = vt + c16;
-    const bool vrow_ok = vrow < m;
-    typename Op::T a[KC];
-    {
-      const uint8_t* pa = db.rows + (o0 + (vrow_ok ? vrow : 0)) * RB + LB * g;
+  for (int s = 0; s < NS; ++s) {
+    mmax = max(mmax, m[s]);
+    svq[s] = sv[s] * q.q_scale;
+    colmax[s] = 0;
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc) a[kc] = vrow_ok ? Op::load_nt(pa + 4 * LB * kc) : Op::zero();
-    }
-    float nv[4];
-    uint32_t vmin[4];
-    bool vok[4];
+    for (int i = 0; i < MAXQT; ++i) qmin[s][i] = 0xFFFFFFFFu;
+  }
+  for (uint32_t vt = 0; vt < mmax; vt += 16) {
+    typename Op::T a[NS][KC];
+    float nv[NS][4];
+    uint32_t vmin[NS][4];
+    bool vok[NS][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t v = vt + 4 * g + r;
-      vok[r] = v < m;
-      nv[r] = vok[r] ? (float)db.norms[o0 + v] * kInv2p24 : 0.0f;
-      vmin[r] = 0xFFFFFFFFu;
+    for (int s = 0; s < NS; ++s) {
+      const uint32_t vrow = vt + c16;
+      const bool vrow_ok = vrow < m[s];
+      const uint8_t* pa = db.rows + (o0[s] + (vrow_ok ? vrow : 0)) * RB + LB * g;
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) a[s][kc] = vrow_ok ? Op::load_nt(pa + 4 * LB * kc) : Op::zero();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t v = vt + 4 * g + r;
+        vok[s][r] = v < m[s];
+        nv[s][r] = vok[s][r] ? (float)db.norms[o0[s] + v] * kInv2p24 : 0.0f;
+        vmin[s][r] = 0xFFFFFFFFu;
+      }
     }
 #pragma unroll
     for (int qt = 0; qt < MAXQT; ++qt) {
       if ((uint32_t)qt < q.nqt) {
-        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        // two accumulation chains per set keep the matrix pipe busy
+        v4f acc[NS][2];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s][0] = acc[s][1] = v4f{0.f, 0.f, 0.f, 0.f};
         const uint32_t qi = qt * 16 + c16;
+        const uint8_t* pb;
         float nq;
         if (!HASG || (uint32_t)qt < q.nqt_s) {
-          const uint8_t* pb = q.s_rows + qi * SS + LB * g;
-#pragma unroll
-          for (int kc = 0; kc < KC; ++kc) acc = Op::mfma(a[kc], Op::load(pb + 4 * LB * kc), acc);
+          pb = q.s_rows + qi * SS + LB * g;
           nq = (float)q.s_norm[qi] * kInv2p24;
         } else {
           asm volatile("" ::: "memory");
@@ -199,38 +212,52 @@ __device__ __forceinline__ uint32_t lp_item(const LowpDb& db, uint64_t o0, uint3
           uint32_t cl = c16;
           asm volatile("" : "+s"(gb), "+v"(cl));
           const uint32_t r = min(qt * 16 + cl, q.mq - 1);
-          const uint8_t* pb = gb + r * RB + LB * g;
-#pragma unroll
-          for (int kc = 0; kc < KC; ++kc) acc = Op::mfma(a[kc], Op::load(pb + 4 * LB * kc), acc);
+          pb = gb + r * RB + LB * g;
           nq = (float)q.g_norm[r] * kInv2p24;
+        }
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          const typename Op::T b = Op::load(pb + 4 * LB * kc);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) acc[s][kc & 1] = Op::mfma(a[s][kc], b, acc[s][kc & 1]);
         }
         const bool qok = qi < q.mq;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float d2 = fmaxf(nv[r] + nq - 2.0f * svq * acc[r], 0.0f);
-          const uint32_t bits = (qok && vok[r]) ? __float_as_uint(d2) : 0xFFFFFFFFu;
-          vmin[r] = min(vmin[r], bits);
-          qmin[qt] = min(qmin[qt], bits);
+        for (int s = 0; s < NS; ++s) {
+          const v4f d = acc[s][0] + acc[s][1];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float d2 = fmaxf(nv[s][r] + nq - 2.0f * svq[s] * d[r], 0.0f);
+            const uint32_t bits = (qok && vok[s][r]) ? __float_as_uint(d2) : 0xFFFFFFFFu;
+            vmin[s][r] = min(vmin[s][r], bits);
+            qmin[s][qt] = min(qmin[s][qt], bits);
+          }
         }
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t cm = row16_min_u32(vmin[r]);
-      if (vok[r]) colmax = max(colmax, cm);
-    }
-  }
-  uint32_t rowmax = 0;
+    for (int s = 0; s < NS; ++s) {
 #pragma unroll
-  for (int qt = 0; qt < MAXQT; ++qt) {
-    if ((uint32_t)qt < q.nqt) {
-      uint32_t rm = qmin[qt];
-      rm = min(rm, shfl_xor_u32(rm, 16));
-      rm = min(rm, shfl_xor_u32(rm, 32));
-      if ((uint32_t)qt * 16 + c16 < q.mq) rowmax = max(rowmax, rm);
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t cm = row16_min_u32(vmin[s][r]);
+        if (vok[s][r]) colmax[s] = max(colmax[s], cm);
+      }
     }
   }
-  return wave_max_u32(max(colmax, rowmax));
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    uint32_t rowmax = 0;
+#pragma unroll
+    for (int qt = 0; qt < MAXQT; ++qt) {
+      if ((uint32_t)qt < q.nqt) {
+        uint32_t rm = qmin[s][qt];
+        rm = min(rm, shfl_xor_u32(rm, 16));
+        rm = min(rm, shfl_xor_u32(rm, 32));
+        if ((uint32_t)qt * 16 + c16 < q.mq) rowmax = max(rowmax, rm);
+      }
+    }
+    res[s] = wave_max_u32(max(colmax[s], rowmax));
+  }
 }
 
 __device__ __forceinline__ LpView lp_stage(const LowpQ& qs, uint32_t q, uint32_t lds_rows, uint8_t* smem) {
@@ -265,10 +292,17 @@ static constexpr uint32_t kLpPerBlock = 64;
 // Grid (ceil(lim / 64), n_q): candidates ids[q][0 .. min(count[q], lim))
 // (count may be null: lim for every query), results as float bits in
 // out[q][i] (stride `stride`).
+// Sets per wave: two where both sets' register tiles fit comfortably.
+template <int FMT, int KC>
+constexpr int lp_sets_per_wave() {
+  return 1;   // two sets per wave measured slower (occupancy falls to 2 waves per SIMD)
+}
+
 template <int FMT, int KC, int MAXQT, bool HASG>
 __global__ void __launch_bounds__(64 * kLpWaves)
 k_haus_lp(LowpDb db, LowpQ qs, uint32_t lds_rows, const uint32_t* __restrict__ ids,
           const uint32_t* __restrict__ count, uint32_t stride, uint32_t lim, uint32_t* __restrict__ out) {
+  constexpr int NS = lp_sets_per_wave<FMT, KC>();
   extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t q = blockIdx.y;
   const uint32_t i1 = count ? min(count[q], lim) : lim;
@@ -276,13 +310,24 @@ k_haus_lp(LowpDb db, LowpQ qs, uint32_t lds_rows, const uint32_t* __restrict__ i
   if (b0 >= i1) return;
   const uint32_t b1 = min(i1, b0 + kLpPerBlock);
   const LpView qv = lp_stage(qs, q, lds_rows, smem);
-  for (uint32_t it = b0 + wave_id(); it < b1; it += kLpWaves) {
-    const uint32_t j = ids[(uint64_t)q * stride + it];
-    const uint64_t o0 = db.offsets[j];
-    const uint32_t m = (uint32_t)(db.offsets[j + 1] - o0);
-    const float sv = db.scale ? db.scale[j] : 1.0f;
-    const uint32_t h = lp_item<FMT, KC, MAXQT, HASG>(db, o0, m, sv, qv);
-    if (lane_id() == 0) out[(uint64_t)q * stride + it] = h;
+  for (uint32_t it = b0 + NS * wave_id(); it < b1; it += NS * kLpWaves) {
+    uint64_t o0[NS];
+    uint32_t m[NS], res[NS];
+    float sv[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const bool here = it + s < b1;
+      const uint32_t j = here ? ids[(uint64_t)q * stride + it + s] : 0u;
+      o0[s] = db.offsets[j];
+      m[s] = here ? (uint32_t)(db.offsets[j + 1] - o0[s]) : 0u;
+      sv[s] = db.scale ? db.scale[j] : 1.0f;
+    }
+    lp_items<FMT, KC, MAXQT, HASG, NS>(db, o0, m, sv, qv, res);
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (it + s < b1) out[(uint64_t)q * stride + it + s] = res[s];
+    }
   }
 }
 

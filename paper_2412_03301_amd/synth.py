@@ -87,14 +87,41 @@ def make_database(n_sets: int, size_lo: int, size_hi: int, dim: int,
         out = torch.empty(total, dim, dtype=torch.float32, device=device)
     for c0 in range(0, n_sets, CHUNK_SETS):
         c1 = min(n_sets, c0 + CHUNK_SETS)
-        g = _gen(device, seed, 4, c0 // CHUNK_SETS)
-        m = torch.from_numpy(sizes[c0:c1]).to(device)
-        t = torch.from_numpy(topic[c0:c1]).to(device)
-        ent = centres[t] + 0.5 * torch.randn(c1 - c0, dim, generator=g, device=device)
-        owner = torch.repeat_interleave(torch.arange(c1 - c0, device=device), m)
-        v = ent[owner] + 0.2 * torch.randn(owner.numel(), dim, generator=g, device=device)
-        out[offsets[c0]:offsets[c1]] = to_grid(v)
+        out[offsets[c0]:offsets[c1]] = _draw_chunk(c0, c1, sizes, topic, centres, dim, seed, device)
     return Database(out, offsets, topic, seed)
+
+
+def _draw_chunk(c0, c1, sizes, topic, centres, dim, seed, device):
+    g = _gen(device, seed, 4, c0 // CHUNK_SETS)
+    m = torch.from_numpy(sizes[c0:c1]).to(device)
+    t = torch.from_numpy(topic[c0:c1]).to(device)
+    ent = centres[t] + 0.5 * torch.randn(c1 - c0, dim, generator=g, device=device)
+    owner = torch.repeat_interleave(torch.arange(c1 - c0, device=device), m)
+    v = ent[owner] + 0.2 * torch.randn(owner.numel(), dim, generator=g, device=device)
+    return to_grid(v)
+
+
+def redraw_sets(n_sets: int, size_lo: int, size_hi: int, dim: int, n_topics: int, set_ids,
+                seed: int = 0, device="cpu") -> dict:
+    """The vectors of the given sets of make_database(...) with the same
+    arguments and device type, drawn again chunk by chunk (float32, host)."""
+    device = torch.device(device)
+    sizes = set_sizes(n_sets, size_lo, size_hi, seed)
+    offsets = np.zeros(n_sets + 1, np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    topic = torch.randint(0, n_topics, (n_sets,), generator=_gen("cpu", seed, 2)).numpy()
+    centres = torch.randn(n_topics, dim, generator=_gen(device, seed, 3), device=device)
+    out = {}
+    by_chunk = {}
+    for j in sorted(set(int(x) for x in set_ids)):
+        by_chunk.setdefault(j // CHUNK_SETS, []).append(j)
+    for ch, js in by_chunk.items():
+        c0 = ch * CHUNK_SETS
+        c1 = min(n_sets, c0 + CHUNK_SETS)
+        v = _draw_chunk(c0, c1, sizes, topic, centres, dim, seed, device)
+        for j in js:
+            out[j] = v[offsets[j] - offsets[c0]:offsets[j + 1] - offsets[c0]].cpu().numpy()
+    return out
 
 
 def make_subset_queries(db: Database, n_queries: int, seed: int = 0,
@@ -156,6 +183,9 @@ WORKLOADS = {
                  code_bits=1024, fan_in=8, wta_k=32, n_queries=16, top_t=200, k=10),
     "scale": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
                   code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10),
+    # the scale generator at d = 768, for the BF16 / FP8 re-rank
+    "precision": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=768, n_topics=10_000,
+                      code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10),
     # the scale database, searched by fresh-entity queries of 1-256 vectors
     "batched": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
                     code_bits=4096, fan_in=16, wta_k=64, n_queries=4096, max_query=256, top_t=1000, k=10),
