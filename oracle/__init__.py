@@ -23,6 +23,9 @@ text by eye:
   lowp       the precision form of the re-rank: bfloat16 / OCP E4M3
              quantisation, approximate Hausdorff values, and the exact
              re-check of candidates within a margin of the k-th
+  learned    the learned projection (two-layer network before the
+             winner-take-all) and its triplet training objective with
+             gradients
 
 Parity status: every function is pinned by tests under tests/ (worked
 examples printed in the paper, closed forms, invariants, brute force on
@@ -30,4 +33,4 @@ tiny inputs).  `prng.projection_rows` follows a construction the paper
 leaves open (it only says W is random); it is pinned by a published
 splitmix64 test vector and by distribution invariants.
 """
-from . import prng, flyhash, sketch, filter, hausdorff, search, index, lowp  # noqa: F401
+from . import prng, flyhash, sketch, filter, hausdorff, search, index, lowp, learned  # noqa: F401
