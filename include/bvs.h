@@ -346,6 +346,81 @@ bvs_status bvs_hausdorff_lowp(const bvs_index* ix, int fmt, const float* d_q,
                               void* d_workspace, uint64_t workspace_bytes,
                               float* d_h2, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned projection.  The paper hashes with a learned projection before
+ * the winner-take-all (Sec. 4.1; it does not specify the network or its
+ * training).  Here the projection W of Def. 7 is replaced by a two-layer
+ * network y = W2 relu(W1 x + b1) + b2 (dim -> hidden -> code_bits), and the
+ * code of x keeps the wta_k largest bfloat16(y), ties to the lower index.
+ * Inference runs on the matrix cores with bfloat16 operands (x, W1,
+ * relu(...), W2) and float32 accumulation.  Everything after the codes
+ * (sketches, filters, re-rank, the batched and precision forms) is
+ * unchanged.
+ *
+ * Weights are float32, packed: W1 [hidden][dim], b1 [hidden],
+ * W2 [code_bits][hidden], b2 [code_bits] (bvs_mlp_weight_count floats).
+ * Requirements: dim % 8 == 0, hidden % 8 == 0 (<= 8192), code_bits a power
+ * of two in 256..4096 (BVS_ENOTSUP otherwise).
+ *
+ * Training (bvs_train_projection): triplets (q, p, n) of set ids into the
+ * training collection (sets given like database sets, up to 65535 vectors
+ * each): a query set q, a set p among the exact nearest of q by Hausdorff
+ * distance, and another set n.  Objective: soft codes c = sigmoid((y - t) /
+ * tau), t the midpoint of the wta_k-th and (wta_k+1)-th largest y of the row
+ * (held constant); soft sketches S = 1 - prod over the set's rows of (1 - c)
+ * (the OR of Def. 10); soft Hamming h(A, B) = sum S_A + S_B - 2 S_A S_B; loss
+ * = mean over triplets of max(0, margin + h(q, p) - h(q, n)).  Adam (beta1
+ * 0.9, beta2 0.999, eps 1e-8) on the float32 weights, batches of
+ * batch_triplets triplets in a splitmix64(seed) shuffle per epoch.
+ */
+typedef struct bvs_train_config {
+  uint32_t dim, hidden, code_bits, wta_k;
+  uint32_t batch_triplets, epochs;
+  float lr, tau, margin;
+  uint32_t reserved;       /* 0 */
+  uint64_t seed;
+} bvs_train_config;
+
+bvs_status bvs_mlp_weight_count(uint32_t dim, uint32_t hidden, uint32_t code_bits, uint64_t* out_floats);
+
+/* Uniform initialisation in +-sqrt(6 / fan_in), biases 0, from splitmix64 of
+ * (seed, parameter index).  Synchronises `stream`. */
+bvs_status bvs_mlp_init(uint32_t dim, uint32_t hidden, uint32_t code_bits, uint64_t seed, float* d_weights,
+                        void* stream);
+
+/* Index and build-workspace bytes of an index with a learned projection. */
+bvs_status bvs_learned_index_bytes(const bvs_params* p, uint32_t hidden, uint64_t n_sets, uint64_t n_vectors,
+                                   uint64_t* out_bytes);
+bvs_status bvs_learned_build_workspace_bytes(const bvs_params* p, uint32_t hidden, uint64_t n_sets,
+                                             uint64_t n_vectors, uint64_t* out_bytes);
+
+/* As bvs_build_index, with the codes of the network d_weights (copied into
+ * the index as bfloat16; p->fan_in and p->seed are not used).  Queries of
+ * every search call are then encoded with the same network. */
+bvs_status bvs_build_index_learned(const bvs_params* p, uint32_t hidden, const float* d_weights,
+                                   const float* d_vectors, const uint64_t* h_offsets, uint64_t n_sets,
+                                   void* d_index_mem, uint64_t index_bytes, void* d_workspace,
+                                   uint64_t workspace_bytes, void* stream, bvs_index** out);
+
+/* Training workspace for batches of up to max_batch_rows vectors (the rows
+ * of the distinct sets of a batch). */
+bvs_status bvs_train_workspace_bytes(const bvs_train_config* c, uint64_t max_batch_rows, uint64_t* out_bytes);
+
+/* Loss and gradients (packed like the weights, into d_grads) of one batch
+ * of n_triplets <= batch_triplets triplets (h_triplets uint32 [n][3]). */
+bvs_status bvs_train_gradients(const bvs_train_config* c, const float* d_vectors, const uint64_t* h_offsets,
+                               uint64_t n_sets, const uint32_t* h_triplets, uint32_t n_triplets,
+                               const float* d_weights, float* d_grads, float* h_loss,
+                               void* d_workspace, uint64_t workspace_bytes, void* stream);
+
+/* Trains d_weights in place for c->epochs epochs; h_epoch_loss (may be
+ * NULL) receives the mean batch loss of each epoch.  BVS_ENOSPC when a
+ * batch has more rows than the workspace holds. */
+bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vectors, const uint64_t* h_offsets,
+                                uint64_t n_sets, const uint32_t* h_triplets, uint64_t n_triplets,
+                                float* d_weights, void* d_workspace, uint64_t workspace_bytes,
+                                float* h_epoch_loss, void* stream);
+
 /* Stage timing.  When enabled, the library records a pair of HIP events on
  * the call's stream around every stage it launches and, after the call's
  * final synchronisation, adds the elapsed time to a process-wide table.

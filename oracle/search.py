@@ -60,7 +60,20 @@ def rank_by_distance(ids: np.ndarray, h2: np.ndarray, k: int):
 def search(index: Index, Q, A: int, M: int, T: int, k: int) -> dict:
     """One query set Q [m_q, d]; returns every intermediate of Alg. 6."""
     Q = np.asarray(Q, dtype=np.float64)
-    HQ = codes(Q, index.idx, index.wta_k)
+    return search_codes(index, Q, codes(Q, index.idx, index.wta_k), A, M, T, k)
+
+
+def index_from_codes(X, offsets, H, wta_k: int) -> Index:
+    """An index whose codes come from elsewhere (the learned projection)."""
+    X = np.asarray(X, dtype=np.float64)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    H = np.asarray(H, dtype=bool)
+    return Index(X, offsets, np.zeros((0, 0), np.int64), wta_k, H, count_bloom(H, offsets), binary_bloom(H, offsets))
+
+
+def search_codes(index: Index, Q, HQ, A: int, M: int, T: int, k: int) -> dict:
+    """Alg. 6 for query Q with query codes HQ given."""
+    Q = np.asarray(Q, dtype=np.float64)
     C_Q, S_Q = flt.query_sketches(HQ)
     P = flt.top_positions(C_Q, A)
     member = flt.first_filter(index.C, P, M)

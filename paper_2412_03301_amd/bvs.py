@@ -29,7 +29,9 @@ EXPORTED = [
     "bvs_version", "bvs_profile_enable", "bvs_profile_read", "bvs_stage_name",
     "bvs_batch_create", "bvs_batch_bind", "bvs_batch_launch", "bvs_batch_status", "bvs_batch_get_info",
     "bvs_batch_destroy", "bvs_lowp_bytes", "bvs_lowp_attach", "bvs_lowp_workspace_bytes", "bvs_search_lowp",
-    "bvs_hausdorff_lowp",
+    "bvs_hausdorff_lowp", "bvs_mlp_weight_count", "bvs_mlp_init", "bvs_learned_index_bytes",
+    "bvs_learned_build_workspace_bytes", "bvs_build_index_learned", "bvs_train_workspace_bytes",
+    "bvs_train_gradients", "bvs_train_projection",
 ]
 LOWP = {"bf16": 1, "fp8": 2}
 TUNE_MAX = 16
@@ -69,6 +71,12 @@ class BatchInfo(C.Structure):
                 ("blocks", C.c_uint32), ("from_cache", C.c_uint32), ("graph", C.c_uint32),
                 ("n_tried", C.c_uint32), ("tried_lds_rows", C.c_uint32 * TUNE_MAX),
                 ("tried_waves", C.c_uint32 * TUNE_MAX), ("tried_ms", C.c_float * TUNE_MAX)]
+
+
+class TrainConfig(C.Structure):
+    _fields_ = [("dim", C.c_uint32), ("hidden", C.c_uint32), ("code_bits", C.c_uint32), ("wta_k", C.c_uint32),
+                ("batch_triplets", C.c_uint32), ("epochs", C.c_uint32), ("lr", C.c_float), ("tau", C.c_float),
+                ("margin", C.c_float), ("reserved", C.c_uint32), ("seed", C.c_uint64)]
 
 
 class BvsError(RuntimeError):
@@ -127,6 +135,14 @@ def lib():
             "bvs_lowp_workspace_bytes": (C.c_int, [P, U32, U64, PU64]),
             "bvs_search_lowp": (C.c_int, [P, C.c_int, C.c_float, P, P, U32, U32, P, U64, P, P, P, P, P]),
             "bvs_hausdorff_lowp": (C.c_int, [P, C.c_int, P, P, U32, P, U32, P, U64, P, P]),
+            "bvs_mlp_weight_count": (C.c_int, [U32, U32, U32, PU64]),
+            "bvs_mlp_init": (C.c_int, [U32, U32, U32, U64, P, P]),
+            "bvs_learned_index_bytes": (C.c_int, [P, U32, U64, U64, PU64]),
+            "bvs_learned_build_workspace_bytes": (C.c_int, [P, U32, U64, U64, PU64]),
+            "bvs_build_index_learned": (C.c_int, [P, U32, P, P, P, U64, P, U64, P, U64, P, C.POINTER(P)]),
+            "bvs_train_workspace_bytes": (C.c_int, [P, U64, PU64]),
+            "bvs_train_gradients": (C.c_int, [P, P, P, U64, P, U32, P, P, C.POINTER(C.c_float), P, U64, P]),
+            "bvs_train_projection": (C.c_int, [P, P, P, U64, P, U64, P, P, U64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -208,7 +224,8 @@ class Index:
     """A built index.  `vectors` is a float32 CUDA tensor [N, dim] on the
     2^-12 grid; `offsets` host offsets [n + 1]."""
 
-    def __init__(self, params: Params, vectors: torch.Tensor, offsets, stream=None):
+    def __init__(self, params: Params, vectors: torch.Tensor, offsets, stream=None, mlp=None):
+        """mlp: optional (hidden, float32 packed weights tensor) of a learned projection."""
         L = lib()
         if not (vectors.is_cuda and vectors.dtype == torch.float32 and vectors.is_contiguous()):
             raise ValueError("vectors must be a contiguous float32 CUDA tensor")
@@ -217,13 +234,23 @@ class Index:
         off = _offsets(offsets)
         n = len(off) - 1
         N = int(off[-1]) if n >= 0 else 0
-        nbytes = _bytes(L.bvs_index_bytes, C.byref(self.params), n, N)
-        wbytes = _bytes(L.bvs_build_workspace_bytes, C.byref(self.params), n, N)
-        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        ws = _workspace(wbytes, self.device)
         h = C.c_void_p()
-        check(L.bvs_build_index(C.byref(self.params), _ptr(vectors), _u64p(off), n, _ptr(self.mem), nbytes,
-                                _ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+        if mlp is None:
+            nbytes = _bytes(L.bvs_index_bytes, C.byref(self.params), n, N)
+            wbytes = _bytes(L.bvs_build_workspace_bytes, C.byref(self.params), n, N)
+            self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            ws = _workspace(wbytes, self.device)
+            check(L.bvs_build_index(C.byref(self.params), _ptr(vectors), _u64p(off), n, _ptr(self.mem), nbytes,
+                                    _ptr(ws), ws.numel(), _stream(stream), C.byref(h)))
+        else:
+            hidden, weights = mlp
+            nbytes = _bytes(L.bvs_learned_index_bytes, C.byref(self.params), hidden, n, N)
+            wbytes = _bytes(L.bvs_learned_build_workspace_bytes, C.byref(self.params), hidden, n, N)
+            self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            ws = _workspace(wbytes, self.device)
+            check(L.bvs_build_index_learned(C.byref(self.params), hidden, _ptr(weights), _ptr(vectors), _u64p(off),
+                                            n, _ptr(self.mem), nbytes, _ptr(ws), ws.numel(), _stream(stream),
+                                            C.byref(h)))
         self._h = h
         del ws
         info = IndexInfo()
@@ -460,3 +487,50 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# -- learned projection
+def mlp_weights(dim: int, hidden: int, code_bits: int, seed: int = 0, device="cuda") -> torch.Tensor:
+    """Initialised packed float32 weights [W1 | b1 | W2 | b2]."""
+    n = C.c_uint64()
+    check(lib().bvs_mlp_weight_count(dim, hidden, code_bits, C.byref(n)))
+    w = torch.empty(int(n.value), dtype=torch.float32, device=device)
+    check(lib().bvs_mlp_init(dim, hidden, code_bits, seed, _ptr(w), _stream(None)))
+    return w
+
+
+def unpack_mlp(w: torch.Tensor, dim: int, hidden: int, code_bits: int):
+    a = hidden * dim
+    b = a + hidden
+    c = b + code_bits * hidden
+    return (w[:a].view(hidden, dim), w[a:b], w[b:c].view(code_bits, hidden), w[c:])
+
+
+class Trainer:
+    """Triplet training of the learned projection on a training collection
+    (float32 CUDA vectors, host offsets); triplets uint32 [n, 3] of set ids."""
+
+    def __init__(self, cfg: TrainConfig, vectors: torch.Tensor, offsets, max_batch_rows: int):
+        self.cfg = TrainConfig.from_buffer_copy(cfg)
+        self.vectors = vectors
+        self.off = _offsets(offsets)
+        nb = C.c_uint64()
+        check(lib().bvs_train_workspace_bytes(C.byref(self.cfg), max_batch_rows, C.byref(nb)))
+        self.ws = _workspace(int(nb.value), vectors.device)
+
+    def gradients(self, weights: torch.Tensor, triplets: np.ndarray):
+        trip = np.ascontiguousarray(np.asarray(triplets, np.uint32))
+        grads = torch.empty_like(weights)
+        loss = C.c_float()
+        check(lib().bvs_train_gradients(C.byref(self.cfg), _ptr(self.vectors), _u64p(self.off), len(self.off) - 1,
+                                        trip.ctypes.data_as(C.c_void_p), len(trip), _ptr(weights), _ptr(grads),
+                                        C.byref(loss), _ptr(self.ws), self.ws.numel(), _stream(None)))
+        return float(loss.value), grads
+
+    def train(self, weights: torch.Tensor, triplets: np.ndarray):
+        trip = np.ascontiguousarray(np.asarray(triplets, np.uint32))
+        losses = (C.c_float * max(1, self.cfg.epochs))()
+        check(lib().bvs_train_projection(C.byref(self.cfg), _ptr(self.vectors), _u64p(self.off), len(self.off) - 1,
+                                         trip.ctypes.data_as(C.c_void_p), len(trip), _ptr(weights), _ptr(self.ws),
+                                         self.ws.numel(), losses, _stream(None)))
+        return [float(x) for x in losses[: self.cfg.epochs]]

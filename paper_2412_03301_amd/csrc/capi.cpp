@@ -283,6 +283,12 @@ struct bvs_index {
   // attached precision copies, by format (BVS_LOWP_BF16, BVS_LOWP_FP8)
   uint8_t* lowp[3] = {nullptr, nullptr, nullptr};
   float* lowp_scale[3] = {nullptr, nullptr, nullptr};
+  // learned projection (codes from the network instead of W)
+  bool learned = false;
+  uint32_t hidden = 0;
+  uint16_t* w16 = nullptr;   // packed bfloat16 [W1 | b1 | W2 | b2]
+  float* b1 = nullptr;       // [hidden]
+  float* b2 = nullptr;       // [L]
 };
 
 namespace {
@@ -343,6 +349,10 @@ struct QueryWs {
   uint32_t* thr;          // [n_q] re-rank bound
   unsigned long long* stats;   // [4] work counters
   uint64_t* topk_tmp;
+  // learned projection: query rows in bfloat16, hidden layer, outputs
+  uint16_t* lx16;
+  uint16_t* lh16;
+  float* ly;
 };
 
 constexpr uint32_t kMaxK = 64;
@@ -408,6 +418,36 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->thr = c.take<uint32_t>(n_q);
   w->stats = c.take<unsigned long long>((uint64_t)kStatSlots * kStatCounters);
   w->topk_tmp = c.take<uint64_t>(topk_tmp_words(g.T, n_q, kMaxK));
+  w->lx16 = nullptr;
+  w->lh16 = nullptr;
+  w->ly = nullptr;
+  if (ix->learned) {
+    w->lx16 = c.take<uint16_t>(NQ * g.d);
+    w->lh16 = c.take<uint16_t>(NQ * ix->hidden);
+    w->ly = c.take<float>(NQ * g.L);
+  }
+}
+
+Mlp index_mlp(const bvs_index* ix) {
+  Mlp m;
+  m.d = ix->g.d;
+  m.H = ix->hidden;
+  m.L = ix->g.L;
+  m.wta_k = ix->g.wta_k;
+  m.W1 = ix->w16;
+  m.b1 = ix->b1;
+  m.W2 = ix->w16 + (uint64_t)ix->hidden * ix->g.d + ix->hidden;
+  m.b2 = ix->b2;
+  return m;
+}
+
+// Codes of n converted rows (exact planes) through the index's projection.
+hipError_t encode_planes(const bvs_index* ix, const int8_t* hi, const uint8_t* lo, uint64_t n, uint64_t* codes,
+                         uint16_t* x16, uint16_t* h16, float* y, hipStream_t st) {
+  if (!ix->learned) return launch_encode_vectors(hash_geom(ix), hi, lo, n, codes, ix->n_cu, st);
+  hipError_t e = launch_planes_to_bf16(hi, lo, ix->g.dp, ix->g.d, n, x16, st);
+  if (e != hipSuccess) return e;
+  return encode_learned(index_mlp(ix), x16, n, h16, y, codes, st);
 }
 
 void layout_brute(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, QueryWs* w) {
@@ -450,7 +490,8 @@ bvs_status query_side(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Quer
                       CallProf& prof) {
   const Geometry& g = ix->g;
   const HashGeom hg = hash_geom(ix);
-  HIP_TRY(staged(prof, S_ENCODE, [&] { return launch_encode_vectors(hg, w.qhi, w.qlo, NQ, w.codes, ix->n_cu, st); }));
+  (void)hg;
+  HIP_TRY(staged(prof, S_ENCODE, [&] { return encode_planes(ix, w.qhi, w.qlo, NQ, w.codes, w.lx16, w.lh16, w.ly, st); }));
   HIP_TRY(staged(prof, S_QSKETCH, [&] {
     return launch_query_sketch(w.codes, w.qoff, n_q, g.L, g.R, g.A, w.cq, w.sq, w.pos, w.gate, w.gate_chunks, st);
   }));
@@ -769,6 +810,11 @@ bvs_status bvs_encode_workspace_bytes(const bvs_index* ix, uint64_t n, uint64_t*
   c.take<int8_t>(n * ix->g.dp);
   c.take<uint8_t>(n * ix->g.dp);
   c.take<uint32_t>(n);
+  if (ix->learned) {
+    c.take<uint16_t>(n * ix->g.d);
+    c.take<uint16_t>(n * ix->hidden);
+    c.take<float>(n * ix->g.L);
+  }
   *out = align_up(c.off, 256);
   return BVS_OK;
 }
@@ -787,9 +833,12 @@ bvs_status bvs_encode(const bvs_index* ix, const float* d_x, uint64_t n, void* d
   int8_t* hi = c.take<int8_t>(n * ix->g.dp);
   uint8_t* lo = c.take<uint8_t>(n * ix->g.dp);
   uint32_t* norms = c.take<uint32_t>(n);
+  uint16_t* x16 = ix->learned ? c.take<uint16_t>(n * ix->g.d) : nullptr;
+  uint16_t* h16 = ix->learned ? c.take<uint16_t>(n * ix->hidden) : nullptr;
+  float* y = ix->learned ? c.take<float>(n * ix->g.L) : nullptr;
   HIP_TRY(launch_fill_u32(status, 4, 0, st));
   HIP_TRY(launch_convert(d_x, n, ix->g.d, ix->g.dp, hi, lo, norms, status, ix->n_cu, st));
-  HIP_TRY(launch_encode_vectors(hash_geom(ix), hi, lo, n, d_codes, ix->n_cu, st));
+  HIP_TRY(encode_planes(ix, hi, lo, n, d_codes, x16, h16, y, st));
   return read_status(status, st, "vectors");
 }
 
@@ -1455,6 +1504,397 @@ bvs_status bvs_hausdorff_lowp(const bvs_index* ix, int fmt, const float* d_q, co
   const bvs_status s = read_status(l.w.status, st, "queries");
   prof.finish();
   return s;
+}
+
+}  // extern "C"
+
+// ====================================================================== learned projection
+namespace {
+
+uint64_t mlp_floats(uint32_t d, uint32_t H, uint32_t L) { return (uint64_t)H * d + H + (uint64_t)L * H + L; }
+
+bvs_status check_mlp_shape(uint32_t d, uint32_t H, uint32_t L) {
+  if (d == 0 || d > 1024 || d % 8 != 0) return fail(BVS_ENOTSUP, "learned projection needs dim %% 8 == 0, <= 1024");
+  if (H == 0 || H > 8192 || H % 8 != 0) return fail(BVS_ENOTSUP, "hidden size must be a multiple of 8 in 8..8192");
+  if (L < 256 || L > 4096 || (L & (L - 1))) return fail(BVS_ENOTSUP, "code_bits must be a power of two in 256..4096");
+  return BVS_OK;
+}
+
+// Rows encoded per pass of the learned build.
+constexpr uint64_t kLearnChunkRows = 1u << 18;
+
+void layout_learned_weights(Carver& c, const Geometry& g, uint32_t H, bvs_index* ix) {
+  ix->w16 = c.take<uint16_t>(mlp_floats(g.d, H, g.L));
+  ix->b1 = c.take<float>(H);
+  ix->b2 = c.take<float>(g.L);
+}
+
+struct TrainWs {
+  uint64_t* rows;        // [cap] source rows of the batch
+  uint32_t* row_off;     // [max_sets + 1]
+  uint32_t* trip;        // [B][3]
+  uint16_t* x16;         // [cap][d]
+  uint16_t* h16;         // [cap][H]
+  float* y;              // [cap][L]
+  float* thr;            // [cap]
+  float* ls;             // [max_sets][L]
+  float* s;              // [max_sets][L]
+  float* ds;             // [max_sets][L]
+  float* dy;             // [cap][L]
+  uint16_t* dy16;        // [cap][L]
+  float* dh;             // [cap][H]
+  uint16_t* dp16;        // [cap][H]
+  float* loss;           // [1]
+  float* grad;           // packed like the weights
+  uint16_t* w16;         // packed bfloat16 weights
+  float* adam_m;
+  float* adam_v;
+};
+
+void layout_train(Carver& c, const bvs_train_config& t, uint64_t cap, TrainWs* w) {
+  const uint64_t ms = 3ull * t.batch_triplets;
+  const uint64_t nw = mlp_floats(t.dim, t.hidden, t.code_bits);
+  w->rows = c.take<uint64_t>(cap);
+  w->row_off = c.take<uint32_t>(ms + 1);
+  w->trip = c.take<uint32_t>(3ull * t.batch_triplets);
+  w->x16 = c.take<uint16_t>(cap * t.dim);
+  w->h16 = c.take<uint16_t>(cap * t.hidden);
+  w->y = c.take<float>(cap * t.code_bits);
+  w->thr = c.take<float>(cap);
+  w->ls = c.take<float>(ms * t.code_bits);
+  w->s = c.take<float>(ms * t.code_bits);
+  w->ds = c.take<float>(ms * t.code_bits);
+  w->dy = c.take<float>(cap * t.code_bits);
+  w->dy16 = c.take<uint16_t>(cap * t.code_bits);
+  w->dh = c.take<float>(cap * t.hidden);
+  w->dp16 = c.take<uint16_t>(cap * t.hidden);
+  w->loss = c.take<float>(4);
+  w->grad = c.take<float>(nw);
+  w->w16 = c.take<uint16_t>(nw);
+  w->adam_m = c.take<float>(nw);
+  w->adam_v = c.take<float>(nw);
+}
+
+bvs_status check_train_config(const bvs_train_config* t) {
+  if (!t) return fail(BVS_EINVAL, "config is NULL");
+  BVS_TRY(check_mlp_shape(t->dim, t->hidden, t->code_bits));
+  if (t->wta_k < 1 || t->wta_k >= t->code_bits) return fail(BVS_EINVAL, "wta_k outside 1..code_bits-1");
+  if (t->batch_triplets < 1 || t->batch_triplets > 65536) return fail(BVS_EINVAL, "batch_triplets outside 1..65536");
+  if (!(t->tau > 0.f) || !(t->lr >= 0.f) || !(t->margin >= 0.f) || !std::isfinite(t->tau) || !std::isfinite(t->lr) ||
+      !std::isfinite(t->margin))
+    return fail(BVS_EINVAL, "tau must be > 0, lr and margin >= 0, all finite");
+  return BVS_OK;
+}
+
+// One batch of triplets: forward, loss, gradients into w.grad (packed).
+// Sets are rows h_off[s] .. h_off[s+1] of d_vectors.
+bvs_status train_batch(const bvs_train_config& t, const float* d_vectors, const uint64_t* h_off, uint64_t n_sets,
+                       const uint32_t* trips, uint32_t nt, uint64_t cap, const uint16_t* w16, const float* w32,
+                       TrainWs& w, hipStream_t st, std::vector<uint64_t>& rows, std::vector<uint32_t>& roff,
+                       std::vector<uint32_t>& tl) {
+  // distinct sets of the batch, in first-seen order
+  std::map<uint32_t, uint32_t> local;
+  std::vector<uint32_t> sets;
+  tl.resize(3ull * nt);
+  for (uint32_t i = 0; i < nt; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t sid = trips[3ull * i + k];
+      if (sid >= n_sets) return fail(BVS_EINVAL, "triplet %u names set %u of %llu", i, sid, (unsigned long long)n_sets);
+      auto it = local.find(sid);
+      if (it == local.end()) {
+        it = local.emplace(sid, (uint32_t)sets.size()).first;
+        sets.push_back(sid);
+      }
+      tl[3ull * i + k] = it->second;
+    }
+  }
+  rows.clear();
+  roff.assign(1, 0);
+  for (uint32_t sid : sets) {
+    for (uint64_t r = h_off[sid]; r < h_off[sid + 1]; ++r) rows.push_back(r);
+    roff.push_back((uint32_t)rows.size());
+  }
+  const uint64_t nb = rows.size();
+  if (nb > cap)
+    return fail(BVS_ENOSPC, "a batch holds %llu rows; the workspace fits %llu", (unsigned long long)nb,
+                (unsigned long long)cap);
+  const uint32_t d = t.dim, H = t.hidden, L = t.code_bits;
+  const uint32_t ns = (uint32_t)sets.size();
+  HIP_TRY(hipMemcpyAsync(w.rows, rows.data(), nb * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w.row_off, roff.data(), roff.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w.trip, tl.data(), tl.size() * 4, hipMemcpyHostToDevice, st));
+  const uint16_t* W1 = w16;
+  const uint16_t* W2 = w16 + (uint64_t)H * d + H;
+  const float* b1 = w32 + (uint64_t)H * d;
+  const float* b2 = w32 + (uint64_t)H * d + H + (uint64_t)L * H;
+  float* gW1 = w.grad;
+  float* gb1 = w.grad + (uint64_t)H * d;
+  float* gW2 = gb1 + H;
+  float* gb2 = gW2 + (uint64_t)L * H;
+  // forward
+  HIP_TRY(launch_rows_to_bf16(d_vectors, d, w.rows, nb, w.x16, st));
+  HIP_TRY(launch_gemm(false, false, w.x16, d, W1, d, (uint32_t)nb, H, d, b1, true, nullptr, w.h16, H, st));
+  HIP_TRY(launch_gemm(false, false, w.h16, H, W2, H, (uint32_t)nb, L, H, b2, false, w.y, nullptr, L, st));
+  HIP_TRY(launch_row_thresholds(w.y, nb, L, t.wta_k, w.thr, st));
+  HIP_TRY(launch_set_soft(w.y, w.thr, w.row_off, ns, L, t.tau, w.ls, w.s, st));
+  // loss and sketch gradients
+  HIP_TRY(launch_fill_u32((uint32_t*)w.ds, (uint64_t)ns * L, 0u, st));
+  HIP_TRY(launch_fill_u32((uint32_t*)w.loss, 1, 0u, st));
+  HIP_TRY(launch_triplet(w.s, w.trip, nt, L, t.margin, w.ds, w.loss, st));
+  // backward
+  HIP_TRY(launch_soft_backward(w.y, w.thr, w.row_off, ns, L, t.tau, w.ls, w.ds, w.dy, w.dy16, st));
+  HIP_TRY(launch_gemm(false, true, w.dy16, L, W2, H, (uint32_t)nb, H, L, nullptr, false, w.dh, nullptr, H, st));
+  HIP_TRY(launch_relu_backward(w.dh, w.h16, nb * H, w.dh, w.dp16, st));
+  HIP_TRY(launch_gemm(true, true, w.dy16, L, w.h16, H, L, H, (uint32_t)nb, nullptr, false, gW2, nullptr, H, st));
+  HIP_TRY(launch_gemm(true, true, w.dp16, H, w.x16, d, H, d, (uint32_t)nb, nullptr, false, gW1, nullptr, d, st));
+  HIP_TRY(launch_colsum(w.dy, nb, L, gb2, st));
+  HIP_TRY(launch_colsum(w.dh, nb, H, gb1, st));
+  return BVS_OK;
+}
+
+uint64_t train_capacity(const bvs_train_config& t, uint64_t ws_bytes) {
+  // largest row capacity whose layout fits ws_bytes
+  uint64_t lo = 0, hi = 1ull << 26;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi + 1) / 2;
+    Carver c(nullptr);
+    TrainWs w;
+    layout_train(c, t, mid, &w);
+    if (align_up(c.off, 256) <= ws_bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace
+
+extern "C" {
+
+bvs_status bvs_mlp_weight_count(uint32_t dim, uint32_t hidden, uint32_t code_bits, uint64_t* out) {
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  BVS_TRY(check_mlp_shape(dim, hidden, code_bits));
+  *out = mlp_floats(dim, hidden, code_bits);
+  return BVS_OK;
+}
+
+bvs_status bvs_mlp_init(uint32_t dim, uint32_t hidden, uint32_t code_bits, uint64_t seed, float* d_weights,
+                        void* stream) {
+  BVS_TRY(check_mlp_shape(dim, hidden, code_bits));
+  if (!d_weights) return fail(BVS_EINVAL, "weights are NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_mlp_init(d_weights, dim, hidden, code_bits, seed, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return BVS_OK;
+}
+
+bvs_status bvs_learned_index_bytes(const bvs_params* p, uint32_t hidden, uint64_t n_sets, uint64_t n_vectors,
+                                   uint64_t* out) {
+  Geometry g;
+  BVS_TRY(derive(p, &g));
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  BVS_TRY(check_mlp_shape(g.d, hidden, g.L));
+  Carver c(nullptr);
+  bvs_index tmp;
+  layout_index(c, g, n_sets, n_vectors, &tmp);
+  layout_learned_weights(c, g, hidden, &tmp);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_learned_build_workspace_bytes(const bvs_params* p, uint32_t hidden, uint64_t n_sets,
+                                             uint64_t n_vectors, uint64_t* out) {
+  Geometry g;
+  BVS_TRY(derive(p, &g));
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  BVS_TRY(check_mlp_shape(g.d, hidden, g.L));
+  const uint64_t rows = std::min<uint64_t>(std::max<uint64_t>(n_vectors, 1), kLearnChunkRows + 256);
+  Carver c(nullptr);
+  c.take<uint32_t>(4);
+  c.take<uint8_t>(n_sets * g.L);
+  c.take<uint64_t>(n_sets * g.R);
+  c.take<uint16_t>(rows * g.d);
+  c.take<uint16_t>(rows * hidden);
+  c.take<float>(rows * g.L);
+  c.take<uint64_t>(rows * g.R);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_build_index_learned(const bvs_params* p, uint32_t hidden, const float* d_weights,
+                                   const float* d_vectors, const uint64_t* h_offsets, uint64_t n_sets,
+                                   void* d_index_mem, uint64_t index_bytes, void* d_ws, uint64_t ws_bytes,
+                                   void* stream, bvs_index** out) {
+  Geometry g;
+  BVS_TRY(derive(p, &g));
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  *out = nullptr;
+  BVS_TRY(check_mlp_shape(g.d, hidden, g.L));
+  if (!d_weights) return fail(BVS_EINVAL, "weights are NULL");
+  if (n_sets == 0) return fail(BVS_EINVAL, "n_sets must be positive");
+  if (n_sets >= 0xFFFFFFFFull) return fail(BVS_ENOTSUP, "n_sets must be below 2^32 - 1");
+  if (!d_vectors) return fail(BVS_EINVAL, "vectors are NULL");
+  uint32_t max_m = 0;
+  BVS_TRY(check_offsets(h_offsets, n_sets, 255, "database", &max_m));
+  const uint64_t N = h_offsets[n_sets];
+  uint64_t need = 0, wneed = 0;
+  BVS_TRY(bvs_learned_index_bytes(p, hidden, n_sets, N, &need));
+  BVS_TRY(bvs_learned_build_workspace_bytes(p, hidden, n_sets, N, &wneed));
+  if (!d_index_mem) return fail(BVS_EINVAL, "index memory is NULL");
+  if (index_bytes < need)
+    return fail(BVS_ENOSPC, "index memory of %llu bytes, %llu needed", (unsigned long long)index_bytes,
+                (unsigned long long)need);
+  BVS_TRY(need_ws(ws_bytes, wneed, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  std::unique_ptr<bvs_index> ix(new bvs_index());
+  ix->p = *p;
+  ix->g = g;
+  ix->n = n_sets;
+  ix->N = N;
+  ix->max_m = max_m;
+  if (hipGetDevice(&ix->device) != hipSuccess) ix->device = 0;
+  ix->n_cu = device_cus(ix->device);
+  Carver c(d_index_mem);
+  layout_index(c, g, n_sets, N, ix.get());
+  layout_learned_weights(c, g, hidden, ix.get());
+  ix->learned = true;
+  ix->hidden = hidden;
+  const uint64_t rows_cap = std::min<uint64_t>(std::max<uint64_t>(N, 1), kLearnChunkRows + 256);
+  Carver wc(d_ws);
+  uint32_t* status = wc.take<uint32_t>(4);
+  uint8_t* cnt_rm = wc.take<uint8_t>(n_sets * g.L);
+  uint64_t* bits_rm = wc.take<uint64_t>(n_sets * g.R);
+  uint16_t* x16 = wc.take<uint16_t>(rows_cap * g.d);
+  uint16_t* h16 = wc.take<uint16_t>(rows_cap * hidden);
+  float* y = wc.take<float>(rows_cap * g.L);
+  uint64_t* codes = wc.take<uint64_t>(rows_cap * g.R);
+  const uint64_t nw = mlp_floats(g.d, hidden, g.L);
+  auto run = [&]() -> bvs_status {
+    HIP_TRY(hipMemcpyAsync(ix->offsets, h_offsets, (n_sets + 1) * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_f32_to_bf16(d_weights, nw, ix->w16, st));
+    HIP_TRY(hipMemcpyAsync(ix->b1, d_weights + (uint64_t)hidden * g.d, (uint64_t)hidden * 4,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ix->b2, d_weights + (uint64_t)hidden * g.d + hidden + (uint64_t)g.L * hidden,
+                           (uint64_t)g.L * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_fill_u32(status, 4, 0, st));
+    HIP_TRY(launch_convert(d_vectors, N, g.d, g.dp, ix->hi, ix->lo, ix->norms, status, ix->n_cu, st));
+    // codes and set sketches, a chunk of whole sets at a time
+    uint64_t s0 = 0;
+    while (s0 < n_sets) {
+      uint64_t s1 = s0;
+      while (s1 < n_sets && h_offsets[s1 + 1] - h_offsets[s0] <= rows_cap) ++s1;
+      const uint64_t r0 = h_offsets[s0], nr = h_offsets[s1] - r0;
+      HIP_TRY(encode_planes(ix.get(), ix->hi + r0 * g.dp, ix->lo + r0 * g.dp, nr, codes, x16, h16, y, st));
+      HIP_TRY(launch_sets_from_codes(codes, ix->offsets, r0, s0, s1 - s0, g.R, cnt_rm, bits_rm, st));
+      s0 = s1;
+    }
+    HIP_TRY(launch_transpose_sketches(cnt_rm, bits_rm, n_sets, ix->ld, g.L, ix->cnt, ix->bits, st));
+    HIP_TRY(launch_bitmap_planes(ix->cnt, ix->ld, g.L, ix->planes, st));
+    return read_status(status, st, "database");
+  };
+  const bvs_status s = run();
+  if (s != BVS_OK) {
+    (void)hipStreamSynchronize(st);
+    return s;
+  }
+  *out = ix.release();
+  return BVS_OK;
+}
+
+bvs_status bvs_train_workspace_bytes(const bvs_train_config* t, uint64_t max_batch_rows, uint64_t* out) {
+  BVS_TRY(check_train_config(t));
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  Carver c(nullptr);
+  TrainWs w;
+  layout_train(c, *t, std::max<uint64_t>(max_batch_rows, 1), &w);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_train_gradients(const bvs_train_config* t, const float* d_vectors, const uint64_t* h_offsets,
+                               uint64_t n_sets, const uint32_t* h_triplets, uint32_t n_triplets,
+                               const float* d_weights, float* d_grads, float* h_loss, void* d_ws, uint64_t ws_bytes,
+                               void* stream) {
+  BVS_TRY(check_train_config(t));
+  if (!d_vectors || !d_weights || !d_grads || !h_triplets) return fail(BVS_EINVAL, "NULL argument");
+  if (n_triplets == 0 || n_triplets > t->batch_triplets)
+    return fail(BVS_EINVAL, "n_triplets must be in 1..batch_triplets");
+  uint32_t max_m = 0;
+  BVS_TRY(check_offsets(h_offsets, n_sets, 65535, "training", &max_m));
+  const uint64_t cap = train_capacity(*t, ws_bytes);
+  if (!d_ws || cap == 0) return fail(BVS_ENOSPC, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  TrainWs w;
+  layout_train(c, *t, cap, &w);
+  const uint64_t nw = mlp_floats(t->dim, t->hidden, t->code_bits);
+  std::vector<uint64_t> rows;
+  std::vector<uint32_t> roff, tl;
+  HIP_TRY(launch_f32_to_bf16(d_weights, nw, w.w16, st));
+  BVS_TRY(train_batch(*t, d_vectors, h_offsets, n_sets, h_triplets, n_triplets, cap, w.w16, d_weights, w, st, rows,
+                      roff, tl));
+  HIP_TRY(hipMemcpyAsync(d_grads, w.grad, nw * 4, hipMemcpyDeviceToDevice, st));
+  float l = 0.f;
+  HIP_TRY(hipMemcpyAsync(&l, w.loss, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h_loss) *h_loss = l;
+  return BVS_OK;
+}
+
+bvs_status bvs_train_projection(const bvs_train_config* t, const float* d_vectors, const uint64_t* h_offsets,
+                                uint64_t n_sets, const uint32_t* h_triplets, uint64_t n_triplets, float* d_weights,
+                                void* d_ws, uint64_t ws_bytes, float* h_epoch_loss, void* stream) {
+  BVS_TRY(check_train_config(t));
+  if (!d_vectors || !d_weights || !h_triplets) return fail(BVS_EINVAL, "NULL argument");
+  if (n_triplets == 0) return fail(BVS_EINVAL, "no triplets");
+  uint32_t max_m = 0;
+  BVS_TRY(check_offsets(h_offsets, n_sets, 65535, "training", &max_m));
+  const uint64_t cap = train_capacity(*t, ws_bytes);
+  if (!d_ws || cap == 0) return fail(BVS_ENOSPC, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  TrainWs w;
+  layout_train(c, *t, cap, &w);
+  const uint64_t nw = mlp_floats(t->dim, t->hidden, t->code_bits);
+  HIP_TRY(launch_fill_u32((uint32_t*)w.adam_m, nw, 0u, st));
+  HIP_TRY(launch_fill_u32((uint32_t*)w.adam_v, nw, 0u, st));
+  HIP_TRY(launch_f32_to_bf16(d_weights, nw, w.w16, st));
+  // triplet order: a splitmix64-driven shuffle per epoch
+  std::vector<uint64_t> order(n_triplets);
+  for (uint64_t i = 0; i < n_triplets; ++i) order[i] = i;
+  uint64_t rng = t->seed;
+  auto next = [&rng]() {
+    rng += 0x9E3779B97F4A7C15ull;
+    uint64_t z = rng;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  std::vector<uint32_t> batch;
+  std::vector<uint64_t> rows;
+  std::vector<uint32_t> roff, tl;
+  uint32_t step = 0;
+  for (uint32_t ep = 0; ep < t->epochs; ++ep) {
+    for (uint64_t i = n_triplets - 1; i > 0; --i) std::swap(order[i], order[next() % (i + 1)]);
+    double ep_loss = 0.0;
+    uint64_t n_batches = 0;
+    for (uint64_t b0 = 0; b0 < n_triplets; b0 += t->batch_triplets) {
+      const uint32_t nt = (uint32_t)std::min<uint64_t>(t->batch_triplets, n_triplets - b0);
+      batch.resize(3ull * nt);
+      for (uint32_t i = 0; i < nt; ++i)
+        for (int k = 0; k < 3; ++k) batch[3ull * i + k] = h_triplets[3 * order[b0 + i] + k];
+      BVS_TRY(train_batch(*t, d_vectors, h_offsets, n_sets, batch.data(), nt, cap, w.w16, d_weights, w, st, rows,
+                          roff, tl));
+      HIP_TRY(launch_adam(d_weights, w.grad, w.adam_m, w.adam_v, nw, t->lr, 0.9f, 0.999f, 1e-8f, ++step, w.w16,
+                          st));
+      float l = 0.f;
+      HIP_TRY(hipMemcpyAsync(&l, w.loss, 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      ep_loss += l;
+      ++n_batches;
+    }
+    if (h_epoch_loss) h_epoch_loss[ep] = (float)(ep_loss / std::max<uint64_t>(1, n_batches));
+  }
+  return BVS_OK;
 }
 
 }  // extern "C"

@@ -176,6 +176,46 @@ hipError_t launch_lowp_select(const uint32_t* approx, const uint32_t* ids, const
                               uint32_t n_q, uint32_t k, float factor, uint32_t* r_ids, uint32_t* r_count,
                               hipStream_t st);
 
+// Learned projection (bfloat16 weights; biases float32).
+struct Mlp {
+  uint32_t d, H, L, wta_k;
+  const uint16_t* W1;   // [H][d]
+  const float* b1;      // [H]
+  const uint16_t* W2;   // [L][H]
+  const float* b2;      // [L]
+};
+// C = A B (see k_gemm for the layouts), bfloat16 operands, float32 accumulation.
+hipError_t launch_gemm(bool at, bool bt, const uint16_t* A, uint64_t lda, const uint16_t* B, uint64_t ldb,
+                       uint32_t M, uint32_t N, uint32_t K, const float* bias, bool relu, float* C32, uint16_t* C16,
+                       uint64_t ldc, hipStream_t st);
+hipError_t launch_rows_to_bf16(const float* X, uint32_t d, const uint64_t* rows, uint64_t n, uint16_t* out,
+                               hipStream_t st);
+hipError_t launch_planes_to_bf16(const int8_t* hi, const uint8_t* lo, uint32_t dp, uint32_t d, uint64_t n,
+                                 uint16_t* out, hipStream_t st);
+hipError_t launch_f32_to_bf16(const float* x, uint64_t n, uint16_t* out, hipStream_t st);
+hipError_t launch_wta_rows(const float* Y, uint64_t ldy, uint64_t n, uint32_t L, uint32_t k, uint64_t* codes,
+                           hipStream_t st);
+hipError_t launch_sets_from_codes(const uint64_t* codes, const uint64_t* offsets, uint64_t base, uint64_t s0,
+                                  uint64_t n_sets, uint32_t R, uint8_t* cnt_rm, uint64_t* bits_rm, hipStream_t st);
+// Codes of n bfloat16 rows X16 [n][d] through the network (scratch H16 [n][H], Y [n][L]).
+hipError_t encode_learned(const Mlp& m, const uint16_t* X16, uint64_t n, uint16_t* H16, float* Y, uint64_t* codes,
+                          hipStream_t st);
+// Training kernels.
+hipError_t launch_row_thresholds(const float* Y, uint64_t n, uint32_t L, uint32_t k, float* thr, hipStream_t st);
+hipError_t launch_set_soft(const float* Y, const float* thr, const uint32_t* row_off, uint32_t n_sets, uint32_t L,
+                           float tau, float* LS, float* S, hipStream_t st);
+hipError_t launch_triplet(const float* S, const uint32_t* trip, uint32_t n_trip, uint32_t L, float margin,
+                          float* dS, float* loss, hipStream_t st);
+hipError_t launch_soft_backward(const float* Y, const float* thr, const uint32_t* row_off, uint32_t n_sets, uint32_t L,
+                                float tau, const float* LS, const float* dS, float* dY, uint16_t* dY16,
+                                hipStream_t st);
+hipError_t launch_relu_backward(const float* dH, const uint16_t* H16, uint64_t n, float* dP, uint16_t* dP16,
+                                hipStream_t st);
+hipError_t launch_colsum(const float* X, uint64_t n, uint32_t C, float* out, hipStream_t st);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, uint64_t n, float lr, float b1, float b2,
+                       float eps, uint32_t step, uint16_t* w16, hipStream_t st);
+hipError_t launch_mlp_init(float* w, uint32_t d, uint32_t H, uint32_t L, uint64_t seed, hipStream_t st);
+
 // Fill a u32 buffer (used instead of hipMemsetAsync so work stays graph-safe).
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st,
                            const uint32_t* run_if = nullptr);
