@@ -45,7 +45,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scale", choices=["scale", "tiny", "batched", "precision"])
+    ap.add_argument("--workload", default="scale", choices=["scale", "tiny", "batched", "precision", "learned"])
+    ap.add_argument("--train-epochs", type=int, default=1)
+    ap.add_argument("--train-batch", type=int, default=256)
+    ap.add_argument("--train-lr", type=float, default=3e-4)
+    ap.add_argument("--train-tau", type=float, default=0.01)
+    ap.add_argument("--train-margin", type=float, default=64.0)
+    ap.add_argument("--mine-queries", type=int, default=None)
+    ap.add_argument("--train-sets", type=int, default=None)
+    ap.add_argument("--sweep-t", default="500,1000,2000")
     ap.add_argument("--margin", type=float, default=0.02, help="precision workload: re-check margin")
     ap.add_argument("--form", default="fp8", choices=["fp8", "bf16"], help="precision workload: reported form")
     ap.add_argument("--per-query-sample", type=int, default=1024,
@@ -481,6 +489,159 @@ def precision(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
     }
 
 
+def learned_bench(args, w, cfg, dev):
+    """Learned projection: mine triplets with the exact brute force on a
+    separate training corpus, train the network with the library's trainer,
+    then search the evaluation database with the learned index and with the
+    random FlyHash index over a sweep of T (recall@10 against brute force and
+    throughput for each), keeping the random projection if the learned one
+    does not reach its recall."""
+    import numpy as np
+    import torch
+
+    from paper_2412_03301_amd import bvs, synth
+
+    d, L, k_wta, H = w["dim"], w["code_bits"], w["wta_k"], w["hidden"]
+    n_tr = args.train_sets or w["train_sets"]
+    n_mine = args.mine_queries or w["mine_queries"]
+    n_neg = w["negatives"]
+    k = w["k"]
+    t_start = time.perf_counter()
+    log(f"training corpus: {n_tr} sets (d={d}, seed {w['train_seed']})")
+    tdb = synth.make_database(n_tr, w["size_lo"], w["size_hi"], d, w["n_topics"], seed=w["train_seed"], device=dev)
+    tq, tq_off, _ = synth.make_subset_queries(tdb, n_mine, seed=w["train_seed"] + 1)
+    tq = tq.contiguous()
+    p_tr = bvs.Params.make(dim=d, code_bits=L, fan_in=w["fan_in"], wta_k=k_wta, top_t=w["top_t"], seed=0)
+    tix = bvs.Index(p_tr, tdb.vectors, tdb.offsets)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pos = np.zeros((n_mine, 10), np.int64)
+    ch = 2048
+    for c0 in range(0, n_mine, ch):
+        c1 = min(n_mine, c0 + ch)
+        qc = tq[int(tq_off[c0]):int(tq_off[c1])].contiguous()
+        ids, _, _ = tix.bruteforce(qc, tq_off[c0:c1 + 1] - tq_off[c0], 10)
+        pos[c0:c1] = ids.cpu().numpy().view(np.uint32)
+    mine_s = time.perf_counter() - t0
+    log(f"mined the exact top-10 of {n_mine} training queries in {mine_s:.1f} s")
+    del tix
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(w["train_seed"] + 2)
+    neg = rng.integers(0, n_tr, size=(n_mine, n_neg))
+    qid = n_tr + np.arange(n_mine)
+    trip = np.stack([np.repeat(qid, 10 * n_neg), np.repeat(pos.reshape(-1), n_neg), np.tile(neg, (1, 10)).reshape(-1)],
+                    axis=1).astype(np.uint32)
+    coll = torch.cat([tdb.vectors, tq]).contiguous()
+    coll_off = np.concatenate([tdb.offsets, tdb.offsets[-1] + tq_off[1:]])
+    del tdb
+    weights = bvs.mlp_weights(d, H, L, seed=w["train_seed"] + 3)
+    tc = bvs.TrainConfig(d, H, L, k_wta, args.train_batch, args.train_epochs, args.train_lr, args.train_tau,
+                         args.train_margin, 0, w["train_seed"] + 4)
+    max_rows = args.train_batch * 3 * int(np.diff(coll_off).max())
+    trainer = bvs.Trainer(tc, coll, coll_off, max_rows)
+    loss0, _ = trainer.gradients(weights, trip[: args.train_batch])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = trainer.train(weights, trip)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    loss1, _ = trainer.gradients(weights, trip[: args.train_batch])
+    log(f"trained on {len(trip)} triplets in {train_s:.1f} s: epoch losses {losses}, first batch {loss0:.2f} -> "
+        f"{loss1:.2f}")
+    del trainer, coll
+    torch.cuda.empty_cache()
+
+    log(f"evaluation corpus: {w['n_sets']} sets (d={d}, seed 0)")
+    db = synth.make_database(w["n_sets"], w["size_lo"], w["size_hi"], d, w["n_topics"], seed=0, device=dev)
+    q, q_off, _ = synth.make_subset_queries(db, w["n_queries"], seed=1)
+    q = q.contiguous()
+    n_q = w["n_queries"]
+    NQ = int(q_off[-1])
+    nb = min(args.brute_queries, n_q)
+    truth = None
+    rows = []
+    out = (torch.empty(n_q, k, dtype=torch.int32, device=dev), torch.empty(n_q, k, dtype=torch.float32, device=dev),
+           torch.empty(n_q, dtype=torch.int32, device=dev))
+    counters = None
+    for form in ("random", "learned"):
+        for T in [int(x) for x in args.sweep_t.split(",")]:
+            p = bvs.Params.make(dim=d, code_bits=L, fan_in=w["fan_in"], wta_k=k_wta, top_t=T, seed=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ix = bvs.Index(p, db.vectors, db.offsets, mlp=(H, weights) if form == "learned" else None)
+            torch.cuda.synchronize()
+            build_s = time.perf_counter() - t0
+            ws = ix.search_workspace(n_q, NQ)
+            for i in range(args.warmup):
+                ix.search(q, q_off, k, ws=ws, out=out)
+            bvs.profile_enable(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                ix.search(q, q_off, k, ws=ws, out=out)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            st = {nm: ms / max(1, c) for nm, (ms, c) in bvs.profile_read().items() if c}
+            bvs.profile_enable(False)
+            if form == "learned" and T == w["top_t"]:
+                bvs.profile_enable(False, counters=True)
+                ix.search(q, q_off, k, ws=ws, out=out)
+                counters = dict(bvs.profile_counters())
+                bvs.profile_enable(False)
+            ids = out[0].cpu().numpy().view(np.uint32)
+            if truth is None:
+                qb = q[: int(q_off[nb])].contiguous()
+                t1 = time.perf_counter()
+                bids, _, _ = ix.bruteforce(qb, q_off[: nb + 1], k)
+                torch.cuda.synchronize()
+                brute_qps = nb / (time.perf_counter() - t1)
+                truth = bids.cpu().numpy().view(np.uint32)
+            recall = float(np.mean([len(set(ids[i].tolist()) & set(truth[i].tolist())) / k for i in range(nb)]))
+            rows.append({"form": form, "top_t": T, "qps": n_q * args.steps / el, "recall_at_10": recall,
+                         "ms_per_step": el * 1e3 / args.steps, "build_s": build_s, "stages_ms_per_step": st})
+            log(f"{form} T={T}: {rows[-1]['qps']:.0f} q/s, recall@10 {recall:.4f} (build {build_s:.1f} s)")
+            del ix, ws
+            torch.cuda.empty_cache()
+    at_t = {r["form"]: r for r in rows if r["top_t"] == w["top_t"]}
+    keep = "learned" if at_t["learned"]["recall_at_10"] >= at_t["random"]["recall_at_10"] else "random"
+    best = at_t[keep]
+    roof = None
+    if counters is not None and keep == "learned":
+        work = {k2: float(v) for k2, v in counters.items()}
+        roof, _ = rooflines(best["stages_ms_per_step"], work, L, -(-d // 64) * 64, "k_haus_cand", "k_haus.hip")
+    return {
+        "metric": METRIC,
+        "value": best["qps"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": best["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={d}, {w['n_topics']} topics; "
+                         f"learned projection {d}->{H} relu->{L}, WTA k={k_wta}; A=3, M=1, T={w['top_t']}; "
+                         f"{n_q} subset queries per step; top-{k}; projection in use: {keep}"),
+            "n_sets": w["n_sets"], "n_queries": n_q, "query_vectors": NQ,
+        },
+        "projection_in_use": keep,
+        "training": {"corpus_sets": n_tr, "mined_queries": n_mine, "triplets": int(len(trip)), "mine_s": mine_s,
+                     "train_s": train_s, "epoch_losses": losses, "first_batch_loss_before_after": [loss0, loss1],
+                     "batch_triplets": args.train_batch, "lr": args.train_lr, "tau": args.train_tau,
+                     "margin": args.train_margin, "hidden": H},
+        "sweep": rows,
+        "bruteforce_qps": brute_qps,
+        "recall_sample_queries": nb,
+        "roofline": roof,
+        "cpu_baseline": None,
+        "total_s": time.perf_counter() - t_start,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -509,6 +670,10 @@ def main():
         w["top_t"] = args.top_t
     cfg = dict(seed=0, dim=w["dim"], code_bits=w["code_bits"], fan_in=w["fan_in"], wta_k=w["wta_k"], A=3, M=1,
                top_t=w["top_t"], k=w["k"])
+
+    if args.workload == "learned":
+        print(json.dumps(learned_bench(args, w, cfg, dev)), flush=True)
+        return
 
     log(f"generating {w['n_sets']} sets (d={w['dim']}) on the GPU")
     t0 = time.perf_counter()

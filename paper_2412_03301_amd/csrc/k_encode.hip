@@ -92,9 +92,16 @@ template <int R>
 __device__ __forceinline__ void hash_keys(const int16_t* __restrict__ av, const uint16_t* __restrict__ idx,
                                           uint32_t SP, uint32_t koff, uint32_t lgL, uint32_t L,
                                           uint32_t lane, uint32_t (&key)[R]) {
+  // The row addresses depend only on the lane; rebuilding them per vector
+  // from an opaque copy of the lane keeps the compiler from holding all R of
+  // them live across the vector loop (which spills at R = 64).
+  uint32_t ln = lane;
+  asm volatile("" : "+v"(ln));
 #pragma unroll
   for (int t = 0; t < R; ++t) {
-    const uint32_t j = lane + 64u * t;
+    // bound the gathers in flight
+    if (t % 8 == 0) asm volatile("" ::: "memory");
+    const uint32_t j = ln + 64u * t;
     const uint16_t* row = idx + j * SP;
     int y = 0;
     for (uint32_t i0 = 0; i0 < SP; i0 += 8) {
@@ -112,9 +119,11 @@ __device__ __forceinline__ uint32_t kth_largest(const uint32_t (&key)[R], uint32
   uint32_t theta = 0;
   for (int b = topbit; b >= 0; --b) {
     const uint32_t cand = theta | (1u << b);
-    uint32_t cnt = 0;
+    // per-lane count, then one wave sum (no per-key ballots held in scalars)
+    uint32_t local = 0;
 #pragma unroll
-    for (int t = 0; t < R; ++t) cnt += popc64(ballot(key[t] >= cand));
+    for (int t = 0; t < R; ++t) local += key[t] >= cand ? 1u : 0u;
+    const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(local));
     if (cnt == k) {
       // Exactly k keys reach the prefix: the k-th largest is their minimum.
       uint32_t mn = 0xFFFFFFFFu;
@@ -157,7 +166,7 @@ size_t encode_lds_bytes(const HashGeom& g, uint32_t waves) {
 }
 
 template <int R>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_encode_vectors(HashGeom g, const int8_t* __restrict__ hi, const uint8_t* __restrict__ lo, uint64_t n,
                  uint64_t* __restrict__ codes, int topbit) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -246,20 +255,26 @@ static hipError_t dispatch_R(uint32_t R, F&& f) {
   }
 }
 
+// Waves per workgroup: the projection table fills most of the LDS, so one
+// workgroup runs per CU; queries use 16 waves (4 per SIMD), the set kernel,
+// whose per-set counters need more registers, 8.
+static constexpr uint32_t kEncodeVecWaves = 16;
 static constexpr uint32_t kEncodeWaves = 8;
 
 hipError_t launch_encode_vectors(const HashGeom& g, const int8_t* hi, const uint8_t* lo, uint64_t n,
                                  uint64_t* codes, int n_cu, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  const size_t lds = encode_lds_bytes(g, kEncodeWaves);
+  // 8 waves when 16 staging slots would not fit beside the table
+  const uint32_t nw = encode_lds_bytes(g, kEncodeVecWaves) <= 160 * 1024 ? kEncodeVecWaves : kEncodeWaves;
+  const size_t lds = encode_lds_bytes(g, nw);
   const int topbit = key_topbit(g);
-  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kEncodeWaves - 1) / kEncodeWaves, (uint64_t)n_cu);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + nw - 1) / nw, (uint64_t)n_cu);
   return dispatch_R(g.R, [&](auto rc) -> hipError_t {
     constexpr int R = decltype(rc)::value;
     hipError_t e = hipFuncSetAttribute((const void*)k_encode_vectors<R>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_encode_vectors<R>, dim3(grid), dim3(64 * kEncodeWaves), lds, st, g, hi, lo, n,
+    hipLaunchKernelGGL(k_encode_vectors<R>, dim3(grid), dim3(64 * nw), lds, st, g, hi, lo, n,
                        codes, topbit);
     return hipGetLastError();
   });

@@ -186,6 +186,11 @@ WORKLOADS = {
     # the scale generator at d = 768, for the BF16 / FP8 re-rank
     "precision": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=768, n_topics=10_000,
                       code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10),
+    # learned projection: trained on a separate 100k-set corpus (its own seed)
+    # with triplets mined by brute force, evaluated on the precision database
+    "learned": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=768, n_topics=10_000,
+                    code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10,
+                    hidden=1024, train_sets=100_000, train_seed=100, mine_queries=20_000, negatives=10),
     # the scale database, searched by fresh-entity queries of 1-256 vectors
     "batched": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
                     code_bits=4096, fan_in=16, wta_k=64, n_queries=4096, max_query=256, top_t=1000, k=10),
