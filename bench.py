@@ -140,21 +140,31 @@ def cpu_baseline(db_cpu, offsets, q_cpu, q_off, cfg, n_sets_full, sample_sets, s
     }
 
 
-def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file):
+def sketch_rows(ix, q, q_off):
+    """Sum over the queries of |S_Q|: the tile rows the bit-sliced filter
+    adds for every set (computed outside the timed region)."""
+    import numpy as np
+    _, sq, _ = ix.query_sketch(q, q_off)
+    return float(np.unpackbits(sq.cpu().numpy().view(np.uint8)).sum())
+
+
+def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=None):
     """Roofline of the dominant stage (filter or re-rank) from its
     algorithmic work per launch and its measured time per launch."""
     csrc = os.path.join(ROOT, "paper_2412_03301_amd", "csrc")
     dominant = max(("filter", "rerank"), key=lambda s2: per_step.get(s2, 0.0))
     rer_bytes = work["rerank_vectors"] * (dim_padded * 2 + 4)
-    if dominant == "filter":
-        # member-only scoring: per (member set, query) pair, one XOR and one
-        # popcount per 32-bit word of the L-bit sketches
-        ops = work["filter_pairs"] * (L // 32) * 2
+    if dominant == "filter" and n_sets and work.get("sketch_rows"):
+        # bit-sliced counting: every query adds its |S_Q| tile rows for every
+        # set; one 3:2 carry-save compression (two 3-input logic ops) per
+        # row and 32-bit word of 32 sets
+        words = -(-n_sets // 32)
+        ops = work["sketch_rows"] * words * 2
         ach = ops / (per_step["filter"] / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_TOPS, "unit": "Tops/s", "frac": ach / ALU_PEAK_TOPS,
-                "kernel": "k_filter_sparse<32,true>",
-                "algorithmic": f"{work['filter_pairs']:.4g} member pairs x {L // 32} words x 2 int32 ops per launch",
-                "traffic": traffic_from_profiles(os.path.join(csrc, "k_filter.hip"), "k_filter_sparse")}
+                "kernel": "k_filter_sliced<4,9>",
+                "algorithmic": f"{work['sketch_rows']:.4g} query rows x {words} words x 2 int32 ops per launch",
+                "traffic": traffic_from_profiles(os.path.join(csrc, "k_sliced.hip"), "k_filter_sliced")}
     else:
         ach = rer_bytes / (per_step["rerank"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
@@ -281,7 +291,9 @@ def batched(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
         recall, brute_qps = brute_recall(ix, q, q_off, ids, k, nb)
         log(f"brute force on {nb} queries: {brute_qps:.1f} q/s; recall@10 {recall:.4f}")
 
-    roof, rerank_roof = rooflines(per_step, work, w["code_bits"], ix.dim_padded, "k_haus_queue", "k_batch.hip")
+    work["sketch_rows"] = sketch_rows(ix, q, q_off)
+    roof, rerank_roof = rooflines(per_step, work, w["code_bits"], ix.dim_padded, "k_haus_queue", "k_batch.hip",
+                                  w["n_sets"])
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
@@ -768,7 +780,8 @@ def main():
     per_step = {name: ms / max(1, calls) for name, (ms, calls) in stages.items() if calls}
     work = {k2: v / args.steps for k2, v in counters.items()}
     L = w["code_bits"]
-    roof, rerank_roof = rooflines(per_step, work, L, ix.dim_padded, "k_haus_cand", "k_haus.hip")
+    work["sketch_rows"] = sketch_rows(ix, q, q_off)
+    roof, rerank_roof = rooflines(per_step, work, L, ix.dim_padded, "k_haus_cand", "k_haus.hip", w["n_sets"])
 
     cpu = None
     if not args.no_cpu_baseline:

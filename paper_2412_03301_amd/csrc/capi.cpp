@@ -280,6 +280,7 @@ struct bvs_index {
   uint8_t* cnt;
   uint64_t* bits;
   uint64_t* planes;   // [L][ld/64]: bit j of plane p set when C^(j)[p] >= 1
+  uint16_t* spop;     // [ld]: |B| of every set (0 for padding)
   // attached precision copies, by format (BVS_LOWP_BF16, BVS_LOWP_FP8)
   uint8_t* lowp[3] = {nullptr, nullptr, nullptr};
   float* lowp_scale[3] = {nullptr, nullptr, nullptr};
@@ -303,6 +304,7 @@ void layout_index(Carver& c, const Geometry& g, uint64_t n, uint64_t N, bvs_inde
   ix->cnt = c.take<uint8_t>((uint64_t)g.L * ld);
   ix->bits = c.take<uint64_t>((uint64_t)g.R * ld);
   ix->planes = c.take<uint64_t>((uint64_t)g.L * (ld / 64));
+  ix->spop = c.take<uint16_t>(ld);
   ix->ld = ld;
 }
 
@@ -341,7 +343,11 @@ struct QueryWs {
   uint32_t* cand_count;   // [n_q]
   uint64_t* cand_app;     // [n_q][cap]
   uint32_t cap;
-  uint64_t* f1;           // [n_q][ld/64] first-layer bitmaps
+  uint32_t* lists;        // [n_q rounded up to 32][4][L + 48] row lists by rank
+  uint32_t* qbits;        // [n_q]
+  uint32_t* order;        // [n_q]
+  uint32_t* sbits;        // [n_q]
+  uint32_t* gsteps;       // [n_q rounded up to 32, / 16]
   uint32_t* f2_ids;
   uint16_t* f2_scores;
   uint32_t* f2_count;
@@ -381,6 +387,15 @@ bool use_sparse_filter(uint32_t M) {
   return M >= 1;
 }
 
+// Bit-sliced scoring for the first layer M = 1 (the usual setting) when the
+// sketch fits a tile (L a multiple of 256, at most 4096), unless
+// BVS_FILTER=sparse or dense asks for another kernel.
+bool use_sliced_filter(const Geometry& g) {
+  const char* e = std::getenv("BVS_FILTER");
+  if (e && (std::strcmp(e, "dense") == 0 || std::strcmp(e, "sparse") == 0)) return false;
+  return g.M == 1 && g.L % 256 == 0 && g.L <= 4096;
+}
+
 bool force_dense_select() {
   const char* e = std::getenv("BVS_SELECT");
   return e && std::strcmp(e, "dense") == 0;
@@ -410,7 +425,11 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->cutoff = c.take<uint32_t>(n_q);
   w->cand_count = c.take<uint32_t>(n_q);
   w->cand_app = c.take<uint64_t>((uint64_t)n_q * w->cap);
-  w->f1 = c.take<uint64_t>((uint64_t)n_q * (ix->ld / 64));
+  w->lists = c.take<uint32_t>(align_up(n_q, 32) * sliced_parts() * (g.L + 48));
+  w->qbits = c.take<uint32_t>(n_q);
+  w->order = c.take<uint32_t>(n_q);
+  w->sbits = c.take<uint32_t>(n_q);
+  w->gsteps = c.take<uint32_t>(align_up(n_q, 32) / 16);
   w->f2_ids = c.take<uint32_t>((uint64_t)n_q * g.T);
   w->f2_scores = c.take<uint16_t>((uint64_t)n_q * g.T);
   w->f2_count = c.take<uint32_t>(n_q);
@@ -520,7 +539,15 @@ FilterArgs filter_args(const bvs_index* ix, uint32_t n_q, const QueryWs& w) {
   a.cap = w.cap;
   a.cand_count = w.cand_count;
   a.planes = ix->planes;
-  a.f1 = w.f1;
+  a.L = g.L;
+  a.spop = ix->spop;
+  a.parts = sliced_parts();
+  a.LP = g.L + 48;
+  a.lists = w.lists;
+  a.qbits = w.qbits;
+  a.order = w.order;
+  a.sbits = w.sbits;
+  a.gsteps = w.gsteps;
   a.stats = nullptr;   // set by the caller when profiling
   return a;
 }
@@ -542,13 +569,14 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
   if (!force_dense_select()) {
     const uint32_t n_blocks = (uint32_t)(ix->ld / 256);
     const bool sparse = use_sparse_filter(g.M);
+    const bool sliced = use_sliced_filter(g);
     uint32_t* d_fail = w.status + 1;
     HIP_TRY(launch_fill_u32(w.cand_count, n_q, 0, st));
     HIP_TRY(launch_fill_u32(d_fail, 1, 0, st));
     HIP_TRY(staged(prof, S_CUTOFF, [&]() -> hipError_t {
       hipError_t e;
-      if (sparse && g.M == 1) {
-        e = launch_f1_bitmap(a, st);
+      if (sliced) {
+        e = launch_query_rows(a, w.sq, g.R, st);
         if (e != hipSuccess) return e;
       }
       if (ix->n <= w.cap) {
@@ -573,6 +601,11 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
       return launch_cutoff(w.sample, (uint32_t)S, g.L, r, n_q, w.cutoff, st);
     }));
     HIP_TRY(staged(prof, S_FILTER, [&]() -> hipError_t {
+      if (sliced) {
+        FilterArgs af = a;
+        af.fail = d_fail;
+        return launch_filter_sliced(af, st);
+      }
       return sparse ? launch_filter_sparse_append(a, st) : launch_filter_append(a, st);
     }));
     HIP_TRY(staged(prof, S_SELECT, [&] {
@@ -766,6 +799,7 @@ bvs_status bvs_build_index(const bvs_params* p, const float* d_vectors, const ui
     HIP_TRY(launch_encode_sets(hash_geom(ix), ix->hi, ix->lo, ix->offsets, n_sets, cnt_rm, bits_rm, ix->n_cu, st));
     HIP_TRY(launch_transpose_sketches(cnt_rm, bits_rm, n_sets, ix->ld, g.L, ix->cnt, ix->bits, st));
     HIP_TRY(launch_bitmap_planes(ix->cnt, ix->ld, g.L, ix->planes, st));
+    HIP_TRY(launch_set_weight(ix->bits, g.L / 128, ix->ld, ix->spop, st));
     return read_status(status, st, "database");
   };
   const bvs_status s = run();
@@ -1789,6 +1823,7 @@ bvs_status bvs_build_index_learned(const bvs_params* p, uint32_t hidden, const f
     }
     HIP_TRY(launch_transpose_sketches(cnt_rm, bits_rm, n_sets, ix->ld, g.L, ix->cnt, ix->bits, st));
     HIP_TRY(launch_bitmap_planes(ix->cnt, ix->ld, g.L, ix->planes, st));
+    HIP_TRY(launch_set_weight(ix->bits, g.L / 128, ix->ld, ix->spop, st));
     return read_status(status, st, "database");
   };
   const bvs_status s = run();

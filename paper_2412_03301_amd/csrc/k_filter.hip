@@ -151,26 +151,6 @@ hipError_t launch_filter_append(FilterArgs a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- member-only scoring
-// First-layer bitmaps of each query: f1[q][w] = OR over its A positions p of
-// planes[p][w] (M = 1), so that set j is in F1 exactly when bit j is set.
-__global__ void __launch_bounds__(256)
-k_f1_bitmap(const uint64_t* __restrict__ planes, uint64_t wpp, const uint32_t* __restrict__ pos, uint32_t A,
-            uint64_t* __restrict__ f1) {
-  const uint32_t q = blockIdx.y;
-  const uint64_t w = blockIdx.x * 256ull + threadIdx.x;
-  if (w >= wpp) return;
-  uint64_t m = 0;
-  for (uint32_t t = 0; t < A; ++t) m |= planes[(uint64_t)pos[(uint64_t)q * A + t] * wpp + w];
-  f1[(uint64_t)q * wpp + w] = m;
-}
-
-hipError_t launch_f1_bitmap(const FilterArgs& a, hipStream_t st) {
-  const uint64_t wpp = a.ld / 64;
-  hipLaunchKernelGGL(k_f1_bitmap, dim3((uint32_t)((wpp + 255) / 256), a.n_q), dim3(256), 0, st, a.planes, wpp, a.pos,
-                     a.A, a.f1);
-  return hipGetLastError();
-}
-
 // First-layer membership of the 256 sets of a tile for query q, as four
 // 64-bit masks (uniform across the wave).
 __device__ __forceinline__ void tile_members(const FilterArgs& a, uint32_t q, uint64_t tile0, uint32_t lane,
@@ -179,9 +159,18 @@ __device__ __forceinline__ void tile_members(const FilterArgs& a, uint32_t q, ui
 #pragma unroll
     for (int i = 0; i < 4; ++i) m[i] = vmask[i];
   } else if (a.M == 1) {
-    const cptr<uint64_t> f = as_const(a.f1) + (uint64_t)q * (a.ld / 64) + tile0 / 64;
+    // C[p] >= 1 for one of the query's A positions: OR of their bitmap rows
+    const cptr<uint64_t> pl = as_const(a.planes) + tile0 / 64;
+    const uint64_t wpp = a.ld / 64;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) m[i] = f[i] & vmask[i];
+    for (int i = 0; i < 4; ++i) m[i] = 0;
+    for (uint32_t t = 0; t < a.A; ++t) {
+      const uint64_t r = (uint64_t)as_const(a.pos)[(uint64_t)q * a.A + t] * wpp;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) m[i] |= pl[r + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] &= vmask[i];
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

@@ -65,8 +65,18 @@ struct FilterArgs {
   uint64_t* cand;              // append mode: [n_q][cap] keys (score << 32 | id)
   uint32_t cap;
   uint32_t* cand_count;        // append mode: [n_q]
-  const uint64_t* planes;      // membership bitmaps [L][ld/64] (first layer, M = 1)
-  uint64_t* f1;                // per-query first-layer bitmaps [n_q][ld/64] (M = 1)
+  const uint64_t* planes;      // position-major bitmaps [L][ld/64] (bit j of row p: set j has p)
+  uint32_t L;                  // sketch length
+  // bit-sliced scoring (see launch_filter_sliced)
+  const uint16_t* spop;        // |B| of every set [ld]
+  uint32_t parts;              // parts of a row list (4: 8 bytes of a tile row each)
+  uint32_t LP;                 // list stride, L + 48
+  uint32_t* lists;             // [n_q rounded up to 32][4][LP] row offsets by rank (bank-scheduled)
+  uint32_t* qbits;             // [n_q] |S_Q|
+  uint32_t* order;             // [n_q] queries by decreasing |S_Q| (blocks of 16)
+  uint32_t* sbits;             // [n_q] |S_Q| by rank
+  uint32_t* gsteps;            // [2 ceil(n_q / 32)] steps of 16 rows (per half of a rank pair)
+  uint32_t* fail;              // set to 1 when the result must come from the dense path
   unsigned long long* stats;   // work counters (see bvs_stage_times), may be null
   const uint32_t* run_if;      // dense mode: skip all work unless *run_if != 0 (may be null)
 };
@@ -76,9 +86,16 @@ hipError_t launch_filter_append(FilterArgs a, hipStream_t st);
 // Member-only scoring: tiles of 256 sets in LDS, first-layer members
 // compacted into lanes.  Sample mode writes member scores (the caller
 // pre-fills the sample buffer with 0xFFFF); append mode as above.
-hipError_t launch_f1_bitmap(const FilterArgs& a, hipStream_t st);
 hipError_t launch_filter_sparse_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st);
 hipError_t launch_filter_sparse_append(FilterArgs a, hipStream_t st);
+// Bit-sliced scoring (first layer M <= 1), append mode only: the same
+// appended keys as launch_filter_sparse_append.  launch_query_rows fills
+// lists, qbits and order from the query sketches sq [n_q][R] first.
+hipError_t launch_set_weight(const uint64_t* bits, uint32_t RC, uint64_t ld, uint16_t* w, hipStream_t st);
+hipError_t launch_query_rows(const FilterArgs& a, const uint64_t* sq, uint32_t R, hipStream_t st);
+hipError_t launch_filter_sliced(const FilterArgs& a, hipStream_t st);
+uint32_t sliced_parts();
+size_t sliced_lds_bytes(uint32_t L);
 hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_t r, uint32_t n_q,
                          uint32_t* cutoff, hipStream_t st);
 hipError_t launch_sort_append(const uint64_t* cand, const uint32_t* cand_count, const uint32_t* cutoff, uint32_t cap,

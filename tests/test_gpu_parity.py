@@ -173,6 +173,11 @@ VARIANTS = {
     "d768_fresh_queries": (600, 5, 60, 768, 10, 4096, 16, 64, 200, 6, 3, 1, 48),
     "big_queries": (500, 2, 30, 128, 6, 1024, 8, 32, 100, 4, 3, 1, 128),
     "sampled_cutoff_30k": (30000, 2, 16, 64, 300, 512, 4, 16, 100, 6, 3, 1, "subset"),
+    # more queries than one pass of the bit-sliced filter's waves
+    "many_queries": (2600, 2, 20, 64, 40, 1024, 4, 24, 60, 300, 3, 1, "subset"),
+    # long and short query sketches in one call: both bit-sliced instances
+    "mixed_sketches": (2000, 2, 20, 64, 30, 1024, 4, 32, 60, 70, 3, 1,
+                       [60, 1, 45, 2, 3, 1, 2] * 10),
 }
 
 
