@@ -348,6 +348,7 @@ struct QueryWs {
   uint32_t* order;        // [n_q]
   uint32_t* sbits;        // [n_q]
   uint32_t* gsteps;       // [n_q rounded up to 32, / 16]
+  uint32_t* any_long;     // [1]
   uint32_t* f2_ids;
   uint16_t* f2_scores;
   uint32_t* f2_count;
@@ -430,6 +431,7 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->order = c.take<uint32_t>(n_q);
   w->sbits = c.take<uint32_t>(n_q);
   w->gsteps = c.take<uint32_t>(align_up(n_q, 32) / 16);
+  w->any_long = c.take<uint32_t>(1);
   w->f2_ids = c.take<uint32_t>((uint64_t)n_q * g.T);
   w->f2_scores = c.take<uint16_t>((uint64_t)n_q * g.T);
   w->f2_count = c.take<uint32_t>(n_q);
@@ -548,6 +550,8 @@ FilterArgs filter_args(const bvs_index* ix, uint32_t n_q, const QueryWs& w) {
   a.order = w.order;
   a.sbits = w.sbits;
   a.gsteps = w.gsteps;
+  a.any_long = w.any_long;
+  a.fail = w.status + 1;   // raised when the dense path must answer
   a.stats = nullptr;   // set by the caller when profiling
   return a;
 }
@@ -590,7 +594,7 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
         e = launch_fill_u32((uint32_t*)w.sample, (uint64_t)n_q * nsb * 128, 0xFFFFFFFFu, st);
         if (e != hipSuccess) return e;
         as.stats = nullptr;
-        e = launch_filter_sparse_sample(as, nsb, st);
+        e = sliced ? launch_filter_sliced_sample(as, nsb, st) : launch_filter_sparse_sample(as, nsb, st);
       } else {
         e = launch_filter_sample(as, nsb, st);
       }
@@ -601,11 +605,7 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
       return launch_cutoff(w.sample, (uint32_t)S, g.L, r, n_q, w.cutoff, st);
     }));
     HIP_TRY(staged(prof, S_FILTER, [&]() -> hipError_t {
-      if (sliced) {
-        FilterArgs af = a;
-        af.fail = d_fail;
-        return launch_filter_sliced(af, st);
-      }
+      if (sliced) return launch_filter_sliced(a, st);
       return sparse ? launch_filter_sparse_append(a, st) : launch_filter_append(a, st);
     }));
     HIP_TRY(staged(prof, S_SELECT, [&] {

@@ -59,11 +59,12 @@ k_query_bits(const uint64_t* __restrict__ sq, uint32_t R, uint32_t* __restrict__
 // One workgroup: queries ordered by list length (in blocks of 16 rows),
 // longest first, so that the queries sharing a wave do similar work.  The
 // order within a length is unspecified (results do not depend on it).
-// Also writes |S_Q| by rank.
+// Also writes |S_Q| by rank, and clears the flag of long-sketch pairs.
 __global__ void __launch_bounds__(1024)
 k_order_queries(const uint32_t* __restrict__ qbits, uint32_t n_q, uint32_t nbins, uint32_t* __restrict__ order,
-                uint32_t* __restrict__ sbits) {
+                uint32_t* __restrict__ sbits, uint32_t* __restrict__ any_long) {
   extern __shared__ uint32_t hist[];
+  if (threadIdx.x == 0) *any_long = 0;
   for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   for (uint32_t q = threadIdx.x; q < n_q; q += blockDim.x) {
@@ -104,7 +105,7 @@ k_order_queries(const uint32_t* __restrict__ qbits, uint32_t n_q, uint32_t nbins
 // by rank; part k (of 4) adds 8 k bytes to every row offset.
 __global__ void __launch_bounds__(512)
 k_pass_lists(const uint64_t* __restrict__ sq, uint32_t R, uint32_t L, uint32_t n_q, const uint32_t* __restrict__ order,
-             uint32_t LP, uint32_t* __restrict__ lists, uint32_t* __restrict__ gsteps) {
+             uint32_t LP, uint32_t* __restrict__ lists, uint32_t* __restrict__ gsteps, uint32_t* __restrict__ any_long) {
   __shared__ uint64_t sk[kPairRanks][64];   // sketches of the 32 queries (R <= 64)
   __shared__ uint32_t cnt[8][4][4];         // [group][query][class]
   __shared__ uint32_t seg_len[8][16];
@@ -170,6 +171,7 @@ k_pass_lists(const uint64_t* __restrict__ sq, uint32_t R, uint32_t L, uint32_t n
   for (int i = 0; i < 8; ++i) dmax = max(dmax, depth[i]);
   const uint32_t nblk = (dmax + 15) / 16;
   if (threadIdx.x < 2) gsteps[2 * pair + threadIdx.x] = nblk;
+  if (threadIdx.x == 0 && nblk > kSmallSteps) atomicOr(any_long, 1u);
   const uint32_t part = lane & 3, c = (lane >> 2) & 3, r = lane >> 4;
   const uint64_t cmask = 0x1111111111111111ull << c;
   const uint32_t zero_row = (L + c) * kRowBytes + part * 8;
@@ -207,12 +209,12 @@ hipError_t launch_query_rows(const FilterArgs& a, const uint64_t* sq, uint32_t R
   if (e != hipSuccess) return e;
   const uint32_t nbins = a.L / 16 + 1;
   hipLaunchKernelGGL(k_order_queries, dim3(1), dim3(1024), nbins * 4, st, (const uint32_t*)a.qbits, a.n_q, nbins,
-                     a.order, a.sbits);
+                     a.order, a.sbits, a.any_long);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint32_t pairs = (a.n_q + kPairRanks - 1) / kPairRanks;
   hipLaunchKernelGGL(k_pass_lists, dim3(pairs), dim3(512), 0, st, sq, R, a.L, a.n_q, (const uint32_t*)a.order, a.LP,
-                     a.lists, a.gsteps);
+                     a.lists, a.gsteps, a.any_long);
   return hipGetLastError();
 }
 
@@ -332,42 +334,29 @@ __device__ __forceinline__ void add_sixteens(Words<W> x, Slices<W, S>& c) {
   }
 }
 
-// Grid: tiles of 256 sets, XCD-aware (workgroup b runs on XCD b % 8 and takes
-// tile (b % 8) * per_xcd + b / 8, so that the workgroups of one XCD share the
-// cache lines of neighbouring tiles).  16 waves; lane = (query slot, part):
-// the lane counts W words (32 W sets) of its query's tile row, in S counter
-// slices.  Two instances share the work by rank pairs (kPairRanks ranks):
+// One tile of 256 sets for the queries of part q_part (of q_parts) of the
+// wave passes: stage the tile's rows, count, then append the members that
+// pass the cutoff (SAMPLE false) or write every member's score to block
+// out_block of the sample rows (SAMPLE true).  16 waves; lane = (query
+// slot, part): the lane counts W words (32 W sets) of its query's tile row,
+// in S counter slices.  Two instances share the work by rank pairs
+// (kPairRanks ranks):
 //   W = 4, S = 9    pairs of at most kSmallSteps steps (|S_Q| < 512): one
 //                   wave pass takes a whole pair
-//   W = 2, S = 13   the other pairs (long sketches), half a pair per pass;
-//                   with none, its workgroups return before staging
-template <int W, int S>
-__global__ void __launch_bounds__(1024)
-k_filter_sliced(FilterArgs a, uint32_t per_xcd, uint32_t n_tiles) {
+//   W = 2, S = 13   the other pairs (long sketches), half a pair per pass
+template <int W, int S, bool SAMPLE>
+__device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, uint32_t out_block, uint32_t q_part,
+                                            uint32_t q_parts, uint8_t* smem) {
   constexpr bool kSmall = S == 9;
   constexpr uint32_t PARTS = 8 / W;           // lanes per query
   constexpr uint32_t QPW = BVS_WAVE / PARTS;  // queries per wave pass
   constexpr uint32_t NW = 16;
   constexpr int CB = kSmall ? 12 : 13;        // bits of dot + (2048 - u)
-  extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t L = a.L;
-  const uint32_t n_pairs = (a.n_q + kPairRanks - 1) / kPairRanks;
   auto big = [&](uint32_t pr) { return as_const(a.gsteps)[2 * pr] > kSmallSteps; };
-  if constexpr (!kSmall) {
-    bool any = false;
-    for (uint32_t pr = 0; pr < n_pairs && !any; ++pr) any = big(pr);
-    if (!any) return;
-  }
   uint8_t* rows = smem;                                           // [L + 4][32 B]
   uint32_t* vsl = (uint32_t*)(smem + (size_t)(L + 4) * kRowBytes);  // [2][kVSlices][8]
   uint16_t* nset = (uint16_t*)(vsl + 2 * kVSlices * 8);           // [256]
-  const uint32_t tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (tile >= n_tiles) return;
-  if (lds_address(smem) != 0) {
-    // the row offsets would miss the tile: let the dense path answer
-    if (threadIdx.x == 0) atomicOr(a.fail, 1u);
-    return;
-  }
   const uint64_t tile0 = (uint64_t)tile * 256;
   const uint64_t wpp = a.ld / 64;
   for (uint32_t i = threadIdx.x; i < 2 * L; i += blockDim.x) {
@@ -404,7 +393,7 @@ k_filter_sliced(FilterArgs a, uint32_t per_xcd, uint32_t n_tiles) {
     valid.v[i] = b >= a.n_sets ? 0u : (a.n_sets - b >= 32 ? ~0u : (1u << (a.n_sets - b)) - 1u);
   }
   uint32_t pairs = 0;
-  for (uint32_t qb0 = w * QPW; qb0 < a.n_q; qb0 += NW * QPW) {
+  for (uint32_t qb0 = (w + NW * q_part) * QPW; qb0 < a.n_q; qb0 += NW * q_parts * QPW) {
     if (big(qb0 / kPairRanks) == kSmall) continue;   // the other instance's pass
     const uint32_t qi = qb0 + slot;
     const bool active = qi < a.n_q;
@@ -458,6 +447,23 @@ k_filter_sliced(FilterArgs a, uint32_t per_xcd, uint32_t n_tiles) {
     }
 #pragma unroll
     for (int i = 0; i < W; ++i) pairs += popc32(m.v[i]);
+    if constexpr (SAMPLE) {
+      // every member's score: |S_Q| + |B| - 2 dot
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        uint32_t pw = m.v[i];
+        while (pw) {
+          const uint32_t sb = (uint32_t)__builtin_ctz(pw);
+          pw &= pw - 1;
+          uint32_t dot = 0;
+#pragma unroll
+          for (int k = 0; k < S; ++k) dot |= ((c.s[k].v[i] >> sb) & 1u) << k;
+          const uint32_t jt = 32u * (part * W + i) + sb;
+          a.scores[(uint64_t)q * a.ld_out + (uint64_t)out_block * 256 + jt] = (uint16_t)(qbq + nset[jt] - 2 * dot);
+        }
+      }
+      continue;
+    }
 
     // score <= cut  <=>  dot + (2048 - u) >= 2048 + g, with g = ceil((|S_Q| - cut) / 2)
     // and u = ceil(|B| / 2) (|S_Q| - cut even) or floor(|B| / 2) (odd);
@@ -514,13 +520,43 @@ k_filter_sliced(FilterArgs a, uint32_t per_xcd, uint32_t n_tiles) {
       }
     }
   }
-  // (no static LDS in this kernel: the tile starts at LDS address 0, so the
-  // row offsets are addresses)
-  if (a.stats) {
+  if (!SAMPLE && a.stats) {
     const uint32_t wp = wave_sum_u32(pairs);
     if (lane == 0 && wp) atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * kStatCounters], (unsigned long long)wp);
   }
 }
+
+// Virtual blocks vb = blockIdx.x, blockIdx.x + gridDim.x, ... below n_vb.
+// Append mode: vb is a tile, XCD-aware (workgroup b runs on XCD b % 8, and
+// vb takes tile (vb % 8) * per_xcd + vb / 8, so that the workgroups of one
+// XCD share the cache lines of neighbouring tiles).  Sample mode: vb =
+// (sample block, query part).  The long-sketch instance runs one workgroup
+// per compute unit and returns at once unless some pair needs it.
+template <int W, int S, bool SAMPLE>
+__global__ void __launch_bounds__(1024)
+k_filter_sliced(FilterArgs a, uint32_t per_xcd, uint32_t n_tiles, uint32_t n_vb, uint32_t q_parts) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  if (S != 9 && *(const volatile uint32_t*)a.any_long == 0) return;
+  if (lds_address(smem) != 0) {
+    // (no static LDS in this kernel: the tile starts at LDS address 0, so
+    // the row offsets are addresses; otherwise let the dense path answer)
+    if (threadIdx.x == 0) atomicOr(a.fail, 1u);
+    return;
+  }
+  for (uint32_t vb = blockIdx.x; vb < n_vb; vb += gridDim.x) {
+    uint32_t tile, out_block = 0, q_part = 0;
+    if (SAMPLE) {
+      out_block = vb / q_parts;
+      q_part = vb % q_parts;
+      tile = out_block * a.block_stride;
+    } else {
+      tile = (vb % 8) * per_xcd + vb / 8;
+    }
+    if (tile < n_tiles) sliced_tile<W, S, SAMPLE>(a, tile, out_block, q_part, SAMPLE ? q_parts : 1, smem);
+    __syncthreads();
+  }
+}
+
 
 // Lists hold four parts (8 bytes of a tile row each); the 4-word instance
 // uses parts 0 and 2.
@@ -528,21 +564,38 @@ uint32_t sliced_parts() { return 4u; }
 
 size_t sliced_lds_bytes(uint32_t L) { return (size_t)(L + 4) * kRowBytes + 2 * kVSlices * 32 + 512; }
 
-hipError_t launch_filter_sliced(const FilterArgs& a, hipStream_t st) {
-  if (a.n_q == 0) return hipSuccess;
+template <bool SAMPLE>
+static hipError_t go_sliced(const FilterArgs& a, uint32_t n_vb, uint32_t q_parts, hipStream_t st) {
   if (a.L > 4096 || a.L % 256 != 0 || a.ld % 256 != 0 || a.parts != 4) return hipErrorInvalidValue;
   const uint32_t n_tiles = (uint32_t)(a.ld / 256);
   const uint32_t per_xcd = (n_tiles + 7) / 8;
   const size_t lds = sliced_lds_bytes(a.L);
-  auto go = [&](auto kern) -> hipError_t {
+  auto go = [&](auto kern, uint32_t grid) -> hipError_t {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(per_xcd * 8), dim3(1024), lds, st, a, per_xcd, n_tiles);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, st, a, per_xcd, n_tiles, n_vb, q_parts);
     return hipGetLastError();
   };
-  hipError_t e = go(k_filter_sliced<4, 9>);
+  hipError_t e = go(k_filter_sliced<4, 9, SAMPLE>, n_vb);
   if (e != hipSuccess) return e;
-  return go(k_filter_sliced<2, 13>);
+  return go(k_filter_sliced<2, 13, SAMPLE>, std::min(n_vb, 256u));
+}
+
+hipError_t launch_filter_sliced(const FilterArgs& a, hipStream_t st) {
+  if (a.n_q == 0) return hipSuccess;
+  const uint32_t n_tiles = (uint32_t)(a.ld / 256);
+  return go_sliced<false>(a, (n_tiles + 7) / 8 * 8, 1, st);
+}
+
+hipError_t launch_filter_sliced_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st) {
+  if (a.n_q == 0) return hipSuccess;
+  const uint32_t nb = (uint32_t)(a.ld / 256);
+  a.block_stride = std::max(1u, nb / n_sample_blocks);
+  a.ld_out = (uint64_t)n_sample_blocks * 256;
+  // several workgroups per sample block, each a share of the wave passes
+  const uint32_t passes = (a.n_q + 16 * kPairRanks - 1) / (16 * kPairRanks);
+  const uint32_t q_parts = std::max(1u, std::min(passes, 4u));
+  return go_sliced<true>(a, n_sample_blocks * q_parts, q_parts, st);
 }
 
 }  // namespace bvs

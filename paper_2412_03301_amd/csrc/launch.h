@@ -77,6 +77,7 @@ struct FilterArgs {
   uint32_t* sbits;             // [n_q] |S_Q| by rank
   uint32_t* gsteps;            // [2 ceil(n_q / 32)] steps of 16 rows (per half of a rank pair)
   uint32_t* fail;              // set to 1 when the result must come from the dense path
+  uint32_t* any_long;          // 1 when some rank pair needs the long-sketch instance
   unsigned long long* stats;   // work counters (see bvs_stage_times), may be null
   const uint32_t* run_if;      // dense mode: skip all work unless *run_if != 0 (may be null)
 };
@@ -94,6 +95,10 @@ hipError_t launch_filter_sparse_append(FilterArgs a, hipStream_t st);
 hipError_t launch_set_weight(const uint64_t* bits, uint32_t RC, uint64_t ld, uint16_t* w, hipStream_t st);
 hipError_t launch_query_rows(const FilterArgs& a, const uint64_t* sq, uint32_t R, hipStream_t st);
 hipError_t launch_filter_sliced(const FilterArgs& a, hipStream_t st);
+// Sample mode: the member scores of n_sample_blocks spread tiles, written to
+// scores[q][block * 256 + set] (the caller pre-fills 0xFFFF), as the
+// member-only sample; lists as for launch_filter_sliced.
+hipError_t launch_filter_sliced_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st);
 uint32_t sliced_parts();
 size_t sliced_lds_bytes(uint32_t L);
 hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_t r, uint32_t n_q,
