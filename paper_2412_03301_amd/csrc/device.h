@@ -96,6 +96,35 @@ __device__ __forceinline__ uint32_t row16_min_u32(uint32_t v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t row16_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xF, 0xF, false));
+  return v;
+}
+
+// Minimum / maximum over lanes l, l ^ 16, l ^ 32, l ^ 48 (the four DPP rows)
+// with the gfx950 row-swap instructions: v_permlane32_swap exchanges the
+// upper half of one operand with the lower half of the other, and
+// v_permlane16_swap the odd rows of one with the even rows of the other, so
+// swapping a value with itself pairs lane l with l ^ 32, then with l ^ 16.
+__device__ __forceinline__ uint32_t rows4_min_u32(uint32_t v) {
+  const auto a = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  v = min((uint32_t)a[0], (uint32_t)a[1]);
+  const auto b = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return min((uint32_t)b[0], (uint32_t)b[1]);
+}
+__device__ __forceinline__ uint32_t rows4_max_u32(uint32_t v) {
+  const auto a = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  v = max((uint32_t)a[0], (uint32_t)a[1]);
+  const auto b = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return max((uint32_t)b[0], (uint32_t)b[1]);
+}
+
+// Maximum over the wave without LDS traffic (every lane gets it).
+__device__ __forceinline__ uint32_t wave_max_dpp_u32(uint32_t v) { return rows4_max_u32(row16_max_u32(v)); }
+
 // One 16x16x64 int8 matrix-core step with int32 accumulation:
 //   C[i][j] += sum_k A[i][k] * B[k][j]
 // A row i and B column j both come from lane (i or j) + 16 * g, which holds

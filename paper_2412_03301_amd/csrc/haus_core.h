@@ -73,10 +73,13 @@ __device__ __forceinline__ void tile_products(const v4i (&ah)[KS], const v4i (&a
 
 // Squared Hausdorff distance (2^24-scaled) of database set [o0, o0 + m)
 // against the query (HASG: some query tiles may come from global memory).
-// The set is abandoned, returning kAbandoned, as soon as the largest
-// completed column minimum (a lower bound of the result) exceeds `bound`:
-// such a set cannot be among the k nearest when `bound` is at least the k-th
-// smallest distance.
+// The set is abandoned, returning kAbandoned, as soon as a lower bound of
+// the result exceeds `bound` (such a set cannot be among the k nearest when
+// `bound` is at least the k-th smallest distance): the largest completed
+// column minimum (a database vector's distance to the query) after each
+// database tile, and, on the last database tile, the largest row minimum of
+// each query tile (those query vectors' distances to the whole set) as soon
+// as the tile is done.
 template <int KS, int MAXQT, bool HASG>
 __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uint32_t m, const QView& q,
                                               uint32_t bound = 0xFFFFFFFFu, uint32_t* rows_read = nullptr) {
@@ -88,7 +91,9 @@ __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uin
 #pragma unroll
   for (int i = 0; i < MAXQT; ++i) qmin[i] = 0xFFFFFFFFu;
   uint32_t colmax = 0;
+  const bool bounded = bound != 0xFFFFFFFFu;
   for (uint32_t vt = 0; vt < m; vt += 16) {
+    const bool last = vt + 16 >= m;
     if (rows_read) *rows_read += min(16u, m - vt);
     const uint32_t vrow = vt + c16;
     const bool vrow_ok = vrow < m;
@@ -146,6 +151,10 @@ __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uin
           vmin[r] = min(vmin[r], d2);
           qmin[qt] = min(qmin[qt], d2);
         }
+        if (bounded && last) {
+          const uint32_t rm = qok ? rows4_min_u32(qmin[qt]) : 0u;
+          if ((uint32_t)__builtin_amdgcn_readfirstlane((int)row16_max_u32(rm)) > bound) return kAbandoned;
+        }
       }
     }
 #pragma unroll
@@ -153,19 +162,18 @@ __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uin
       const uint32_t cm = row16_min_u32(vmin[r]);
       if (vok[r]) colmax = max(colmax, cm);
     }
-    if (bound != 0xFFFFFFFFu && vt + 16 < m && wave_max_u32(colmax) > bound) return kAbandoned;
+    if (bounded && !last && (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_dpp_u32(colmax)) > bound)
+      return kAbandoned;
   }
   uint32_t rowmax = 0;
 #pragma unroll
   for (int qt = 0; qt < MAXQT; ++qt) {
     if ((uint32_t)qt < q.nqt) {
-      uint32_t rm = qmin[qt];
-      rm = min(rm, shfl_xor_u32(rm, 16));
-      rm = min(rm, shfl_xor_u32(rm, 32));
+      const uint32_t rm = rows4_min_u32(qmin[qt]);
       if ((uint32_t)qt * 16 + c16 < q.mq) rowmax = max(rowmax, rm);
     }
   }
-  return wave_max_u32(max(colmax, rowmax));
+  return wave_max_dpp_u32(max(colmax, rowmax));
 }
 
 // Stage the first min(16 ceil(m_q / 16), lds_rows) rows of query q into LDS

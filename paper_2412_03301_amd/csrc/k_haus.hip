@@ -43,14 +43,23 @@ k_haus_cand(HausDb db, HausQ qs, uint32_t lds_rows, const uint32_t* __restrict__
   const QView qv = stage_query(qs, q, KS * 64, lds_rows, smem);
   const uint32_t w = wave_id();
   uint32_t rows = 0, abandoned = 0, items = 0;
+  // the id of the candidate after next and the offsets of the next one load
+  // while this one is computed (out-of-range ids read set 0, unused)
+  const cptr<uint32_t> idq = as_const(ids) + (uint64_t)q * T;
+  const cptr<uint64_t> offs = as_const(db.offsets);
+  auto id_at = [&](uint32_t i) { return i < b1 ? idq[i] : 0u; };
+  uint32_t jn = id_at(b0 + w);
+  uint64_t o0 = offs[jn], o1 = offs[jn + 1];
+  jn = id_at(b0 + w + kHausWaves);
   for (uint32_t it = b0 + w; it < b1; it += kHausWaves) {
-    const uint32_t j = ids[(uint64_t)q * T + it];
-    const uint64_t o0 = db.offsets[j];
-    const uint32_t m = (uint32_t)(db.offsets[j + 1] - o0);
-    const uint32_t hsq = haus_item<KS, MAXQT, HASG>(db, o0, m, qv, bound, stats ? &rows : nullptr);
+    const uint64_t n0 = offs[jn], n1 = offs[jn + 1];
+    jn = id_at(it + 2 * kHausWaves);
+    const uint32_t hsq = haus_item<KS, MAXQT, HASG>(db, o0, (uint32_t)(o1 - o0), qv, bound, stats ? &rows : nullptr);
     if (lane_id() == 0) h2[(uint64_t)q * T + it] = hsq;
     abandoned += hsq == kAbandoned ? 1u : 0u;
     ++items;
+    o0 = n0;
+    o1 = n1;
   }
   if (stats) stats_add(stats, 1, rows, abandoned, items);
 }
