@@ -122,8 +122,25 @@ __device__ __forceinline__ uint32_t rows4_max_u32(uint32_t v) {
   return max((uint32_t)b[0], (uint32_t)b[1]);
 }
 
-// Maximum over the wave without LDS traffic (every lane gets it).
+__device__ __forceinline__ uint32_t row16_sum_u32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xF, 0xF, false);
+  return v;
+}
+__device__ __forceinline__ uint32_t rows4_sum_u32(uint32_t v) {
+  const auto a = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  v = (uint32_t)a[0] + (uint32_t)a[1];
+  const auto b = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (uint32_t)b[0] + (uint32_t)b[1];
+}
+
+// Maximum / minimum / sum over the wave without LDS traffic (every lane
+// gets it).
 __device__ __forceinline__ uint32_t wave_max_dpp_u32(uint32_t v) { return rows4_max_u32(row16_max_u32(v)); }
+__device__ __forceinline__ uint32_t wave_min_dpp_u32(uint32_t v) { return rows4_min_u32(row16_min_u32(v)); }
+__device__ __forceinline__ uint32_t wave_sum_dpp_u32(uint32_t v) { return rows4_sum_u32(row16_sum_u32(v)); }
 
 // One 16x16x64 int8 matrix-core step with int32 accumulation:
 //   C[i][j] += sum_k A[i][k] * B[k][j]

@@ -123,13 +123,13 @@ __device__ __forceinline__ uint32_t kth_largest(const uint32_t (&key)[R], uint32
     uint32_t local = 0;
 #pragma unroll
     for (int t = 0; t < R; ++t) local += key[t] >= cand ? 1u : 0u;
-    const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(local));
+    const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_dpp_u32(local));
     if (cnt == k) {
       // Exactly k keys reach the prefix: the k-th largest is their minimum.
       uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
       for (int t = 0; t < R; ++t) mn = key[t] >= cand ? min(mn, key[t]) : mn;
-      return wave_min_u32(mn);
+      return wave_min_dpp_u32(mn);
     }
     if (cnt > k) theta = cand;
   }
