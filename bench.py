@@ -71,20 +71,26 @@ def parse():
     return ap.parse_args()
 
 
-def source_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_sha(*paths):
+    """First 16 hex digits of the SHA-256 of the files' contents, in order."""
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(kernel_file, kernel_prefix):
     """HBM bytes per launch from a committed counter summary, if it was taken
-    on the current kernel source; else None."""
+    on the current kernel source (the summary lists the files it hashed);
+    else None."""
     p = os.path.join(ROOT, "profiles", f"pmc_{kernel_prefix}.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
-        if d.get("source_sha") != source_sha(kernel_file):
+        files = [os.path.join(ROOT, f) for f in d.get("sources", [os.path.relpath(kernel_file, ROOT)])]
+        if d.get("source_sha") != source_sha(*files):
             return None
         return d.get("hbm_bytes_per_launch")
     except Exception:
@@ -599,6 +605,7 @@ def learned_bench(args, w, cfg, dev):
                 bvs.profile_enable(False, counters=True)
                 ix.search(q, q_off, k, ws=ws, out=out)
                 counters = dict(bvs.profile_counters())
+                counters["sketch_rows"] = sketch_rows(ix, q, q_off)
                 bvs.profile_enable(False)
             ids = out[0].cpu().numpy().view(np.uint32)
             if truth is None:
@@ -620,7 +627,8 @@ def learned_bench(args, w, cfg, dev):
     roof = None
     if counters is not None and keep == "learned":
         work = {k2: float(v) for k2, v in counters.items()}
-        roof, _ = rooflines(best["stages_ms_per_step"], work, L, -(-d // 64) * 64, "k_haus_cand", "k_haus.hip")
+        roof, _ = rooflines(best["stages_ms_per_step"], work, L, -(-d // 64) * 64, "k_haus_cand", "k_haus.hip",
+                            w["n_sets"])
     return {
         "metric": METRIC,
         "value": best["qps"],
