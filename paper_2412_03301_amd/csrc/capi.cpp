@@ -609,7 +609,7 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
       return sparse ? launch_filter_sparse_append(a, st) : launch_filter_append(a, st);
     }));
     HIP_TRY(staged(prof, S_SELECT, [&] {
-      return launch_sort_append(w.cand_app, w.cand_count, w.cutoff, w.cap, g.T, n_q, f2_ids, f2_scores, f2_count,
+      return launch_sort_append(w.cand_app, w.cand_count, w.cutoff, w.cap, g.T, g.L, n_q, f2_ids, f2_scores, f2_count,
                                 d_fail, st);
     }));
     if (!host_sync) {

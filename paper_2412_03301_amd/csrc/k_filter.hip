@@ -607,47 +607,104 @@ hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_
   return hipGetLastError();
 }
 
-// One block per query: sort the appended keys and keep the first T as F2.
-// A query whose buffer overflowed, or that holds fewer than T sets although
-// its cutoff excluded some members, is counted in *fail and left untouched.
+// One block per query: the first T appended keys by (score, id) as F2.  A
+// histogram of the scores (16-bit counters, two per word) gives the T-th
+// smallest score; only keys at or under it are sorted.  A query whose
+// buffer overflowed, or that holds fewer than T sets although its cutoff
+// excluded some members, is counted in *fail and left untouched.
 __global__ void __launch_bounds__(1024)
 k_sort_append(const uint64_t* __restrict__ cand, const uint32_t* __restrict__ cand_count,
-              const uint32_t* __restrict__ cutoff, uint32_t cap, uint32_t T, uint32_t* __restrict__ f2_ids,
-              uint16_t* __restrict__ f2_scores, uint32_t* __restrict__ f2_count, uint32_t* __restrict__ fail) {
-  extern __shared__ uint64_t keys[];
-  const uint32_t q = blockIdx.x;
+              const uint32_t* __restrict__ cutoff, uint32_t cap, uint32_t np, uint32_t T, uint32_t L,
+              uint32_t* __restrict__ f2_ids, uint16_t* __restrict__ f2_scores, uint32_t* __restrict__ f2_count,
+              uint32_t* __restrict__ fail) {
+  extern __shared__ uint64_t keys[];                 // [np >= cap], then the histogram and the scan
+  uint32_t* hist = (uint32_t*)(keys + np);           // [(L + 2) / 2] packed counters
+  uint32_t* part = hist + (L + 2) / 2;               // [16] per-wave sums
+  __shared__ uint32_t thr_s, m_s;
+  const uint32_t q = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
   const uint32_t n = cand_count[q];
   const bool ok = n <= cap && (n >= T || cutoff[q] == 0xFFFFFFFFu);
   if (!ok) {
-    if (threadIdx.x == 0) atomicAdd(fail, 1u);
+    if (tid == 0) atomicAdd(fail, 1u);
     return;
   }
+  const uint64_t* cq = cand + (uint64_t)q * cap;
+  const uint32_t nbw = (L + 2) / 2;
+  if (tid == 0) {
+    thr_s = 0xFFFFFFFFu;
+    m_s = 0;
+  }
+  if (n > T) {
+    for (uint32_t i = tid; i < nbw; i += bd) hist[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += bd) {
+      const uint32_t sc = (uint32_t)(cq[i] >> 32);
+      atomicAdd(&hist[sc >> 1], 1u << (16 * (sc & 1)));
+    }
+    __syncthreads();
+    // thread t sums bins [t per, (t + 1) per); block exclusive scan; the
+    // thread whose range reaches T finds the score
+    const uint32_t nb = L + 1, per = (nb + bd - 1) / bd;
+    const uint32_t b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
+    auto bin = [&](uint32_t b) { return (hist[b >> 1] >> (16 * (b & 1))) & 0xFFFFu; };
+    uint32_t own = 0;
+    for (uint32_t b = b0; b < b1; ++b) own += bin(b);
+    uint32_t inc = own;
+    const uint32_t lane = lane_id(), w = tid / BVS_WAVE;
+#pragma unroll
+    for (int d = 1; d < BVS_WAVE; d <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_up((int)inc, d, BVS_WAVE);
+      if (lane >= (uint32_t)d) inc += o;
+    }
+    if (lane == BVS_WAVE - 1) part[w] = inc;
+    __syncthreads();
+    uint32_t pre = inc - own;
+    for (uint32_t i = 0; i < w; ++i) pre += part[i];
+    if (pre < T && pre + own >= T) {
+      uint32_t cum = pre;
+      for (uint32_t b = b0; b < b1; ++b) {
+        cum += bin(b);
+        if (cum >= T) {
+          thr_s = b;
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t thr = thr_s;
+  for (uint32_t i = tid; i < n; i += bd) {
+    const uint64_t key = cq[i];
+    if ((uint32_t)(key >> 32) <= thr) keys[atomicAdd(&m_s, 1u)] = key;
+  }
+  __syncthreads();
+  const uint32_t m = m_s;
   uint32_t NP = 2;
-  while (NP < n) NP <<= 1;
-  for (uint32_t i = threadIdx.x; i < NP; i += blockDim.x) keys[i] = i < n ? cand[(uint64_t)q * cap + i] : ~0ull;
+  while (NP < m) NP <<= 1;
+  for (uint32_t i = m + tid; i < NP; i += bd) keys[i] = ~0ull;
   __syncthreads();
   bitonic_sort_lds(keys, NP);
   const uint32_t Tq = min(T, n);
-  for (uint32_t i = threadIdx.x; i < T; i += blockDim.x) {
+  for (uint32_t i = tid; i < T; i += bd) {
     const bool v = i < Tq;
     const uint64_t key = v ? keys[i] : ~0ull;
     f2_ids[(uint64_t)q * T + i] = v ? (uint32_t)key : 0xFFFFFFFFu;
     if (f2_scores) f2_scores[(uint64_t)q * T + i] = v ? (uint16_t)(key >> 32) : (uint16_t)0xFFFF;
   }
-  if (threadIdx.x == 0) f2_count[q] = Tq;
+  if (tid == 0) f2_count[q] = Tq;
 }
 
 hipError_t launch_sort_append(const uint64_t* cand, const uint32_t* cand_count, const uint32_t* cutoff, uint32_t cap,
-                              uint32_t T, uint32_t n_q, uint32_t* f2_ids, uint16_t* f2_scores, uint32_t* f2_count,
-                              uint32_t* fail, hipStream_t st) {
+                              uint32_t T, uint32_t L, uint32_t n_q, uint32_t* f2_ids, uint16_t* f2_scores,
+                              uint32_t* f2_count, uint32_t* fail, hipStream_t st) {
   if (n_q == 0) return hipSuccess;
   uint32_t np = 2;
-  while (np < cap) np <<= 1;   // the sort pads n <= cap keys to a power of two
-  const size_t lds = (size_t)np * sizeof(uint64_t);
+  while (np < cap) np <<= 1;   // the sort pads at most cap keys to a power of two
+  const size_t lds = (size_t)np * sizeof(uint64_t) + ((L + 2) / 2 + 16) * sizeof(uint32_t);
   hipError_t e = hipFuncSetAttribute((const void*)k_sort_append, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sort_append, dim3(n_q), dim3(1024), lds, st, cand, cand_count, cutoff, cap, T, f2_ids, f2_scores,
-                     f2_count, fail);
+  hipLaunchKernelGGL(k_sort_append, dim3(n_q), dim3(1024), lds, st, cand, cand_count, cutoff, cap, np, T, L, f2_ids,
+                     f2_scores, f2_count, fail);
   return hipGetLastError();
 }
 

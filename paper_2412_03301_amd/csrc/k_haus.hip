@@ -203,10 +203,11 @@ hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipSt
 // ---------------------------------------------------------------- top-k
 static constexpr uint32_t kTopkChunk = 4096;
 
-__device__ void bitonic_sort_4096(uint64_t* k) {
-  for (uint32_t size = 2; size <= kTopkChunk; size <<= 1) {
+// Bitonic sort of the first NP (a power of two, at most 4096) keys.
+__device__ void bitonic_sort_4096(uint64_t* k, uint32_t NP) {
+  for (uint32_t size = 2; size <= NP; size <<= 1) {
     for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t i = threadIdx.x; i < kTopkChunk / 2; i += blockDim.x) {
+      for (uint32_t i = threadIdx.x; i < NP / 2; i += blockDim.x) {
         const uint32_t lo = 2 * i - (i & (stride - 1));
         const uint32_t hi = lo + stride;
         const bool asc = (lo & size) == 0;
@@ -243,7 +244,12 @@ k_topk(const uint32_t* __restrict__ h2, const uint32_t* __restrict__ ids_in, con
     s[i] = key;
   }
   __syncthreads();
-  bitonic_sort_4096(s);
+  // only the valid keys of the chunk need sorting; the padding after them
+  // already holds the largest key
+  const uint64_t nv_chunk = n_valid > base ? std::min<uint64_t>(n_valid - base, kTopkChunk) : 0;
+  uint32_t NP = 2;
+  while (NP < nv_chunk) NP <<= 1;
+  bitonic_sort_4096(s, NP);
   if (ids) {
     const uint32_t nv = count_in ? count_in[q] : n_valid_total;
     for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) {

@@ -104,8 +104,8 @@ size_t sliced_lds_bytes(uint32_t L);
 hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_t r, uint32_t n_q,
                          uint32_t* cutoff, hipStream_t st);
 hipError_t launch_sort_append(const uint64_t* cand, const uint32_t* cand_count, const uint32_t* cutoff, uint32_t cap,
-                              uint32_t T, uint32_t n_q, uint32_t* f2_ids, uint16_t* f2_scores, uint32_t* f2_count,
-                              uint32_t* fail, hipStream_t st);
+                              uint32_t T, uint32_t L, uint32_t n_q, uint32_t* f2_ids, uint16_t* f2_scores,
+                              uint32_t* f2_count, uint32_t* fail, hipStream_t st);
 
 // Dense top-T selection of the scores; writes F2 sorted by (score, id).
 struct SelectBufs {
