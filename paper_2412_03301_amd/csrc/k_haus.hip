@@ -144,9 +144,10 @@ constexpr bool haus_variant_used() {
   return !HG || haus_stage_bytes(MQ * 16, KS * 64) > kStageBudget;
 }
 
-// Three exact phases: full distances for the first kCandPerBlock candidates
-// (the best by sketch distance), their k-th smallest as a bound per query,
-// then the remaining candidates with abandoning against that bound.
+// Exact phases: full distances for the first max(k, 16) candidates (the
+// best by sketch distance); their k-th smallest bounds the candidates up to
+// kCandPerBlock, whose k-th smallest (abandoned ones exceed it) bounds the
+// remaining candidates; each bound is at least the query's k-th distance.
 hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids, const uint32_t* count,
                             uint32_t T, uint32_t k, uint32_t* thr, uint32_t* h2, unsigned long long* stats,
                             hipStream_t st) {
@@ -163,10 +164,21 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
       auto kern = k_haus_cand<KS, MQ, HG>;
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
+      // the first na candidates bound the next ones up to n0, whose k-th
+      // distance then bounds the rest
+      const uint32_t na = std::min(n0, std::max(k, 16u));
       hipLaunchKernelGGL(kern, dim3(1, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids, count, T, 0u,
-                         n0, (const uint32_t*)nullptr, h2, stats);
+                         na, (const uint32_t*)nullptr, h2, stats);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      if (T <= n0) return hipSuccess;
+      if (T <= na) return hipSuccess;
+      if (na < n0) {
+        hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, na, k, thr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(1, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids, count, T, na,
+                           n0, (const uint32_t*)thr, h2, stats);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (T <= n0) return hipSuccess;
+      }
       hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, n0, k, thr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const uint32_t G = (T - n0 + kCandPerBlock - 1) / kCandPerBlock;
