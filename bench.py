@@ -159,7 +159,10 @@ def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=
     algorithmic work per launch and its measured time per launch."""
     csrc = os.path.join(ROOT, "paper_2412_03301_amd", "csrc")
     dominant = max(("filter", "rerank"), key=lambda s2: per_step.get(s2, 0.0))
-    rer_bytes = work["rerank_vectors"] * (dim_padded * 2 + 4)
+    # exact passes read both planes and the norm; the screen reads the high
+    # plane and the 8-byte screening pair
+    scr_vec = work.get("rerank_screen_vectors", 0.0)
+    rer_bytes = work["rerank_vectors"] * (dim_padded * 2 + 4) + scr_vec * (dim_padded + 8)
     if dominant == "filter" and n_sets and work.get("sketch_rows"):
         # bit-sliced counting: every query adds its |S_Q| tile rows for every
         # set; one 3:2 carry-save compression (two 3-input logic ops) per
@@ -175,11 +178,13 @@ def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=
         ach = rer_bytes / (per_step["rerank"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "kernel": rerank_kernel,
-                "algorithmic": f"{rer_bytes:.4g} bytes per launch (vectors read x (2 dp + 4))",
+                "algorithmic": (f"{rer_bytes:.4g} bytes per launch (vectors read in full x (2 dp + 4) "
+                                f"+ vectors screened x (dp + 8))"),
                 "traffic": traffic_from_profiles(os.path.join(csrc, rerank_file), rerank_kernel)}
     rerank_roof = {"achieved_gbs": rer_bytes / (per_step["rerank"] / 1e3) / 1e9 if per_step.get("rerank") else None,
-                   "vectors_read": work["rerank_vectors"], "candidates": work["rerank_candidates"],
-                   "abandoned": work["rerank_abandoned"]}
+                   "vectors_read": work["rerank_vectors"], "vectors_screened": scr_vec,
+                   "candidates": work["rerank_candidates"], "abandoned": work["rerank_abandoned"],
+                   "screened_out": work.get("rerank_screened", 0.0)}
     return roof, rerank_roof
 
 

@@ -434,15 +434,19 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
  * precision form (encoding of the queries, approximate values, selection
  * of the candidates to re-check), 11 exact re-check of the precision form.
  * Work counters (summed over calls): 0 first-layer member pairs scored by
- * the filter stage, 1 database vectors read by the re-rank stage, 2 re-rank
- * candidates abandoned early, 3 re-rank candidates.
+ * the filter stage, 1 database vectors read in full (both planes) by the
+ * re-rank stage, 2 re-rank candidates abandoned early (screened ones
+ * included), 3 re-rank candidates, 4 database vectors whose high plane the
+ * re-rank's screen read, 5 candidates the screen rejected.  bvs_search
+ * screens the candidates after the first 64 on their high planes unless
+ * the environment sets BVS_SCREEN=0 (the results are the same).
  * bvs_profile_enable(flags) resets the table; flags: BVS_PROFILE_TIMING
  * records the stage events, BVS_PROFILE_COUNTERS collects the work counters
  * (their atomics slow the counted kernels somewhat), 0 turns both off. */
 #define BVS_PROFILE_TIMING 1
 #define BVS_PROFILE_COUNTERS 2
 #define BVS_N_STAGES 12
-#define BVS_N_COUNTERS 4
+#define BVS_N_COUNTERS 6
 typedef struct bvs_stage_times {
   double ms[BVS_N_STAGES];
   uint64_t calls[BVS_N_STAGES];

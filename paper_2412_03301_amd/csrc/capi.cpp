@@ -277,6 +277,7 @@ struct bvs_index {
   int8_t* hi;
   uint8_t* lo;
   uint32_t* norms;
+  uint2* scr;         // [N] {|hi|^2, |lo - 31.5| / 64 rounded up} for re-rank screening
   uint8_t* cnt;
   uint64_t* bits;
   uint64_t* planes;   // [L][ld/64]: bit j of plane p set when C^(j)[p] >= 1
@@ -301,6 +302,7 @@ void layout_index(Carver& c, const Geometry& g, uint64_t n, uint64_t N, bvs_inde
   ix->hi = c.take<int8_t>(N * g.dp);
   ix->lo = c.take<uint8_t>(N * g.dp);
   ix->norms = c.take<uint32_t>(N);
+  ix->scr = c.take<uint2>(N);
   ix->cnt = c.take<uint8_t>((uint64_t)g.L * ld);
   ix->bits = c.take<uint64_t>((uint64_t)g.R * ld);
   ix->planes = c.take<uint64_t>((uint64_t)g.L * (ld / 64));
@@ -329,6 +331,7 @@ struct QueryWs {
   int8_t* qhi;
   uint8_t* qlo;
   uint32_t* qnorm;
+  uint2* qscr;
   // search only
   uint64_t* codes;
   uint16_t* cq;
@@ -354,7 +357,9 @@ struct QueryWs {
   uint32_t* f2_count;
   uint32_t* h2;
   uint32_t* thr;          // [n_q] re-rank bound
-  unsigned long long* stats;   // [4] work counters
+  uint32_t* surv;         // [n_q][T] candidates that passed the re-rank screen
+  uint32_t* surv_count;   // [n_q]
+  unsigned long long* stats;   // [kStatSlots][kStatCounters] work counters
   uint64_t* topk_tmp;
   // learned projection: query rows in bfloat16, hidden layer, outputs
   uint16_t* lx16;
@@ -397,6 +402,13 @@ bool use_sliced_filter(const Geometry& g) {
   return g.M == 1 && g.L % 256 == 0 && g.L <= 4096;
 }
 
+// High-plane screening of bounded re-ranks unless BVS_SCREEN=0 (the
+// results are the same either way; the switch serves comparisons).
+bool screen_enabled() {
+  const char* e = std::getenv("BVS_SCREEN");
+  return !(e && std::strcmp(e, "0") == 0);
+}
+
 bool force_dense_select() {
   const char* e = std::getenv("BVS_SELECT");
   return e && std::strcmp(e, "dense") == 0;
@@ -409,6 +421,7 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->qhi = c.take<int8_t>(NQ * g.dp);
   w->qlo = c.take<uint8_t>(NQ * g.dp);
   w->qnorm = c.take<uint32_t>(NQ);
+  w->qscr = c.take<uint2>(NQ);
   w->codes = c.take<uint64_t>(NQ * g.R);
   w->cq = c.take<uint16_t>((uint64_t)n_q * g.L);
   w->sq = c.take<uint64_t>((uint64_t)n_q * g.R);
@@ -437,6 +450,8 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->f2_count = c.take<uint32_t>(n_q);
   w->h2 = c.take<uint32_t>((uint64_t)n_q * g.T);
   w->thr = c.take<uint32_t>(n_q);
+  w->surv = c.take<uint32_t>((uint64_t)n_q * g.T);
+  w->surv_count = c.take<uint32_t>(n_q);
   w->stats = c.take<unsigned long long>((uint64_t)kStatSlots * kStatCounters);
   w->topk_tmp = c.take<uint64_t>(topk_tmp_words(g.T, n_q, kMaxK));
   w->lx16 = nullptr;
@@ -502,7 +517,7 @@ bvs_status prepare_queries(const bvs_index* ix, const float* d_q, const uint64_t
   HIP_TRY(launch_fill_u32(w.status, 4, 0, st));
   HIP_TRY(hipMemcpyAsync(w.qoff, h_q_off, (n_q + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
   HIP_TRY(staged(prof, S_CONVERT, [&] {
-    return launch_convert(d_q, NQ, ix->g.d, ix->g.dp, w.qhi, w.qlo, w.qnorm, w.status, ix->n_cu, st);
+    return launch_convert(d_q, NQ, ix->g.d, ix->g.dp, w.qhi, w.qlo, w.qnorm, w.qscr, w.status, ix->n_cu, st);
   }));
   return BVS_OK;
 }
@@ -643,6 +658,7 @@ HausDb haus_db(const bvs_index* ix) {
   d.offsets = ix->offsets;
   d.n_sets = ix->n;
   d.dp = ix->g.dp;
+  d.scr = screen_enabled() ? ix->scr : nullptr;
   return d;
 }
 
@@ -651,6 +667,7 @@ HausQ haus_q(const QueryWs& w, uint32_t n_q, uint32_t max_rows) {
   q.hi = w.qhi;
   q.lo = w.qlo;
   q.norms = w.qnorm;
+  q.scr = w.qscr;
   q.offsets = w.qoff;
   q.n_q = n_q;
   q.max_rows = max_rows;
@@ -795,7 +812,7 @@ bvs_status bvs_build_index(const bvs_params* p, const float* d_vectors, const ui
     HIP_TRY(hipMemcpyAsync(ix->idx, padded.data(), padded.size() * 2, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(ix->offsets, h_offsets, (n_sets + 1) * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(launch_fill_u32(status, 4, 0, st));
-    HIP_TRY(launch_convert(d_vectors, N, g.d, g.dp, ix->hi, ix->lo, ix->norms, status, ix->n_cu, st));
+    HIP_TRY(launch_convert(d_vectors, N, g.d, g.dp, ix->hi, ix->lo, ix->norms, ix->scr, status, ix->n_cu, st));
     HIP_TRY(launch_encode_sets(hash_geom(ix), ix->hi, ix->lo, ix->offsets, n_sets, cnt_rm, bits_rm, ix->n_cu, st));
     HIP_TRY(launch_transpose_sketches(cnt_rm, bits_rm, n_sets, ix->ld, g.L, ix->cnt, ix->bits, st));
     HIP_TRY(launch_bitmap_planes(ix->cnt, ix->ld, g.L, ix->planes, st));
@@ -871,7 +888,7 @@ bvs_status bvs_encode(const bvs_index* ix, const float* d_x, uint64_t n, void* d
   uint16_t* h16 = ix->learned ? c.take<uint16_t>(n * ix->hidden) : nullptr;
   float* y = ix->learned ? c.take<float>(n * ix->g.L) : nullptr;
   HIP_TRY(launch_fill_u32(status, 4, 0, st));
-  HIP_TRY(launch_convert(d_x, n, ix->g.d, ix->g.dp, hi, lo, norms, status, ix->n_cu, st));
+  HIP_TRY(launch_convert(d_x, n, ix->g.d, ix->g.dp, hi, lo, norms, nullptr, status, ix->n_cu, st));
   HIP_TRY(encode_planes(ix, hi, lo, n, d_codes, x16, h16, y, st));
   return read_status(status, st, "vectors");
 }
@@ -960,7 +977,7 @@ bvs_status bvs_search(const bvs_index* ix, const float* d_q, const uint64_t* h_q
   BVS_TRY(run_filters(ix, n_q, NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof));
   HIP_TRY(staged(prof, S_RERANK, [&] {
     return launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, k, w.thr, w.h2,
-                            prof.count ? w.stats : nullptr, st);
+                            prof.count ? w.stats : nullptr, w.surv, w.surv_count, st);
   }));
   HIP_TRY(staged(prof, S_TOPK, [&] {
     return launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
@@ -1093,7 +1110,7 @@ bvs_status batch_filters(bvs_batch* b, hipStream_t st, CallProf& prof) {
   QueryWs& w = b->w;
   HIP_TRY(launch_fill_u32(w.status, 4, 0, st));
   HIP_TRY(staged(prof, S_CONVERT, [&] {
-    return launch_convert(b->d_q, b->NQ, ix->g.d, ix->g.dp, w.qhi, w.qlo, w.qnorm, w.status, ix->n_cu, st);
+    return launch_convert(b->d_q, b->NQ, ix->g.d, ix->g.dp, w.qhi, w.qlo, w.qnorm, w.qscr, w.status, ix->n_cu, st);
   }));
   return run_filters(ix, b->n_q, b->NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof, false);
 }
@@ -1502,7 +1519,7 @@ bvs_status bvs_search_lowp(const bvs_index* ix, int fmt, float margin, const flo
   BVS_TRY(ls);
   HIP_TRY(staged(prof, S_RECHECK, [&]() -> hipError_t {
     hipError_t e = launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), l.r_ids, l.r_count, T, k, w.thr, w.h2,
-                                    prof.count ? w.stats : nullptr, st);
+                                    prof.count ? w.stats : nullptr, nullptr, nullptr, st);
     if (e != hipSuccess) return e;
     return launch_topk(w.h2, l.r_ids, l.r_count, T, T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
   }));
@@ -1810,7 +1827,7 @@ bvs_status bvs_build_index_learned(const bvs_params* p, uint32_t hidden, const f
     HIP_TRY(hipMemcpyAsync(ix->b2, d_weights + (uint64_t)hidden * g.d + hidden + (uint64_t)g.L * hidden,
                            (uint64_t)g.L * 4, hipMemcpyDeviceToDevice, st));
     HIP_TRY(launch_fill_u32(status, 4, 0, st));
-    HIP_TRY(launch_convert(d_vectors, N, g.d, g.dp, ix->hi, ix->lo, ix->norms, status, ix->n_cu, st));
+    HIP_TRY(launch_convert(d_vectors, N, g.d, g.dp, ix->hi, ix->lo, ix->norms, ix->scr, status, ix->n_cu, st));
     // codes and set sketches, a chunk of whole sets at a time
     uint64_t s0 = 0;
     while (s0 < n_sets) {

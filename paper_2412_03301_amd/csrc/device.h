@@ -138,6 +138,21 @@ __device__ __forceinline__ uint32_t rows4_sum_u32(uint32_t v) {
 
 // Maximum / minimum / sum over the wave without LDS traffic (every lane
 // gets it).
+// Float minima over the 16 lanes of a DPP row and over the four rows.
+__device__ __forceinline__ float row16_min_f32(float v) {
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xF, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xF, 0xF, false)));
+  return v;
+}
+__device__ __forceinline__ float rows4_min_f32(float v) {
+  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = fminf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  const auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fminf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
 __device__ __forceinline__ uint32_t wave_max_dpp_u32(uint32_t v) { return rows4_max_u32(row16_max_u32(v)); }
 __device__ __forceinline__ uint32_t wave_min_dpp_u32(uint32_t v) { return rows4_min_u32(row16_min_u32(v)); }
 __device__ __forceinline__ uint32_t wave_sum_dpp_u32(uint32_t v) { return rows4_sum_u32(row16_sum_u32(v)); }
@@ -154,11 +169,11 @@ __device__ __forceinline__ v4i mfma_i8(v4i a, v4i b, v4i c) {
 
 __host__ __device__ constexpr uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-// Work counters: kStatSlots slots of 4 counters; workgroups add their totals
+// Work counters: kStatSlots slots of kStatCounters counters; workgroups add their totals
 // to slot (linear block id % kStatSlots) so that no single address takes
 // every atomic.  The host sums the slots.
 constexpr uint32_t kStatSlots = 64;
-constexpr uint32_t kStatCounters = 4;
+constexpr uint32_t kStatCounters = 6;
 
 // Block-wide sum of up to three per-wave counters (lane 0 of each wave holds
 // the wave's value; every wave must call), added to counters first, first+1,

@@ -23,6 +23,20 @@
 //   row minimum over v (per query vector) -> carried per lane across tiles,
 //   reduced over the four lane groups at the end of the set.
 // Hausdorff^2 = max(max_v min_q D2, max_q min_v D2).
+//
+// Screening.  With a bound, candidates can first be compared on the high
+// planes alone, half the bytes.  Write lo = 31.5 + e (e = 0 on the padding
+// coordinates); the triangle inequality gives
+//   |a - b| >= 64 |hi_a - hi_b| - |e_a| - |e_b|,
+// and |hi_a - hi_b|^2 = |hi_a|^2 + |hi_b|^2 - 2 hi_a . hi_b is one int8
+// product.  Each row carries |hi|^2 and r = |e| / 64 rounded up (written at
+// conversion); a pair is provably farther than sqrt(bound) when
+//   |hi_a - hi_b|^2 > (sqrt(bound) / 64 + r_a + r_b)^2,
+// evaluated in float with the right-hand side rounded up.  If some vector
+// of the set's first tile is that far from every query row, or (for sets of
+// one tile) some query row from every vector of the set, the Hausdorff
+// distance exceeds the bound and the set is rejected without its low planes
+// ever being read; the survivors go through the exact pass.
 #pragma once
 #include "device.h"
 #include "launch.h"
@@ -44,6 +58,16 @@ __host__ __device__ constexpr uint32_t q_row_stride(uint32_t dp) { return dp + 1
 __host__ __device__ constexpr size_t haus_stage_bytes(uint32_t rows, uint32_t dp) {
   return (size_t)rows * q_row_stride(dp) * 2 + (size_t)rows * 4;
 }
+
+// LDS of the screening pass: the high plane (same row stride) and the
+// screening pair of `rows` query rows.
+__host__ __device__ constexpr size_t screen_stage_bytes(uint32_t rows, uint32_t dp) {
+  return (size_t)rows * q_row_stride(dp) + (size_t)rows * 8;
+}
+
+// |hi|^2 given to rows past the end of a set or a query: far from
+// everything, and the sums below stay within int32.
+static constexpr uint32_t kScreenPad = 1u << 28;
 
 // Where a wave reads the query: rows [0, 16 nqt_s) staged in LDS (row stride
 // dp + 16, zero padded), the rest from global memory (row stride dp).
@@ -71,6 +95,67 @@ __device__ __forceinline__ void tile_products(const v4i (&ah)[KS], const v4i (&a
   }
 }
 
+// Screen of the first database tile (rows [0, min(16, m)) of the set, whose
+// high planes are in ah) against a query staged by stage_query_screen (high
+// plane rows qh with stride dp + 16 and screening pairs qs, pad rows far):
+// whether the set provably has Hausdorff^2 > bound.  Per pair, |hi_a -
+// hi_b|^2 - X^2 with X >= sqrt(bound) / 64 + r_a + r_b, by one fused
+// multiply-add whose sign is exact; pad rows and columns come out far.  A
+// database vector far from every query vector decides (column minima); when
+// the tile is the whole set, so does a query vector far from every vector of
+// the tile (row minima), checked after each query tile.
+template <int KS, int MAXQT>
+__device__ __forceinline__ bool screen_first_tile(const HausDb& db, uint64_t o0, uint32_t m, const uint8_t* qh,
+                                                  const uint2* qs, uint32_t mq, uint32_t nqt, const v4i (&ah)[KS],
+                                                  float tb) {
+  const uint32_t lane = lane_id();
+  const uint32_t g = lane >> 4, c16 = lane & 15;
+  const uint32_t QS = q_row_stride(KS * 64);
+  const bool whole = m <= 16;
+  uint32_t hv[4];
+  float rv[4], colm[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t v = 4 * g + r;
+    const uint2 sv = v < m ? db.scr[o0 + v] : make_uint2(kScreenPad, 0u);
+    hv[r] = sv.x;
+    rv[r] = __uint_as_float(sv.y);
+    colm[r] = __builtin_inff();
+  }
+#pragma unroll
+  for (int qt = 0; qt < MAXQT; ++qt) {
+    if ((uint32_t)qt < nqt) {
+      v4i hh = {0, 0, 0, 0};
+      const uint32_t qi = qt * 16 + c16;
+      const uint8_t* bh = qh + qi * QS + 16 * g;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) hh = mfma_i8(ah[k], *(const v4i*)(bh + 64 * k), hh);
+      const uint2 sq = qs[qi];
+      const float tq = tb + __uint_as_float(sq.y);
+      float rowm = __builtin_inff();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int h2 = (int)(hv[r] + sq.x) - 2 * hh[r];
+        const float x = tq + rv[r];
+        const float mf = fmaf(-x, x, (float)h2);
+        rowm = fminf(rowm, mf);
+        colm[r] = fminf(colm[r], mf);
+      }
+      if (whole) {
+        const float rm = rows4_min_f32(rowm);
+        if (ballot(qi < mq && rm > 0.0f)) return true;
+      }
+    }
+  }
+  bool far = false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float cm = row16_min_f32(colm[r]);
+    far = far || (4 * g + r < m && cm > 0.0f);
+  }
+  return ballot(far) != 0;
+}
+
 // Squared Hausdorff distance (2^24-scaled) of database set [o0, o0 + m)
 // against the query (HASG: some query tiles may come from global memory).
 // The set is abandoned, returning kAbandoned, as soon as a lower bound of
@@ -87,11 +172,11 @@ __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uin
   const uint32_t g = lane >> 4, c16 = lane & 15;
   const uint32_t dp = KS * 64;
   const uint32_t QS = q_row_stride(dp);
+  const bool bounded = bound != 0xFFFFFFFFu;
   uint32_t qmin[MAXQT];
 #pragma unroll
   for (int i = 0; i < MAXQT; ++i) qmin[i] = 0xFFFFFFFFu;
   uint32_t colmax = 0;
-  const bool bounded = bound != 0xFFFFFFFFu;
   for (uint32_t vt = 0; vt < m; vt += 16) {
     const bool last = vt + 16 >= m;
     if (rows_read) *rows_read += min(16u, m - vt);
@@ -211,6 +296,30 @@ __device__ __forceinline__ QView stage_query(const HausQ& qs, uint32_t q, uint32
   v.ng = qs.norms + o0;
   __syncthreads();
   return v;
+}
+
+// Stage the high plane and the screening pairs of all 16 ceil(m_q / 16) rows
+// of query q (rows past the query: zero plane, pad pair) for the screen.
+// Returns m_q.  Ends with a workgroup barrier.
+__device__ __forceinline__ uint32_t stage_query_screen(const HausQ& qs, uint32_t q, uint32_t dp, uint8_t* smem,
+                                                       uint8_t*& qh, uint2*& qp) {
+  const uint64_t o0 = qs.offsets[q];
+  const uint32_t mq = (uint32_t)(qs.offsets[q + 1] - o0);
+  const uint32_t rows = (mq + 15) / 16 * 16;
+  const uint32_t QS = q_row_stride(dp);
+  qh = smem;
+  qp = (uint2*)(smem + (size_t)rows * QS);
+  const uint32_t c16n = dp / 16;
+  for (uint32_t i = threadIdx.x; i < rows * c16n; i += blockDim.x) {
+    const uint32_t r = i / c16n, c = i % c16n;
+    uint4 h = make_uint4(0, 0, 0, 0);
+    if (r < mq) h = *(const uint4*)(qs.hi + (o0 + r) * dp + 16 * c);
+    *(uint4*)(qh + r * QS + 16 * c) = h;
+  }
+  for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x)
+    qp[r] = r < mq ? qs.scr[o0 + r] : make_uint2(kScreenPad, 0u);
+  __syncthreads();
+  return mq;
 }
 
 // k-th smallest of vals[0 .. nv), nv <= 64, computed by one whole wave (every

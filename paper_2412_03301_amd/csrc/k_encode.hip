@@ -1,7 +1,9 @@
 // FlyHash encoding and per-set Bloom sketches on gfx950.
 //
-//   convert         float32 rows -> exact int8 planes (a = 4096 x = 64 hi + lo)
-//                   and squared norms; validates the 2^-12 grid
+//   convert         float32 rows -> exact int8 planes (a = 4096 x = 64 hi + lo),
+//                   squared norms, and the pair the re-rank screens with
+//                   (|hi|^2 and an upper bound of |lo - 31.5| / 64); validates
+//                   the 2^-12 grid
 //   encode_vectors  one wave per vector: projection y = W a (Def. 7) with the
 //                   sparse rows of W read from an LDS copy of the index table,
 //                   then winner-take-all (Alg. 1): the wta_k largest outputs
@@ -29,7 +31,7 @@ namespace bvs {
 __global__ void __launch_bounds__(256)
 k_convert(const float* __restrict__ x, uint64_t n_rows, uint32_t d, uint32_t dp,
           int8_t* __restrict__ hi, uint8_t* __restrict__ lo, uint32_t* __restrict__ norms,
-          uint32_t* __restrict__ status) {
+          uint2* __restrict__ scr, uint32_t* __restrict__ status) {
   const uint32_t lane = lane_id();
   const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / BVS_WAVE;
   const uint64_t nwaves = (gridDim.x * (uint64_t)blockDim.x) / BVS_WAVE;
@@ -37,6 +39,7 @@ k_convert(const float* __restrict__ x, uint64_t n_rows, uint32_t d, uint32_t dp,
   for (uint64_t r = wave; r < n_rows; r += nwaves) {
     const float* xr = x + r * d;
     uint64_t ss = 0;
+    uint32_t hs = 0, es = 0;
     for (uint32_t e = lane; e < dp; e += BVS_WAVE) {
       int a = 0;
       if (e < d) {
@@ -45,13 +48,24 @@ k_convert(const float* __restrict__ x, uint64_t n_rows, uint32_t d, uint32_t dp,
         float ri = rintf(s);
         if (!(ri == s) || !(fabsf(v) <= 1.0f)) { bad |= ST_OFF_GRID; ri = 0.0f; }
         a = (int)ri;
+        const int e2 = 2 * (a & 63) - 63;   // 2 (lo - 31.5), zero on padding
+        es += (uint32_t)(e2 * e2);
       }
       hi[r * dp + e] = (int8_t)(a >> 6);   // floor(a / 64) in [-64, 64]
       lo[r * dp + e] = (uint8_t)(a & 63);  // a - 64 floor(a / 64) in [0, 63]
       ss += (uint64_t)(a * a);
+      hs += (uint32_t)((a >> 6) * (a >> 6));
     }
     ss = wave_sum_u64(ss);
     if (ss > (1ull << 26)) bad |= ST_NORM;  // ||x|| > 2
+    if (scr) {
+      // |hi|^2 <= 1024 * 64^2 and |2 lo - 63|^2 <= 1024 * 63^2 are exact
+      // in float; the bound sqrt(es) / 128 is rounded up by the factor.
+      hs = wave_sum_dpp_u32(hs);
+      es = wave_sum_dpp_u32(es);
+      const float rb = sqrtf((float)es) * (1.0f / 128.0f) * (1.0f + 0x1p-20f);
+      if (lane == 0) scr[r] = make_uint2(hs, __float_as_uint(rb));
+    }
     if (lane == 0) norms[r] = (uint32_t)(ss > 0xFFFFFFFFull ? 0xFFFFFFFFull : ss);
   }
   const uint64_t b1 = ballot(bad & ST_OFF_GRID), b2 = ballot(bad & ST_NORM);
@@ -59,11 +73,11 @@ k_convert(const float* __restrict__ x, uint64_t n_rows, uint32_t d, uint32_t dp,
 }
 
 hipError_t launch_convert(const float* x, uint64_t n_rows, uint32_t d, uint32_t dp, int8_t* hi,
-                          uint8_t* lo, uint32_t* norms, uint32_t* status, int n_cu, hipStream_t st) {
+                          uint8_t* lo, uint32_t* norms, uint2* scr, uint32_t* status, int n_cu, hipStream_t st) {
   if (n_rows == 0) return hipSuccess;
   const uint64_t want = (n_rows + 3) / 4;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)n_cu * 32);
-  hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, st, x, n_rows, d, dp, hi, lo, norms, status);
+  hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, st, x, n_rows, d, dp, hi, lo, norms, scr, status);
   return hipGetLastError();
 }
 

@@ -28,11 +28,16 @@ size_t haus_lds_bytes(uint32_t max_rows, uint32_t dp) { return haus_stage_bytes(
 // waves take them round-robin.  With bounds != nullptr, candidates whose
 // lower bound exceeds bounds[q] are abandoned (h2 = kAbandoned).
 
+//
+// With sel != nullptr the positions i index sel[q][i], the candidates that
+// passed the screen (count[q] of them), instead of the candidates directly.
+
 template <int KS, int MAXQT, bool HASG>
 __global__ void __launch_bounds__(64 * kHausWaves)
 k_haus_cand(HausDb db, HausQ qs, uint32_t lds_rows, const uint32_t* __restrict__ ids,
             const uint32_t* __restrict__ count, uint32_t T, uint32_t i0, uint32_t lim,
-            const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2, unsigned long long* __restrict__ stats) {
+            const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2, unsigned long long* __restrict__ stats,
+            const uint32_t* __restrict__ sel) {
   extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t q = blockIdx.y;
   const uint32_t i1 = min(count[q], lim);
@@ -46,6 +51,56 @@ k_haus_cand(HausDb db, HausQ qs, uint32_t lds_rows, const uint32_t* __restrict__
   // the id of the candidate after next and the offsets of the next one load
   // while this one is computed (out-of-range ids read set 0, unused)
   const cptr<uint32_t> idq = as_const(ids) + (uint64_t)q * T;
+  const uint32_t* selq = sel ? sel + (uint64_t)q * T : nullptr;
+  const cptr<uint64_t> offs = as_const(db.offsets);
+  auto cand_at = [&](uint32_t i) { return selq ? selq[i] : i; };
+  auto id_at = [&](uint32_t i) { return i < b1 ? idq[cand_at(i)] : 0u; };
+  uint32_t jn = id_at(b0 + w);
+  uint64_t o0 = offs[jn], o1 = offs[jn + 1];
+  jn = id_at(b0 + w + kHausWaves);
+  for (uint32_t it = b0 + w; it < b1; it += kHausWaves) {
+    const uint64_t n0 = offs[jn], n1 = offs[jn + 1];
+    jn = id_at(it + 2 * kHausWaves);
+    const uint32_t hsq = haus_item<KS, MAXQT, HASG>(db, o0, (uint32_t)(o1 - o0), qv, bound, stats ? &rows : nullptr);
+    if (lane_id() == 0) h2[(uint64_t)q * T + cand_at(it)] = hsq;
+    abandoned += hsq == kAbandoned ? 1u : 0u;
+    ++items;
+    o0 = n0;
+    o1 = n1;
+  }
+  if (stats) stats_add(stats, 1, rows, abandoned, items);
+}
+
+// High-plane screen of candidates [i0, count[q]) against bounds[q] (see
+// haus_core.h): rejected candidates get h2 = kAbandoned, the others are
+// appended to sel[q][0 .. sel_count[q]) in no particular order (the exact
+// pass writes each result at its candidate's index, so the order does not
+// change any result).  Grid (G, n_q) as k_haus_cand; the whole query is
+// staged (its high plane and screening pairs).
+template <int KS, int MAXQT>
+__global__ void __launch_bounds__(64 * kHausWaves)
+k_haus_screen(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ count, uint32_t T,
+              uint32_t i0, const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2, uint32_t* __restrict__ sel,
+              uint32_t* __restrict__ sel_count, unsigned long long* __restrict__ stats) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t q = blockIdx.y;
+  const uint32_t i1 = count[q];
+  const uint32_t b0 = i0 + blockIdx.x * kCandPerBlock;
+  if (b0 >= i1) return;
+  const uint32_t b1 = min(i1, b0 + kCandPerBlock);
+  const uint32_t bound = bounds[q];
+  uint8_t* qh;
+  uint2* qp;
+  const uint32_t mq = stage_query_screen(qs, q, KS * 64, smem, qh, qp);
+  const uint32_t nqt = (mq + 15) / 16;
+  // sqrt(bound) / 64 rounded up: the factor covers the int -> float and the
+  // square-root roundings, and the additions in the screen
+  const float tb = sqrtf((float)bound) * (1.0f / 64.0f) * (1.0f + 0x1p-19f);
+  const uint32_t w = wave_id(), lane = lane_id();
+  const uint32_t g = lane >> 4, c16 = lane & 15;
+  constexpr uint32_t dp = KS * 64;
+  uint32_t rows = 0, rejected = 0;
+  const cptr<uint32_t> idq = as_const(ids) + (uint64_t)q * T;
   const cptr<uint64_t> offs = as_const(db.offsets);
   auto id_at = [&](uint32_t i) { return i < b1 ? idq[i] : 0u; };
   uint32_t jn = id_at(b0 + w);
@@ -54,14 +109,34 @@ k_haus_cand(HausDb db, HausQ qs, uint32_t lds_rows, const uint32_t* __restrict__
   for (uint32_t it = b0 + w; it < b1; it += kHausWaves) {
     const uint64_t n0 = offs[jn], n1 = offs[jn + 1];
     jn = id_at(it + 2 * kHausWaves);
-    const uint32_t hsq = haus_item<KS, MAXQT, HASG>(db, o0, (uint32_t)(o1 - o0), qv, bound, stats ? &rows : nullptr);
-    if (lane_id() == 0) h2[(uint64_t)q * T + it] = hsq;
-    abandoned += hsq == kAbandoned ? 1u : 0u;
-    ++items;
+    const uint32_t m = (uint32_t)(o1 - o0);
+    const bool vrow_ok = c16 < m;
+    v4i ah[KS];
+    {
+      const v4i* ph = (const v4i*)(db.hi + (o0 + (vrow_ok ? c16 : 0)) * dp + 16 * g);
+      const v4i z = {0, 0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < KS; ++k) ah[k] = vrow_ok ? __builtin_nontemporal_load(ph + 4 * k) : z;
+    }
+    rows += min(16u, m);
+    const bool far = bound != 0xFFFFFFFFu && screen_first_tile<KS, MAXQT>(db, o0, m, qh, qp, mq, nqt, ah, tb);
+    if (lane == 0) {
+      if (far) {
+        h2[(uint64_t)q * T + it] = kAbandoned;
+      } else {
+        const uint32_t pos = atomicAdd(sel_count + q, 1u);
+        sel[(uint64_t)q * T + pos] = it;
+      }
+    }
+    rejected += far ? 1u : 0u;
     o0 = n0;
     o1 = n1;
   }
-  if (stats) stats_add(stats, 1, rows, abandoned, items);
+  if (stats) {
+    stats_add(stats, 2, rejected, rejected);   // abandoned and candidates
+    __syncthreads();   // stats_add reuses its LDS words
+    stats_add(stats, 4, rows, rejected);
+  }
 }
 
 // One wave per query: bounds[q] = k-th smallest of h2[q][0 .. min(count, n)),
@@ -148,9 +223,12 @@ constexpr bool haus_variant_used() {
 // best by sketch distance); their k-th smallest bounds the candidates up to
 // kCandPerBlock, whose k-th smallest (abandoned ones exceed it) bounds the
 // remaining candidates; each bound is at least the query's k-th distance.
+// Given the screening buffers (and screening pairs on both sides, and a
+// query that fits the screen's LDS), the remaining candidates are screened
+// on their high planes first and only the survivors take the exact pass.
 hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids, const uint32_t* count,
                             uint32_t T, uint32_t k, uint32_t* thr, uint32_t* h2, unsigned long long* stats,
-                            hipStream_t st) {
+                            uint32_t* sel, uint32_t* sel_count, hipStream_t st) {
   if (q.n_q == 0) return hipSuccess;
   const uint32_t lds_rows = haus_lds_rows(q.max_rows, db.dp);
   const size_t lds = haus_stage_bytes(lds_rows, db.dp);
@@ -168,22 +246,38 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
       // distance then bounds the rest
       const uint32_t na = std::min(n0, std::max(k, 16u));
       hipLaunchKernelGGL(kern, dim3(1, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids, count, T, 0u,
-                         na, (const uint32_t*)nullptr, h2, stats);
+                         na, (const uint32_t*)nullptr, h2, stats, (const uint32_t*)nullptr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if (T <= na) return hipSuccess;
       if (na < n0) {
         hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, na, k, thr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(1, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids, count, T, na,
-                           n0, (const uint32_t*)thr, h2, stats);
+                           n0, (const uint32_t*)thr, h2, stats, (const uint32_t*)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (T <= n0) return hipSuccess;
       }
       hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, n0, k, thr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const uint32_t G = (T - n0 + kCandPerBlock - 1) / kCandPerBlock;
+      const size_t slds = screen_stage_bytes((q.max_rows + 15) / 16 * 16, db.dp);
+      if (sel && sel_count && db.scr && q.scr && !HG && slds <= kStageBudget) {
+        // the rest: high-plane screen, then the exact pass over the survivors
+        if ((e = launch_fill_u32(sel_count, q.n_q, 0, st)) != hipSuccess) return e;
+        auto skern = k_haus_screen<KS, MQ>;
+        if ((e = hipFuncSetAttribute((const void*)skern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds)) !=
+            hipSuccess)
+          return e;
+        hipLaunchKernelGGL(skern, dim3(G, q.n_q), dim3(64 * kHausWaves), slds, st, db, q, ids, count, T, n0,
+                           (const uint32_t*)thr, h2, sel, sel_count, stats);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(G, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids,
+                           (const uint32_t*)sel_count, T, 0u, T, (const uint32_t*)thr, h2, stats,
+                           (const uint32_t*)sel);
+        return hipGetLastError();
+      }
       hipLaunchKernelGGL(kern, dim3(G, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids, count, T, n0,
-                         T, (const uint32_t*)thr, h2, stats);
+                         T, (const uint32_t*)thr, h2, stats, (const uint32_t*)nullptr);
       return hipGetLastError();
     }
   });

@@ -17,9 +17,11 @@ struct HashGeom {
 };
 
 // float32 rows -> exact int8 planes a = 64 * hi + lo (a = 4096 x), squared
-// norms of a, and status bits.
+// norms of a, status bits, and (when scr is not null) per row the screening
+// pair {|hi|^2, float bits of an upper bound of |lo - 31.5| / 64} with the
+// 31.5 taken on the d real coordinates only.
 hipError_t launch_convert(const float* x, uint64_t n_rows, uint32_t d, uint32_t dp,
-                          int8_t* hi, uint8_t* lo, uint32_t* norms, uint32_t* status,
+                          int8_t* hi, uint8_t* lo, uint32_t* norms, uint2* scr, uint32_t* status,
                           int n_cu, hipStream_t st);
 
 // Codes of single vectors: codes [n][R] uint64.
@@ -123,20 +125,28 @@ hipError_t launch_select(const uint16_t* scores, uint64_t ld, uint32_t L, uint32
                          uint32_t* f2_count, const uint32_t* run_if, hipStream_t st);
 
 // Exact squared Hausdorff distances (scaled by 2^24).
+// scr: per-row screening pairs written by launch_convert; bounded re-ranks
+// screen with the high planes first when both sides have them (null: no
+// screening).
 struct HausDb {
   const int8_t* hi; const uint8_t* lo; const uint32_t* norms; const uint64_t* offsets;
   uint64_t n_sets; uint32_t dp;
+  const uint2* scr;
 };
 struct HausQ {
   const int8_t* hi; const uint8_t* lo; const uint32_t* norms; const uint64_t* offsets;
   uint32_t n_q; uint32_t max_rows;
+  const uint2* scr;
 };
 // Candidate mode: items are ids[q][0 .. count[q]) with stride T.  Items that
 // provably cannot be among the k nearest may be abandoned (h2 = all ones);
 // thr [n_q] is scratch for the shared bound.
+// sel [n_q][T] and sel_count [n_q] (both may be null: no screening) are
+// scratch for the candidates that pass the high-plane screen.
 hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids,
                             const uint32_t* count, uint32_t T, uint32_t k, uint32_t* thr,
-                            uint32_t* h2, unsigned long long* stats, hipStream_t st);
+                            uint32_t* h2, unsigned long long* stats, uint32_t* sel, uint32_t* sel_count,
+                            hipStream_t st);
 // All sets: h2 [n_q][n_sets].
 hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipStream_t st);
 size_t haus_lds_bytes(uint32_t max_rows, uint32_t dp);

@@ -84,9 +84,10 @@ def test_index_and_workspace_sizes(bvs):
     p = bvs.Params.make(dim=384, code_bits=4096, fan_in=16, wta_k=64, top_t=1000)
     out = C.c_uint64()
     assert bvs.lib().bvs_index_bytes(C.byref(p), 1_000_000, 52_500_000, C.byref(out)) == 0
-    # planes 2 B/element + counts L B/set + bits L/8 B/set + membership
-    # bitmaps L/8 B/set + set weights 2 B/set + norms/offsets
-    approx = 52_500_000 * (384 * 2 + 4) + 1_000_192 * (4096 + 512 + 512 + 2) + 8 * 1_000_001
+    # planes 2 B/element + norms and screening pairs 12 B/vector + counts
+    # L B/set + bits L/8 B/set + membership bitmaps L/8 B/set + set weights
+    # 2 B/set + offsets
+    approx = 52_500_000 * (384 * 2 + 12) + 1_000_192 * (4096 + 512 + 512 + 2) + 8 * 1_000_001
     assert abs(out.value - approx) < 1 << 20
     assert bvs.lib().bvs_build_workspace_bytes(C.byref(p), 1000, 5000, C.byref(out)) == 0
     assert out.value >= 1000 * (4096 + 512)

@@ -117,6 +117,27 @@ def test_selection_paths_agree(tiny, monkeypatch, env, fallback):
         assert used == fallback
 
 
+def test_screen_keeps_results(tiny, monkeypatch):
+    """The high-plane screen only drops candidates that cannot be in the
+    top-k: results with and without it are identical, and it does reject
+    some candidates."""
+    from paper_2412_03301_amd import bvs
+    runs = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BVS_SCREEN", flag)
+        bvs.profile_enable(False, counters=True)
+        out = [to_np(t) for t in tiny.ix_gpu.search(tiny.q, tiny.q_off, 10)]
+        runs[flag] = (out, bvs.profile_counters())
+        bvs.profile_enable(False)
+    for x, y in zip(runs["1"][0], runs["0"][0]):
+        assert np.array_equal(x, y)
+    on, off = runs["1"][1], runs["0"][1]
+    assert 0 < on["rerank_screened"] <= on["rerank_abandoned"]
+    assert on["rerank_screen_vectors"] > 0
+    assert off["rerank_screened"] == 0 and off["rerank_screen_vectors"] == 0
+    assert on["rerank_candidates"] == off["rerank_candidates"]
+
+
 def test_hausdorff_all_exact(tiny):
     h2 = to_np(tiny.ix_gpu.hausdorff_all(tiny.q, tiny.q_off)).astype(np.int64)
     for i in range(4):
