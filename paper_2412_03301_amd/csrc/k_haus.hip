@@ -76,9 +76,10 @@ k_haus_cand(HausDb db, HausQ qs, uint32_t lds_rows, const uint32_t* __restrict__
 // appended to sel[q][0 .. sel_count[q]) in no particular order (the exact
 // pass writes each result at its candidate's index, so the order does not
 // change any result).  Grid (G, n_q) as k_haus_cand; the whole query is
-// staged (its high plane and screening pairs).
+// staged (its high plane and screening pairs).  At head dimensions up to 384
+// and queries of up to 128 vectors it fits 64 VGPRs, eight waves per SIMD.
 template <int KS, int MAXQT>
-__global__ void __launch_bounds__(64 * kHausWaves)
+__global__ void __launch_bounds__(64 * kHausWaves, KS <= 6 && MAXQT <= 8 ? 8 : 1)
 k_haus_screen(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint32_t* __restrict__ count, uint32_t T,
               uint32_t i0, const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2, uint32_t* __restrict__ sel,
               uint32_t* __restrict__ sel_count, unsigned long long* __restrict__ stats) {
