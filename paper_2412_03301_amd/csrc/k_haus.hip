@@ -262,7 +262,7 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const uint32_t G = (T - n0 + kCandPerBlock - 1) / kCandPerBlock;
       const size_t slds = screen_stage_bytes((q.max_rows + 15) / 16 * 16, db.dp);
-      if (sel && sel_count && db.scr && q.scr && !HG && slds <= kStageBudget) {
+      if (sel && sel_count && db.scr && q.scr && slds <= kStageBudget) {
         // the rest: high-plane screen, then the exact pass over the survivors
         if ((e = launch_fill_u32(sel_count, q.n_q, 0, st)) != hipSuccess) return e;
         auto skern = k_haus_screen<KS, MQ>;

@@ -199,6 +199,9 @@ VARIANTS = {
     # long and short query sketches in one call: both bit-sliced instances
     "mixed_sketches": (2000, 2, 20, 64, 30, 1024, 4, 32, 60, 70, 3, 1,
                        [60, 1, 45, 2, 3, 1, 2] * 10),
+    # d = 768 with a 100-vector query: the exact re-rank stages only part of
+    # the query in LDS while the screen stages all of its high plane
+    "d768_long_queries": (400, 5, 60, 768, 8, 4096, 16, 64, 150, 3, 3, 1, [100, 5, 70]),
 }
 
 
