@@ -401,6 +401,12 @@ def precision(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
         bvs.profile_enable(False)
         rows[mode] = {"qps": n_q * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
                       "stages_ms_per_step": {nm: ms / max(1, c) for nm, (ms, c) in stages.items() if c}}
+        # work counters of one more call (outside the timed region)
+        bvs.profile_enable(False, counters=True)
+        run(mode)
+        torch.cuda.synchronize()
+        rows[mode]["work"] = dict(bvs.profile_counters())
+        bvs.profile_enable(False)
         log(f"{mode}: {rows[mode]['qps']:.0f} q/s ({rows[mode]['ms_per_step']:.2f} ms/step)")
 
     exact_ids = outs["exact"][0].cpu().numpy().view(np.uint32)
@@ -462,18 +468,16 @@ def precision(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
     work = {"filter_pairs": 0.0, "rerank_vectors": 0.0, "rerank_candidates": 0.0, "rerank_abandoned": 0.0}
     roof = None
     if best != "exact":
-        # approximate re-rank: every F2 candidate's rows once, at row_bytes + 4 bytes each
-        f2, _, f2c = ix.candidates(q, q_off)
-        sizes = np.diff(offs)
-        f2n = f2.cpu().numpy().view(np.uint32)
-        cnt = f2c.cpu().numpy()
-        vec = float(sum(int(sizes[f2n[i, :cnt[i]]].sum()) for i in range(n_q)))
+        # approximate re-rank: the candidate rows it read (a device work
+        # counter; abandoned candidates count only the tiles they read), at
+        # row_bytes + 4 bytes each
+        vec = float(rows[best]["work"]["lowp_vectors"])
         rb = 2 * ix.dim_padded if best == "bf16" else -(-ix.dim_padded // 128) * 128
         byts = vec * (rb + 4)
         ach = byts / (st["approx"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "kernel": f"k_haus_lp ({best})", "stage": "approx (query encode, approximate values, selection)",
-                "algorithmic": f"{byts:.4g} bytes per launch ({vec:.4g} candidate vectors x {rb + 4} B)",
+                "algorithmic": f"{byts:.4g} bytes per step ({vec:.4g} candidate vectors read x {rb + 4} B)",
                 "traffic": None}
     cpu = None
     if not args.no_cpu_baseline:

@@ -437,7 +437,8 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
  * the filter stage, 1 database vectors read in full (both planes) by the
  * re-rank stage, 2 re-rank candidates abandoned early (screened ones
  * included), 3 re-rank candidates, 4 database vectors whose high plane the
- * re-rank's screen read, 5 candidates the screen rejected.  bvs_search
+ * re-rank's screen read, 5 candidates the screen rejected, 6 database
+ * vectors read by the approximate re-rank of bvs_search_lowp.  bvs_search
  * screens the candidates after the first 64 on their high planes unless
  * the environment sets BVS_SCREEN=0 (the results are the same).
  * bvs_profile_enable(flags) resets the table; flags: BVS_PROFILE_TIMING
@@ -446,7 +447,7 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
 #define BVS_PROFILE_TIMING 1
 #define BVS_PROFILE_COUNTERS 2
 #define BVS_N_STAGES 12
-#define BVS_N_COUNTERS 6
+#define BVS_N_COUNTERS 7
 typedef struct bvs_stage_times {
   double ms[BVS_N_STAGES];
   uint64_t calls[BVS_N_STAGES];

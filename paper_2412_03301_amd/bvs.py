@@ -36,9 +36,9 @@ EXPORTED = [
 LOWP = {"bf16": 1, "fp8": 2}
 TUNE_MAX = 16
 N_STAGES = 12
-N_COUNTERS = 6
+N_COUNTERS = 7
 COUNTER_NAMES = ("filter_pairs", "rerank_vectors", "rerank_abandoned", "rerank_candidates",
-                 "rerank_screen_vectors", "rerank_screened")
+                 "rerank_screen_vectors", "rerank_screened", "lowp_vectors")
 
 
 class Params(C.Structure):

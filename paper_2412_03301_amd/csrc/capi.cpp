@@ -1512,8 +1512,19 @@ bvs_status bvs_search_lowp(const bvs_index* ix, int fmt, float margin, const flo
   HIP_TRY(staged(prof, S_APPROX, [&]() -> hipError_t {
     ls = lowp_queries(ix, fmt, n_q, max_rows, l, st, &lq);
     if (ls != BVS_OK) return hipSuccess;
-    hipError_t e = launch_haus_lowp(fmt, lowp_db(ix, fmt), lq, w.f2_ids, w.f2_count, T, T, l.approx, st);
+    // The first 64 candidates in full; their k-th value times the factor
+    // bounds the rest: a candidate above it could not be selected anyway.
+    const uint32_t n0 = std::min<uint32_t>(T, 64);
+    unsigned long long* stats = prof.count ? w.stats : nullptr;
+    hipError_t e = launch_haus_lowp(fmt, lowp_db(ix, fmt), lq, w.f2_ids, w.f2_count, T, 0, n0, nullptr, factor,
+                                    l.approx, stats, st);
     if (e != hipSuccess) return e;
+    if (T > n0) {
+      if ((e = launch_kth_bound(l.approx, w.f2_count, T, n0, k, n_q, w.thr, st)) != hipSuccess) return e;
+      e = launch_haus_lowp(fmt, lowp_db(ix, fmt), lq, w.f2_ids, w.f2_count, T, n0, T, w.thr, factor, l.approx,
+                           stats, st);
+      if (e != hipSuccess) return e;
+    }
     return launch_lowp_select(l.approx, w.f2_ids, w.f2_count, T, n_q, k, factor, l.r_ids, l.r_count, st);
   }));
   BVS_TRY(ls);
@@ -1551,7 +1562,8 @@ bvs_status bvs_hausdorff_lowp(const bvs_index* ix, int fmt, const float* d_q, co
   BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, l.w, st, prof));
   LowpQ lq;
   BVS_TRY(lowp_queries(ix, fmt, n_q, max_rows, l, st, &lq));
-  HIP_TRY(launch_haus_lowp(fmt, lowp_db(ix, fmt), lq, d_ids, nullptr, m, m, (uint32_t*)d_h2, st));
+  HIP_TRY(launch_haus_lowp(fmt, lowp_db(ix, fmt), lq, d_ids, nullptr, m, 0, m, nullptr, 1.0f, (uint32_t*)d_h2,
+                           nullptr, st));
   const bvs_status s = read_status(l.w.status, st, "queries");
   prof.finish();
   return s;

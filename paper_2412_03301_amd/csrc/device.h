@@ -173,7 +173,7 @@ __host__ __device__ constexpr uint64_t align_up(uint64_t x, uint64_t a) { return
 // to slot (linear block id % kStatSlots) so that no single address takes
 // every atomic.  The host sums the slots.
 constexpr uint32_t kStatSlots = 64;
-constexpr uint32_t kStatCounters = 6;
+constexpr uint32_t kStatCounters = 7;
 
 // Block-wide sum of up to three per-wave counters (lane 0 of each wave holds
 // the wave's value; every wave must call), added to counters first, first+1,

@@ -152,6 +152,14 @@ k_kth_bound(const uint32_t* __restrict__ h2, const uint32_t* __restrict__ count,
   if (lane == 0) bounds[q] = kth;
 }
 
+hipError_t launch_kth_bound(const uint32_t* vals, const uint32_t* count, uint32_t T, uint32_t n, uint32_t k,
+                            uint32_t n_q, uint32_t* bounds, hipStream_t st) {
+  if (n > 64 || k == 0) return hipErrorInvalidValue;
+  if (n_q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kth_bound, dim3(n_q), dim3(64), 0, st, vals, count, T, n, k, bounds);
+  return hipGetLastError();
+}
+
 // All-sets mode.  Work units (query, chunk of kAllChunk sets) are numbered so
 // that units sharing a chunk of the database run at the same time on the same
 // XCD: consecutive workgroup ids are dealt round-robin over the 8 XCDs, so the

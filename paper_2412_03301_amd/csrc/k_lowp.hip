@@ -152,10 +152,16 @@ constexpr float kInv2p24 = 1.0f / 16777216.0f;
 // non-negative, so they order like the values).  Set s is [o0[s], o0[s] +
 // m[s]) with scale sv[s]; m[s] = 0 marks an absent set.  With NS = 2 every
 // query tile read from LDS feeds both sets' matrix products, which halves
-// the LDS traffic per product.
+// the LDS traffic per product.  With one set and a threshold thr (float
+// bits), the set is abandoned (all ones, which no threshold admits) as soon
+// as a completed part of its value exceeds thr: the largest column minimum
+// after each database tile, the largest row minimum of each query tile on
+// the last one.
 template <int FMT, int KC, int MAXQT, bool HASG, int NS>
 __device__ __forceinline__ void lp_items(const LowpDb& db, const uint64_t (&o0)[NS], const uint32_t (&m)[NS],
-                                         const float (&sv)[NS], const LpView& q, uint32_t (&res)[NS]) {
+                                         const float (&sv)[NS], const LpView& q, uint32_t (&res)[NS],
+                                         uint32_t thr, uint32_t& rows_read) {
+  const bool bounded = NS == 1 && thr != 0xFFFFFFFFu;
   using Op = LpOp<FMT>;
   constexpr uint32_t LB = Op::LB;
   const uint32_t lane = lane_id();
@@ -174,6 +180,9 @@ __device__ __forceinline__ void lp_items(const LowpDb& db, const uint64_t (&o0)[
     for (int i = 0; i < MAXQT; ++i) qmin[s][i] = 0xFFFFFFFFu;
   }
   for (uint32_t vt = 0; vt < mmax; vt += 16) {
+    const bool last = vt + 16 >= mmax;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) rows_read += vt < m[s] ? min(16u, m[s] - vt) : 0u;
     typename Op::T a[NS][KC];
     float nv[NS][4];
     uint32_t vmin[NS][4];
@@ -233,6 +242,13 @@ __device__ __forceinline__ void lp_items(const LowpDb& db, const uint64_t (&o0)[
             qmin[s][qt] = min(qmin[s][qt], bits);
           }
         }
+        if (bounded && last) {
+          const uint32_t rm = qok ? rows4_min_u32(qmin[0][qt]) : 0u;
+          if ((uint32_t)__builtin_amdgcn_readfirstlane((int)row16_max_u32(rm)) > thr) {
+            res[0] = 0xFFFFFFFFu;
+            return;
+          }
+        }
       }
     }
 #pragma unroll
@@ -242,6 +258,10 @@ __device__ __forceinline__ void lp_items(const LowpDb& db, const uint64_t (&o0)[
         const uint32_t cm = row16_min_u32(vmin[s][r]);
         if (vok[s][r]) colmax[s] = max(colmax[s], cm);
       }
+    }
+    if (bounded && !last && (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_dpp_u32(colmax[0])) > thr) {
+      res[0] = 0xFFFFFFFFu;
+      return;
     }
   }
 #pragma unroll
@@ -289,9 +309,11 @@ __device__ __forceinline__ LpView lp_stage(const LowpQ& qs, uint32_t q, uint32_t
 static constexpr uint32_t kLpWaves = 8;
 static constexpr uint32_t kLpPerBlock = 64;
 
-// Grid (ceil(lim / 64), n_q): candidates ids[q][0 .. min(count[q], lim))
-// (count may be null: lim for every query), results as float bits in
-// out[q][i] (stride `stride`).
+// Grid (ceil((lim - i0) / 64), n_q): candidates ids[q][i0 .. min(count[q],
+// lim)) (count may be null: lim for every query), results as float bits in
+// out[q][i] (stride `stride`).  With bounds, candidates whose value provably
+// exceeds float32(bounds[q] as float) * factor get all ones (bounds[q] all
+// ones: no bound).
 // Sets per wave: two where both sets' register tiles fit comfortably.
 template <int FMT, int KC>
 constexpr int lp_sets_per_wave() {
@@ -301,15 +323,20 @@ constexpr int lp_sets_per_wave() {
 template <int FMT, int KC, int MAXQT, bool HASG>
 __global__ void __launch_bounds__(64 * kLpWaves)
 k_haus_lp(LowpDb db, LowpQ qs, uint32_t lds_rows, const uint32_t* __restrict__ ids,
-          const uint32_t* __restrict__ count, uint32_t stride, uint32_t lim, uint32_t* __restrict__ out) {
+          const uint32_t* __restrict__ count, uint32_t stride, uint32_t i0, uint32_t lim,
+          const uint32_t* __restrict__ bounds, float factor, uint32_t* __restrict__ out,
+          unsigned long long* __restrict__ stats) {
   constexpr int NS = lp_sets_per_wave<FMT, KC>();
   extern __shared__ __align__(16) uint8_t smem[];
   const uint32_t q = blockIdx.y;
   const uint32_t i1 = count ? min(count[q], lim) : lim;
-  const uint32_t b0 = blockIdx.x * kLpPerBlock;
+  const uint32_t b0 = i0 + blockIdx.x * kLpPerBlock;
   if (b0 >= i1) return;
   const uint32_t b1 = min(i1, b0 + kLpPerBlock);
+  uint32_t thr = 0xFFFFFFFFu;
+  if (bounds && bounds[q] != 0xFFFFFFFFu) thr = __float_as_uint(__uint_as_float(bounds[q]) * factor);
   const LpView qv = lp_stage(qs, q, lds_rows, smem);
+  uint32_t rows = 0;
   for (uint32_t it = b0 + NS * wave_id(); it < b1; it += NS * kLpWaves) {
     uint64_t o0[NS];
     uint32_t m[NS], res[NS];
@@ -322,13 +349,14 @@ k_haus_lp(LowpDb db, LowpQ qs, uint32_t lds_rows, const uint32_t* __restrict__ i
       m[s] = here ? (uint32_t)(db.offsets[j + 1] - o0[s]) : 0u;
       sv[s] = db.scale ? db.scale[j] : 1.0f;
     }
-    lp_items<FMT, KC, MAXQT, HASG, NS>(db, o0, m, sv, qv, res);
+    lp_items<FMT, KC, MAXQT, HASG, NS>(db, o0, m, sv, qv, res, thr, rows);
     if (lane_id() == 0) {
 #pragma unroll
       for (int s = 0; s < NS; ++s)
         if (it + s < b1) out[(uint64_t)q * stride + it + s] = res[s];
     }
   }
+  if (stats) stats_add(stats, 6, rows);
 }
 
 static constexpr size_t kLpStageBudget = 128 * 1024;
@@ -373,14 +401,15 @@ static hipError_t dispatch_lp_kc(uint32_t kc, F&& f) {
 
 template <int FMT>
 static hipError_t launch_lp_fmt(const LowpDb& db, const LowpQ& q, const uint32_t* ids, const uint32_t* count,
-                                uint32_t stride, uint32_t lim, uint32_t* out, hipStream_t st) {
+                                uint32_t stride, uint32_t i0, uint32_t lim, const uint32_t* bounds, float factor,
+                                uint32_t* out, unsigned long long* stats, hipStream_t st) {
   const uint32_t RB = db.row_bytes;
   const uint32_t kc = RB / (4 * LpOp<FMT>::LB);
   const uint32_t lds_rows = lowp_lds_rows(q.max_rows, RB);
   const size_t lds = (size_t)lds_rows * (RB + 16) + (size_t)lds_rows * 4;
   const uint32_t nqt = (q.max_rows + 15) / 16;
   const bool hasg = lds_rows < nqt * 16;
-  const uint32_t G = (lim + kLpPerBlock - 1) / kLpPerBlock;
+  const uint32_t G = (lim - i0 + kLpPerBlock - 1) / kLpPerBlock;
   return dispatch_lp_kc<FMT>(kc, [&](auto kct) -> hipError_t {
     constexpr int KC = decltype(kct)::value;
     auto go = [&](auto mqt, auto hgt) -> hipError_t {
@@ -393,7 +422,7 @@ static hipError_t launch_lp_fmt(const LowpDb& db, const LowpQ& q, const uint32_t
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(G, q.n_q), dim3(64 * kLpWaves), lds, st, db, q, lds_rows, ids, count,
-                           stride, lim, out);
+                           stride, i0, lim, bounds, factor, out, stats);
         return hipGetLastError();
       }
     };
@@ -412,10 +441,13 @@ static hipError_t launch_lp_fmt(const LowpDb& db, const LowpQ& q, const uint32_t
 }
 
 hipError_t launch_haus_lowp(int fmt, const LowpDb& db, const LowpQ& q, const uint32_t* ids, const uint32_t* count,
-                            uint32_t stride, uint32_t lim, uint32_t* out, hipStream_t st) {
-  if (q.n_q == 0 || lim == 0) return hipSuccess;
-  if (fmt == BVS_LOWP_BF16) return launch_lp_fmt<BVS_LOWP_BF16>(db, q, ids, count, stride, lim, out, st);
-  if (fmt == BVS_LOWP_FP8) return launch_lp_fmt<BVS_LOWP_FP8>(db, q, ids, count, stride, lim, out, st);
+                            uint32_t stride, uint32_t i0, uint32_t lim, const uint32_t* bounds, float factor,
+                            uint32_t* out, unsigned long long* stats, hipStream_t st) {
+  if (q.n_q == 0 || lim <= i0) return hipSuccess;
+  if (fmt == BVS_LOWP_BF16)
+    return launch_lp_fmt<BVS_LOWP_BF16>(db, q, ids, count, stride, i0, lim, bounds, factor, out, stats, st);
+  if (fmt == BVS_LOWP_FP8)
+    return launch_lp_fmt<BVS_LOWP_FP8>(db, q, ids, count, stride, i0, lim, bounds, factor, out, stats, st);
   return hipErrorInvalidValue;
 }
 

@@ -200,9 +200,17 @@ uint32_t lowp_row_bytes(int fmt, uint32_t dp);
 hipError_t launch_lowp_encode(const int8_t* hi, const uint8_t* lo, uint32_t dp, const uint64_t* offsets,
                               uint64_t n_sets, int fmt, uint32_t row_bytes, uint8_t* out, float* scale,
                               hipStream_t st);
-// Approximate squared Hausdorff values (float bits) of ids[q][0 .. min(count[q], lim)).
+// Approximate squared Hausdorff values (float bits) of ids[q][i0 .. min(count[q], lim)).
+// With bounds (float bits per query, all ones: none), values that provably
+// exceed bounds[q] * factor (float32) come out all ones.  stats (nullable):
+// rows read, added to work counter 6.
 hipError_t launch_haus_lowp(int fmt, const LowpDb& db, const LowpQ& q, const uint32_t* ids, const uint32_t* count,
-                            uint32_t stride, uint32_t lim, uint32_t* out, hipStream_t st);
+                            uint32_t stride, uint32_t i0, uint32_t lim, const uint32_t* bounds, float factor,
+                            uint32_t* out, unsigned long long* stats, hipStream_t st);
+// bounds[q] = k-th smallest of vals[q][0 .. min(count[q], n)) (stride T,
+// n <= 64) for q < n_q, all ones when fewer than k.
+hipError_t launch_kth_bound(const uint32_t* vals, const uint32_t* count, uint32_t T, uint32_t n, uint32_t k,
+                            uint32_t n_q, uint32_t* bounds, hipStream_t st);
 // Candidates to re-check: the prefix of (value, id) order within factor of the k-th value.
 hipError_t launch_lowp_select(const uint32_t* approx, const uint32_t* ids, const uint32_t* count, uint32_t T,
                               uint32_t n_q, uint32_t k, float factor, uint32_t* r_ids, uint32_t* r_count,
