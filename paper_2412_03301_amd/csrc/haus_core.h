@@ -54,9 +54,9 @@ static constexpr uint32_t kCandPerBlock = kCandPerItem;
 __host__ __device__ constexpr uint32_t q_row_stride(uint32_t dp) { return dp + 16; }
 
 // Bytes of LDS that staging `rows` query rows takes (planes with a 16-byte
-// row pad against bank conflicts, and the norms).
+// row pad against bank conflicts, the norms and the screening pairs).
 __host__ __device__ constexpr size_t haus_stage_bytes(uint32_t rows, uint32_t dp) {
-  return (size_t)rows * q_row_stride(dp) * 2 + (size_t)rows * 4;
+  return (size_t)rows * q_row_stride(dp) * 2 + (size_t)rows * 12;
 }
 
 // LDS of the screening pass: the high plane (same row stride) and the
@@ -75,9 +75,11 @@ struct QView {
   const uint8_t* hs;
   const uint8_t* ls;
   const uint32_t* ns;
+  const uint2* ss;     // screening pairs of the staged rows (pad rows: kScreenPad)
   const uint8_t* hg;
   const uint8_t* lg;
   const uint32_t* ng;
+  const uint2* sg;     // null when the query has no screening pairs
   uint32_t mq, nqt, nqt_s;
 };
 
@@ -154,6 +156,92 @@ __device__ __forceinline__ bool screen_first_tile(const HausDb& db, uint64_t o0,
     far = far || (4 * g + r < m && cm > 0.0f);
   }
   return ballot(far) != 0;
+}
+
+// The same screen against a query staged by stage_query (query tiles past
+// the staged rows read from global memory when HASG).
+template <int KS, int MAXQT, bool HASG>
+__device__ __forceinline__ bool screen_first_tile_q(uint32_t m, const QView& q, const v4i (&ah)[KS],
+                                                    const uint2 (&sv)[4], float tb) {
+  const uint32_t lane = lane_id();
+  const uint32_t g = lane >> 4, c16 = lane & 15;
+  const uint32_t dp = KS * 64;
+  const uint32_t QS = q_row_stride(dp);
+  const bool whole = m <= 16;
+  float colm[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) colm[r] = __builtin_inff();
+#pragma unroll
+  for (int qt = 0; qt < MAXQT; ++qt) {
+    if ((uint32_t)qt < q.nqt) {
+      v4i hh = {0, 0, 0, 0};
+      const uint32_t qi = qt * 16 + c16;
+      uint2 sq;
+      if (!HASG || (uint32_t)qt < q.nqt_s) {
+        const uint8_t* bh = q.hs + qi * QS + 16 * g;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) hh = mfma_i8(ah[k], *(const v4i*)(bh + 64 * k), hh);
+        sq = q.ss[qi];
+      } else {
+        asm volatile("" ::: "memory");
+        const uint8_t* hg = uniform_ptr(q.hg);
+        uint32_t cl = c16;
+        asm volatile("" : "+s"(hg), "+v"(cl));
+        const uint32_t r = min(qt * 16 + cl, q.mq - 1);
+        const uint8_t* bh = hg + r * dp + 16 * g;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) hh = mfma_i8(ah[k], *(const v4i*)(bh + 64 * k), hh);
+        sq = qi < q.mq ? q.sg[r] : make_uint2(kScreenPad, 0u);
+      }
+      const float tq = tb + __uint_as_float(sq.y);
+      float rowm = __builtin_inff();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int h2 = (int)(sv[r].x + sq.x) - 2 * hh[r];
+        const float x = tq + __uint_as_float(sv[r].y);
+        const float mf = fmaf(-x, x, (float)h2);
+        rowm = fminf(rowm, mf);
+        colm[r] = fminf(colm[r], mf);
+      }
+      if (whole) {
+        const float rm = rows4_min_f32(rowm);
+        if (ballot(qi < q.mq && rm > 0.0f)) return true;
+      }
+    }
+  }
+  bool far = false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float cm = row16_min_f32(colm[r]);
+    far = far || (4 * g + r < m && cm > 0.0f);
+  }
+  return ballot(far) != 0;
+}
+
+// Load the first tile's high planes and screening pairs of set [o0, o0 + m)
+// and screen it against bound (true: the set is provably farther).
+template <int KS, int MAXQT, bool HASG>
+__device__ __forceinline__ bool screen_set(const HausDb& db, uint64_t o0, uint32_t m, const QView& q,
+                                           uint32_t bound) {
+  const uint32_t lane = lane_id();
+  const uint32_t g = lane >> 4, c16 = lane & 15;
+  const uint32_t dp = KS * 64;
+  const bool vrow_ok = c16 < m;
+  v4i ah[KS];
+  uint2 sv[4];
+  {
+    const v4i* ph = (const v4i*)(db.hi + (o0 + (vrow_ok ? c16 : 0)) * dp + 16 * g);
+    const v4i z = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < KS; ++k) ah[k] = vrow_ok ? __builtin_nontemporal_load(ph + 4 * k) : z;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t v = 4 * g + r;
+      sv[r] = v < m ? db.scr[o0 + v] : make_uint2(kScreenPad, 0u);
+    }
+  }
+  const float tb = sqrtf((float)bound) * (1.0f / 64.0f) * (1.0f + 0x1p-19f);
+  return screen_first_tile_q<KS, MAXQT, HASG>(m, q, ah, sv, tb);
 }
 
 // Squared Hausdorff distance (2^24-scaled) of database set [o0, o0 + m)
@@ -276,6 +364,7 @@ __device__ __forceinline__ QView stage_query(const HausQ& qs, uint32_t q, uint32
   uint8_t* qh_s = smem;
   uint8_t* ql_s = smem + (size_t)lds_rows * QS;
   uint32_t* qn_s = (uint32_t*)(smem + (size_t)2 * lds_rows * QS);
+  uint2* qs_s = (uint2*)(qn_s + lds_rows);
   const uint32_t c16n = dp / 16;
   for (uint32_t i = threadIdx.x; i < rows * c16n; i += blockDim.x) {
     const uint32_t r = i / c16n, c = i % c16n;
@@ -287,13 +376,18 @@ __device__ __forceinline__ QView stage_query(const HausQ& qs, uint32_t q, uint32
     *(uint4*)(qh_s + r * QS + 16 * c) = h;
     *(uint4*)(ql_s + r * QS + 16 * c) = l;
   }
-  for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x) qn_s[r] = r < v.mq ? qs.norms[o0 + r] : 0u;
+  for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x) {
+    qn_s[r] = r < v.mq ? qs.norms[o0 + r] : 0u;
+    if (qs.scr) qs_s[r] = r < v.mq ? qs.scr[o0 + r] : make_uint2(kScreenPad, 0u);
+  }
   v.hs = qh_s;
   v.ls = ql_s;
   v.ns = qn_s;
+  v.ss = qs_s;
   v.hg = (const uint8_t*)qs.hi + o0 * dp;
   v.lg = qs.lo + o0 * dp;
   v.ng = qs.norms + o0;
+  v.sg = qs.scr ? qs.scr + o0 : nullptr;
   __syncthreads();
   return v;
 }

@@ -28,7 +28,7 @@ k_haus_queue(HausDb db, HausQ qs, QueueArgs a) {
   const uint32_t n_q = qs.n_q, nch = a.nch;
   const uint32_t n_items = n_q * nch;
   const uint32_t w = wave_id();
-  uint32_t rows = 0, abandoned = 0, items = 0;
+  uint32_t rows = 0, abandoned = 0, items = 0, srows = 0, screened = 0;
   uint32_t staged = 0xFFFFFFFFu;
   QView qv;
   for (;;) {
@@ -63,7 +63,15 @@ k_haus_queue(HausDb db, HausQ qs, QueueArgs a) {
         const uint32_t j = a.ids[(uint64_t)q * a.T + it];
         const uint64_t o0 = db.offsets[j];
         const uint32_t m = (uint32_t)(db.offsets[j + 1] - o0);
-        const uint32_t hsq = haus_item<KS, kMaxQueryTiles, true>(db, o0, m, qv, bound, a.stats ? &rows : nullptr);
+        // candidates after the first chunk: the high-plane screen first
+        uint32_t hsq;
+        if (bound != 0xFFFFFFFFu && db.scr && qv.sg && screen_set<KS, kMaxQueryTiles, true>(db, o0, m, qv, bound)) {
+          hsq = kAbandoned;
+          srows += min(16u, m);
+          ++screened;
+        } else {
+          hsq = haus_item<KS, kMaxQueryTiles, true>(db, o0, m, qv, bound, a.stats ? &rows : nullptr);
+        }
         if (lane_id() == 0) {
           a.h2[(uint64_t)q * a.T + it] = hsq;
           if (chunk == 0) s_h2[it] = hsq;
@@ -84,7 +92,11 @@ k_haus_queue(HausDb db, HausQ qs, QueueArgs a) {
     // the item counter and the staged query are rewritten by the next item
     __syncthreads();
   }
-  if (a.stats) stats_add(a.stats, 1, rows, abandoned, items);
+  if (a.stats) {
+    stats_add(a.stats, 1, rows, abandoned, items);
+    __syncthreads();   // stats_add reuses its LDS words
+    stats_add(a.stats, 4, srows, screened);
+  }
 }
 
 template <typename F>
