@@ -439,8 +439,8 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
  * included), 3 re-rank candidates, 4 database vectors whose high plane the
  * re-rank's screen read, 5 candidates the screen rejected, 6 database
  * vectors read by the approximate re-rank of bvs_search_lowp.  bvs_search
- * screens the candidates after the first 64 on their high planes unless
- * the environment sets BVS_SCREEN=0 (the results are the same).
+ * and batches screen the candidates after the first 64 on their high planes
+ * unless the environment sets BVS_SCREEN=0 (the results are the same).
  * bvs_profile_enable(flags) resets the table; flags: BVS_PROFILE_TIMING
  * records the stage events, BVS_PROFILE_COUNTERS collects the work counters
  * (their atomics slow the counted kernels somewhat), 0 turns both off. */

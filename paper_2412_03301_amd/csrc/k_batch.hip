@@ -11,7 +11,8 @@
 // The first chunk of a query is computed in full; its workgroup then
 // publishes the k-th smallest of those distances as the query's bound (an
 // atomic word: 0 = not yet, else bound + 1).  A later chunk reads the word
-// once when it starts: with a bound it abandons sets that provably cannot be
+// once when it starts: with a bound it first screens each set on its first
+// tile's high planes (haus_core.h) and abandons sets that provably cannot be
 // among the k nearest, without one it computes every distance.  Either way
 // the k nearest are computed exactly, so the result does not depend on
 // timing.

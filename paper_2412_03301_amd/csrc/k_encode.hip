@@ -127,12 +127,18 @@ __device__ __forceinline__ void hash_keys(const int16_t* __restrict__ av, const 
   }
 }
 
-// The k-th largest of the wave's 64 R unique keys.
+// The k-th largest of the wave's 64 R unique keys.  A prefix above the
+// largest key admits no key, so those bits are skipped without counting.
 template <int R>
 __device__ __forceinline__ uint32_t kth_largest(const uint32_t (&key)[R], uint32_t k, int topbit) {
+  uint32_t kmax = 0;
+#pragma unroll
+  for (int t = 0; t < R; ++t) kmax = max(kmax, key[t]);
+  kmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_dpp_u32(kmax));
   uint32_t theta = 0;
   for (int b = topbit; b >= 0; --b) {
     const uint32_t cand = theta | (1u << b);
+    if (cand > kmax) continue;
     // per-lane count, then one wave sum (no per-key ballots held in scalars)
     uint32_t local = 0;
 #pragma unroll
