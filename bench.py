@@ -391,12 +391,16 @@ def precision(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
         for i in range(args.warmup):
             run(mode)
         torch.cuda.synchronize()
-        bvs.profile_enable(True)
         t0 = time.perf_counter()
         for i in range(args.steps):
             run(mode)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        # stage times from as many steps again with the per-stage events on
+        bvs.profile_enable(True)
+        for i in range(args.steps):
+            run(mode)
+        torch.cuda.synchronize()
         stages = bvs.profile_read()
         bvs.profile_enable(False)
         rows[mode] = {"qps": n_q * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
@@ -604,13 +608,17 @@ def learned_bench(args, w, cfg, dev):
             ws = ix.search_workspace(n_q, NQ)
             for i in range(args.warmup):
                 ix.search(q, q_off, k, ws=ws, out=out)
-            bvs.profile_enable(True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for i in range(args.steps):
                 ix.search(q, q_off, k, ws=ws, out=out)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
+            # stage times from as many steps again with the per-stage events on
+            bvs.profile_enable(True)
+            for i in range(args.steps):
+                ix.search(q, q_off, k, ws=ws, out=out)
+            torch.cuda.synchronize()
             st = {nm: ms / max(1, c) for nm, (ms, c) in bvs.profile_read().items() if c}
             bvs.profile_enable(False)
             if form == "learned" and T == w["top_t"]:
@@ -757,7 +765,6 @@ def main():
         ix.search(q, q_off, k, ws=ws, out=out)
         log(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    bvs.profile_enable(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
@@ -768,6 +775,12 @@ def main():
     torch.cuda.synchronize()
     wall_s = time.perf_counter() - t_wall
     gpu_ms = ev0.elapsed_time(ev1)
+    # stage times from the same number of steps with the per-stage events on
+    # (outside the timed region: the events add a little time of their own)
+    bvs.profile_enable(True)
+    for i in range(args.steps):
+        ix.search(q, q_off, k, ws=ws, out=out)
+    torch.cuda.synchronize()
     stages = bvs.profile_read()
     # work counters from one more (untimed) step: the counted work is the
     # same every step for a fixed batch
