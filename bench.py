@@ -177,8 +177,12 @@ def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=
     else:
         ach = rer_bytes / (per_step["rerank"] / 1e3) / 1e9
         # with the screen, the stage is the screen kernel (high planes of the
-        # candidates after the first 64) and the exact kernel's launches
-        label = f"k_haus_screen + {rerank_kernel} (re-rank stage)" if scr_vec else rerank_kernel
+        # candidates after the first 64) and the exact kernel's launches; the
+        # persistent batched kernel screens inside itself
+        label = rerank_kernel
+        if scr_vec:
+            label = (f"{rerank_kernel} (re-rank stage, first-tile screen inside the kernel)"
+                     if rerank_kernel == "k_haus_queue" else f"k_haus_screen + {rerank_kernel} (re-rank stage)")
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "kernel": label,
                 "algorithmic": (f"{rer_bytes:.4g} bytes per step, all re-rank launches (vectors read in full "
