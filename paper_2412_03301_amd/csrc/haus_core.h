@@ -97,72 +97,26 @@ __device__ __forceinline__ void tile_products(const v4i (&ah)[KS], const v4i (&a
   }
 }
 
-// Screen of the first database tile (rows [0, min(16, m)) of the set, whose
-// high planes are in ah) against a query staged by stage_query_screen (high
-// plane rows qh with stride dp + 16 and screening pairs qs, pad rows far):
-// whether the set provably has Hausdorff^2 > bound.  Per pair, |hi_a -
-// hi_b|^2 - X^2 with X >= sqrt(bound) / 64 + r_a + r_b, by one fused
-// multiply-add whose sign is exact; pad rows and columns come out far.  A
-// database vector far from every query vector decides (column minima); when
-// the tile is the whole set, so does a query vector far from every vector of
-// the tile (row minima), checked after each query tile.
-template <int KS, int MAXQT>
-__device__ __forceinline__ bool screen_first_tile(const HausDb& db, uint64_t o0, uint32_t m, const uint8_t* qh,
-                                                  const uint2* qs, uint32_t mq, uint32_t nqt, const v4i (&ah)[KS],
-                                                  float tb) {
-  const uint32_t lane = lane_id();
-  const uint32_t g = lane >> 4, c16 = lane & 15;
-  const uint32_t QS = q_row_stride(KS * 64);
-  const bool whole = m <= 16;
-  uint32_t hv[4];
-  float rv[4], colm[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t v = 4 * g + r;
-    const uint2 sv = v < m ? db.scr[o0 + v] : make_uint2(kScreenPad, 0u);
-    hv[r] = sv.x;
-    rv[r] = __uint_as_float(sv.y);
-    colm[r] = __builtin_inff();
-  }
-#pragma unroll
-  for (int qt = 0; qt < MAXQT; ++qt) {
-    if ((uint32_t)qt < nqt) {
-      v4i hh = {0, 0, 0, 0};
-      const uint32_t qi = qt * 16 + c16;
-      const uint8_t* bh = qh + qi * QS + 16 * g;
-#pragma unroll
-      for (int k = 0; k < KS; ++k) hh = mfma_i8(ah[k], *(const v4i*)(bh + 64 * k), hh);
-      const uint2 sq = qs[qi];
-      const float tq = tb + __uint_as_float(sq.y);
-      float rowm = __builtin_inff();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int h2 = (int)(hv[r] + sq.x) - 2 * hh[r];
-        const float x = tq + rv[r];
-        const float mf = fmaf(-x, x, (float)h2);
-        rowm = fminf(rowm, mf);
-        colm[r] = fminf(colm[r], mf);
-      }
-      if (whole) {
-        const float rm = rows4_min_f32(rowm);
-        if (ballot(qi < mq && rm > 0.0f)) return true;
-      }
-    }
-  }
-  bool far = false;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const float cm = row16_min_f32(colm[r]);
-    far = far || (4 * g + r < m && cm > 0.0f);
-  }
-  return ballot(far) != 0;
+// sqrt(bound) / 64 rounded up: the factor covers the int -> float and the
+// square-root roundings, and the additions of the screen.
+__device__ __forceinline__ float screen_scale(uint32_t bound) {
+  return sqrtf((float)bound) * (1.0f / 64.0f) * (1.0f + 0x1p-19f);
 }
 
-// The same screen against a query staged by stage_query (query tiles past
-// the staged rows read from global memory when HASG).
+// Screen of the first database tile (rows [0, min(16, m)) of a set, whose
+// high planes are in ah and whose screening pairs are sv[r] for the tile's
+// row 4 (lane / 16) + r, pad for rows past the set): whether the set
+// provably has Hausdorff^2 > bound, with tb >= sqrt(bound) / 64.  The query
+// view needs the high planes and screening pairs of its staged rows (query
+// tiles past them are read from global memory when HASG).  Per pair,
+// |hi_a - hi_b|^2 - X^2 with X >= tb + r_a + r_b, by one fused multiply-add
+// whose sign is exact; pad rows and columns come out far.  A database
+// vector far from every query vector decides (column minima); when the tile
+// is the whole set, so does a query vector far from every vector of the
+// tile (row minima), checked after each query tile.
 template <int KS, int MAXQT, bool HASG>
-__device__ __forceinline__ bool screen_first_tile_q(uint32_t m, const QView& q, const v4i (&ah)[KS],
-                                                    const uint2 (&sv)[4], float tb) {
+__device__ __forceinline__ bool screen_first_tile(uint32_t m, const QView& q, const v4i (&ah)[KS],
+                                                  const uint2 (&sv)[4], float tb) {
   const uint32_t lane = lane_id();
   const uint32_t g = lane >> 4, c16 = lane & 15;
   const uint32_t dp = KS * 64;
@@ -240,8 +194,7 @@ __device__ __forceinline__ bool screen_set(const HausDb& db, uint64_t o0, uint32
       sv[r] = v < m ? db.scr[o0 + v] : make_uint2(kScreenPad, 0u);
     }
   }
-  const float tb = sqrtf((float)bound) * (1.0f / 64.0f) * (1.0f + 0x1p-19f);
-  return screen_first_tile_q<KS, MAXQT, HASG>(m, q, ah, sv, tb);
+  return screen_first_tile<KS, MAXQT, HASG>(m, q, ah, sv, screen_scale(bound));
 }
 
 // Squared Hausdorff distance (2^24-scaled) of database set [o0, o0 + m)
@@ -393,27 +346,32 @@ __device__ __forceinline__ QView stage_query(const HausQ& qs, uint32_t q, uint32
 }
 
 // Stage the high plane and the screening pairs of all 16 ceil(m_q / 16) rows
-// of query q (rows past the query: zero plane, pad pair) for the screen.
-// Returns m_q.  Ends with a workgroup barrier.
-__device__ __forceinline__ uint32_t stage_query_screen(const HausQ& qs, uint32_t q, uint32_t dp, uint8_t* smem,
-                                                       uint8_t*& qh, uint2*& qp) {
+// of query q (rows past the query: zero plane, pad pair) for the screen, and
+// describe them as a query view (no low planes or norms).  Ends with a
+// workgroup barrier.
+__device__ __forceinline__ QView stage_query_screen(const HausQ& qs, uint32_t q, uint32_t dp, uint8_t* smem) {
+  QView v = {};
   const uint64_t o0 = qs.offsets[q];
-  const uint32_t mq = (uint32_t)(qs.offsets[q + 1] - o0);
-  const uint32_t rows = (mq + 15) / 16 * 16;
+  v.mq = (uint32_t)(qs.offsets[q + 1] - o0);
+  v.nqt = (v.mq + 15) / 16;
+  v.nqt_s = v.nqt;
+  const uint32_t rows = v.nqt * 16;
   const uint32_t QS = q_row_stride(dp);
-  qh = smem;
-  qp = (uint2*)(smem + (size_t)rows * QS);
+  uint8_t* qh = smem;
+  uint2* qp = (uint2*)(smem + (size_t)rows * QS);
   const uint32_t c16n = dp / 16;
   for (uint32_t i = threadIdx.x; i < rows * c16n; i += blockDim.x) {
     const uint32_t r = i / c16n, c = i % c16n;
     uint4 h = make_uint4(0, 0, 0, 0);
-    if (r < mq) h = *(const uint4*)(qs.hi + (o0 + r) * dp + 16 * c);
+    if (r < v.mq) h = *(const uint4*)(qs.hi + (o0 + r) * dp + 16 * c);
     *(uint4*)(qh + r * QS + 16 * c) = h;
   }
   for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x)
-    qp[r] = r < mq ? qs.scr[o0 + r] : make_uint2(kScreenPad, 0u);
+    qp[r] = r < v.mq ? qs.scr[o0 + r] : make_uint2(kScreenPad, 0u);
+  v.hs = qh;
+  v.ss = qp;
   __syncthreads();
-  return mq;
+  return v;
 }
 
 // k-th smallest of vals[0 .. nv), nv <= 64, computed by one whole wave (every

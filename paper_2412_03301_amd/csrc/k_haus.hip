@@ -1,6 +1,7 @@
 // Exact Hausdorff re-rank (Def. 4) of candidate sets and of every database
-// set, one launch per stage, and the top-k of the results.  The distance
-// arithmetic lives in haus_core.h.
+// set, one launch per stage, the high-plane screen of the bounded
+// candidates, and the top-k of the results.  The distance arithmetic and
+// the screen's bound live in haus_core.h.
 //
 // Mapping.  One workgroup (8 waves) takes one query and a range of items
 // (candidate sets or database sets).  It stages as many of the query's rows
@@ -90,16 +91,8 @@ k_haus_screen(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint3
   if (b0 >= i1) return;
   const uint32_t b1 = min(i1, b0 + kCandPerBlock);
   const uint32_t bound = bounds[q];
-  uint8_t* qh;
-  uint2* qp;
-  const uint32_t mq = stage_query_screen(qs, q, KS * 64, smem, qh, qp);
-  const uint32_t nqt = (mq + 15) / 16;
-  // sqrt(bound) / 64 rounded up: the factor covers the int -> float and the
-  // square-root roundings, and the additions in the screen
-  const float tb = sqrtf((float)bound) * (1.0f / 64.0f) * (1.0f + 0x1p-19f);
+  const QView qv = stage_query_screen(qs, q, KS * 64, smem);
   const uint32_t w = wave_id(), lane = lane_id();
-  const uint32_t g = lane >> 4, c16 = lane & 15;
-  constexpr uint32_t dp = KS * 64;
   uint32_t rows = 0, rejected = 0;
   const cptr<uint32_t> idq = as_const(ids) + (uint64_t)q * T;
   const cptr<uint64_t> offs = as_const(db.offsets);
@@ -111,16 +104,8 @@ k_haus_screen(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint3
     const uint64_t n0 = offs[jn], n1 = offs[jn + 1];
     jn = id_at(it + 2 * kHausWaves);
     const uint32_t m = (uint32_t)(o1 - o0);
-    const bool vrow_ok = c16 < m;
-    v4i ah[KS];
-    {
-      const v4i* ph = (const v4i*)(db.hi + (o0 + (vrow_ok ? c16 : 0)) * dp + 16 * g);
-      const v4i z = {0, 0, 0, 0};
-#pragma unroll
-      for (int k = 0; k < KS; ++k) ah[k] = vrow_ok ? __builtin_nontemporal_load(ph + 4 * k) : z;
-    }
     rows += min(16u, m);
-    const bool far = bound != 0xFFFFFFFFu && screen_first_tile<KS, MAXQT>(db, o0, m, qh, qp, mq, nqt, ah, tb);
+    const bool far = bound != 0xFFFFFFFFu && screen_set<KS, MAXQT, false>(db, o0, m, qv, bound);
     if (lane == 0) {
       if (far) {
         h2[(uint64_t)q * T + it] = kAbandoned;
