@@ -140,6 +140,37 @@ def test_batch_selection_paths(mixed, per_call, monkeypatch, env):
     b.close()
 
 
+def test_screen_on_and_off_agree(mixed, per_call, monkeypatch):
+    """The high-plane screen (a pass of its own in the per-call search, inside
+    the persistent kernel in a batch) rejects candidates only when they
+    provably cannot be among the k nearest: results with it switched off are
+    identical, and with it on the per-call search does reject some.  (In a
+    batch a later chunk screens only if its query's bound was published
+    before the chunk started, which depends on timing; with 24 queries the
+    chunks mostly start together.)"""
+    from paper_2412_03301_amd import bvs
+    _say("screen on/off")
+    counts = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BVS_SCREEN", flag)
+        bvs.profile_enable(False, counters=True)
+        _same([to_np(t) for t in mixed.ix_gpu.search(mixed.q, mixed.q_off, K)], per_call)
+        counts[("call", flag)] = bvs.profile_counters()
+        b = bvs.Batch(mixed.ix_gpu, mixed.q, mixed.q_off, K, lds_rows=64, waves=4, graph=False)
+        bvs.profile_enable(False, counters=True)
+        _same([to_np(t) for t in b.run()], per_call)
+        counts[("batch", flag)] = bvs.profile_counters()
+        bvs.profile_enable(False)
+        b.close()
+    on, off = counts[("call", "1")], counts[("call", "0")]
+    assert on["rerank_screened"] > 0 and on["rerank_screen_vectors"] > 0
+    for kind in ("call", "batch"):
+        on, off = counts[(kind, "1")], counts[(kind, "0")]
+        assert off["rerank_screened"] == 0 and off["rerank_screen_vectors"] == 0, kind
+        assert on["rerank_screened"] <= on["rerank_abandoned"], kind
+        assert on["rerank_candidates"] == off["rerank_candidates"], kind
+
+
 def test_batch_single_query_and_k(mixed, oracle_res):
     from paper_2412_03301_amd import bvs
     i = SIZES.index(256)
