@@ -418,7 +418,9 @@ hipError_t launch_bitmap_planes(const uint8_t* cnt, uint64_t ld, uint32_t L, uin
 }
 
 // ---------------------------------------------------------------- query sketch
-// One wave per query.  Lane l owns code words t = l and l + 64.
+// One wave per query.  Lane l owns code word l (L <= 4096, so R <= 64): the
+// counts of positions 64 l .. 64 l + 63 stay in its registers for the
+// selection of the A largest.
 __global__ void __launch_bounds__(64)
 k_query_sketch(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ q_off, uint32_t L,
                uint32_t R, uint32_t A, uint32_t lgL, uint16_t* __restrict__ cq, uint64_t* __restrict__ sq,
@@ -426,32 +428,34 @@ k_query_sketch(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ 
   const uint32_t q = blockIdx.x, lane = lane_id();
   const uint64_t o0 = q_off[q], o1 = q_off[q + 1];
   uint16_t* cqq = cq + (uint64_t)q * L;
-  for (uint32_t t = lane; t < R; t += BVS_WAVE) {
-    uint32_t c[64];
+  const bool own = lane < R;
+  uint32_t c[64];
 #pragma unroll
-    for (int b = 0; b < 64; ++b) c[b] = 0;
+  for (int b = 0; b < 64; ++b) c[b] = 0;
+  if (own) {
     uint64_t orw = 0;
     for (uint64_t v = o0; v < o1; ++v) {
-      const uint64_t w = codes[v * R + t];
+      const uint64_t w = codes[v * R + lane];
       orw |= w;
 #pragma unroll
       for (int b = 0; b < 64; ++b) c[b] += (uint32_t)((w >> b) & 1);
     }
-    sq[(uint64_t)q * R + t] = orw;
+    sq[(uint64_t)q * R + lane] = orw;
 #pragma unroll
     for (int b = 0; b < 64; b += 2)
-      *(uint32_t*)(cqq + 64u * t + b) = (c[b] & 0xFFFF) | ((c[b + 1] & 0xFFFF) << 16);
+      *(uint32_t*)(cqq + 64u * lane + b) = (c[b] & 0xFFFF) | ((c[b + 1] & 0xFFFF) << 16);
   }
-  __syncthreads();
   // The A largest (count, -position) keys, one per round.
   uint32_t last = 0xFFFFFFFFu;
   uint32_t p[8];
   for (uint32_t a = 0; a < A; ++a) {
     uint32_t best = 0;
-    bool found = false;
-    for (uint32_t i = lane; i < L; i += BVS_WAVE) {
-      const uint32_t key = ((uint32_t)cqq[i] << lgL) | (L - 1u - i);
-      if (key < last && (!found || key > best)) { best = key; found = true; }
+    if (own) {
+#pragma unroll
+      for (int b = 0; b < 64; ++b) {
+        const uint32_t key = (c[b] << lgL) | (L - 1u - (64u * lane + (uint32_t)b));
+        best = key < last ? max(best, key) : best;
+      }
     }
     // keys are unique and >= 0; a lane with no candidate contributes 0, which
     // can only win when fewer than A positions exist (A <= L is checked).
@@ -461,11 +465,11 @@ k_query_sketch(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ 
   }
   uint64_t chunks = 0;
   for (uint32_t a = 0; a < A; ++a) chunks |= 1ull << (p[a] >> 7);
-  for (uint32_t t = lane; t < R; t += BVS_WAVE) {
+  if (own) {
     uint64_t gw = 0;
     for (uint32_t a = 0; a < A; ++a)
-      if ((p[a] >> 6) == t) gw |= 1ull << (p[a] & 63);
-    gate[(uint64_t)q * R + t] = gw;
+      if ((p[a] >> 6) == lane) gw |= 1ull << (p[a] & 63);
+    gate[(uint64_t)q * R + lane] = gw;
   }
   if (lane == 0) gate_chunks[q] = chunks;
 }
@@ -474,6 +478,7 @@ hipError_t launch_query_sketch(const uint64_t* codes, const uint64_t* q_off, uin
                                uint32_t R, uint32_t A, uint16_t* cq, uint64_t* sq, uint32_t* pos,
                                uint64_t* gate, uint64_t* gate_chunks, hipStream_t st) {
   if (n_q == 0) return hipSuccess;
+  if (R > 64 || A > 8) return hipErrorInvalidValue;
   uint32_t lgL = 0;
   while ((1u << lgL) < L) ++lgL;
   hipLaunchKernelGGL(k_query_sketch, dim3(n_q), dim3(64), 0, st, codes, q_off, L, R, A, lgL, cq, sq, pos,
