@@ -154,9 +154,11 @@ def sketch_rows(ix, q, q_off):
     return float(np.unpackbits(sq.cpu().numpy().view(np.uint8)).sum())
 
 
-def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=None):
+def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=None, counted=True):
     """Roofline of the dominant stage (filter or re-rank) from its
-    algorithmic work per launch and its measured time per launch."""
+    algorithmic work per launch and its measured time per launch.  counted:
+    the committed counter summaries were taken on this workload (the 1M-set,
+    d = 384 one); otherwise traffic is null."""
     csrc = os.path.join(ROOT, "paper_2412_03301_amd", "csrc")
     dominant = max(("filter", "rerank"), key=lambda s2: per_step.get(s2, 0.0))
     # exact passes read both planes and the norm; the screen reads the high
@@ -173,7 +175,8 @@ def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=
         roof = {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_TOPS, "unit": "Tops/s", "frac": ach / ALU_PEAK_TOPS,
                 "kernel": "k_filter_sliced<4,9>",
                 "algorithmic": f"{work['sketch_rows']:.4g} query rows x {words} words x 2 int32 ops per launch",
-                "traffic": traffic_from_profiles(os.path.join(csrc, "k_sliced.hip"), "k_filter_sliced")}
+                "traffic": traffic_from_profiles(os.path.join(csrc, "k_sliced.hip"), "k_filter_sliced")
+                if counted else None}
     else:
         ach = rer_bytes / (per_step["rerank"] / 1e3) / 1e9
         # with the screen, the stage is the screen kernel (high planes of the
@@ -187,7 +190,8 @@ def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=
                 "kernel": label,
                 "algorithmic": (f"{rer_bytes:.4g} bytes per step, all re-rank launches (vectors read in full "
                                 f"x (2 dp + 4) + vectors screened x (dp + 8))"),
-                "traffic": traffic_from_profiles(os.path.join(csrc, rerank_file), rerank_kernel)}
+                "traffic": traffic_from_profiles(os.path.join(csrc, rerank_file), rerank_kernel)
+                if counted else None}
     rerank_roof = {"achieved_gbs": rer_bytes / (per_step["rerank"] / 1e3) / 1e9 if per_step.get("rerank") else None,
                    "vectors_read": work["rerank_vectors"], "vectors_screened": scr_vec,
                    "candidates": work["rerank_candidates"], "abandoned": work["rerank_abandoned"],
@@ -311,7 +315,7 @@ def batched(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
 
     work["sketch_rows"] = sketch_rows(ix, q, q_off)
     roof, rerank_roof = rooflines(per_step, work, w["code_bits"], ix.dim_padded, "k_haus_queue", "k_batch.hip",
-                                  w["n_sets"])
+                                  w["n_sets"], counted=False)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
@@ -652,7 +656,7 @@ def learned_bench(args, w, cfg, dev):
     if counters is not None and keep == "learned":
         work = {k2: float(v) for k2, v in counters.items()}
         roof, _ = rooflines(best["stages_ms_per_step"], work, L, -(-d // 64) * 64, "k_haus_cand", "k_haus.hip",
-                            w["n_sets"])
+                            w["n_sets"], counted=False)
     return {
         "metric": METRIC,
         "value": best["qps"],
