@@ -213,7 +213,8 @@ constexpr bool haus_variant_used() {
   return !HG || haus_stage_bytes(MQ * 16, KS * 64) > kStageBudget;
 }
 
-// Exact phases: full distances for the first max(k, 32) candidates (the
+// Exact phases: full distances for the first max(k, 32) candidates (16
+// without the screening buffers: re-checks of a few near candidates) (the
 // best by sketch distance); their k-th smallest bounds the candidates up to
 // kCandPerBlock, whose k-th smallest (abandoned ones exceed it) bounds the
 // remaining candidates; each bound is at least the query's k-th distance.
@@ -238,7 +239,7 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
       if (e != hipSuccess) return e;
       // the first na candidates bound the next ones up to n0, whose k-th
       // distance then bounds the rest
-      const uint32_t na = std::min(n0, std::max(k, 32u));
+      const uint32_t na = std::min(n0, std::max(k, sel ? 32u : 16u));
       hipLaunchKernelGGL(kern, dim3(1, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids, count, T, 0u,
                          na, (const uint32_t*)nullptr, h2, stats, (const uint32_t*)nullptr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
