@@ -213,9 +213,9 @@ constexpr bool haus_variant_used() {
   return !HG || haus_stage_bytes(MQ * 16, KS * 64) > kStageBudget;
 }
 
-// Exact phases: full distances for the first max(k, 32) candidates (16
-// without the screening buffers: re-checks of a few near candidates) (the
-// best by sketch distance); their k-th smallest bounds the candidates up to
+// Exact phases: full distances for the first max(k, 32) candidates, the
+// best by sketch distance (max(k, 16) without the screening buffers: the
+// re-check of a few near candidates); their k-th smallest bounds those up to
 // kCandPerBlock, whose k-th smallest (abandoned ones exceed it) bounds the
 // remaining candidates; each bound is at least the query's k-th distance.
 // Given the screening buffers (and screening pairs on both sides, and a
