@@ -122,9 +122,28 @@ def approx_hausdorff_sq(Q, V, fmt: str) -> float:
 
 def recheck_threshold(h2_kth: float, margin: float) -> np.float32:
     """Squared-distance threshold of the re-check, every step in float32:
-    distances within (1 + margin) of the k-th approximate distance."""
+    distances within (1 + margin) of the k-th approximate distance.
+
+    A distance d is within the margin when d <= (1 + margin) d_k, that is
+    d^2 <= (1 + margin)^2 d_k^2 (both sides are non-negative), so the test
+    runs on squared values against the k-th squared value times the square
+    of the factor.  The steps are float32, as on the GPU, so that a value
+    right at the threshold is decided the same way on both sides."""
     f1 = np.float32(1.0) + np.float32(margin)
     return np.float32(np.float32(h2_kth) * np.float32(f1 * f1))
+
+
+def select_recheck(ids, ah2, k: int, margin: float) -> np.ndarray:
+    """Candidates to re-check exactly: in (approximate value, id) order,
+    those whose approximate squared value (as float32) is at most the
+    threshold of the k-th one; all of them when there are fewer than k."""
+    ids = np.asarray(ids)
+    ah2 = np.asarray(ah2, dtype=np.float64)
+    order = np.lexsort((ids, ah2))
+    if len(ids) < k:
+        return ids[order]
+    thr = recheck_threshold(ah2[order[k - 1]], margin)
+    return ids[order][ah2[order].astype(np.float32) <= thr]
 
 
 def search_lowp(index, Q, A: int, M: int, T: int, k: int, fmt: str, margin: float) -> dict:
@@ -137,12 +156,7 @@ def search_lowp(index, Q, A: int, M: int, T: int, k: int, fmt: str, margin: floa
     scores = flt.hamming(S_Q, index.B)
     f2_ids, _ = flt.second_filter(member, scores, T)
     ah2 = np.array([approx_hausdorff_sq(Q, index.members(j), fmt) for j in f2_ids], dtype=np.float64)
-    order = np.lexsort((f2_ids, ah2))
-    if len(f2_ids) >= k:
-        thr = recheck_threshold(ah2[order[k - 1]], margin)
-        recheck = f2_ids[order][ah2[order].astype(np.float32) <= thr]
-    else:
-        recheck = f2_ids[order]
+    recheck = select_recheck(f2_ids, ah2, k, margin)
     h2 = np.array([hausdorff_sq(Q, index.members(j)) for j in recheck], dtype=np.float64)
     o2 = np.lexsort((recheck, h2))[:k]
     return dict(f2_ids=f2_ids, approx_h2=ah2, recheck=recheck, ids=recheck[o2], h2=h2[o2],

@@ -127,3 +127,39 @@ def test_search_lowp_recheck_is_a_sorted_prefix_with_exact_values():
         assert all(np.float32(v) > thr for j, v in ah.items() if j not in set(r["recheck"].tolist()))
         for j, h in zip(r["ids"], r["h2"]):
             assert h == hausdorff.hausdorff_sq(Q, ix.members(int(j)))
+
+
+def test_recheck_selection_hand_built_margin():
+    # Approximate distances (not squared) relative to the k-th (k = 3, the
+    # candidate at 1.0): with a 2 % margin a candidate is re-checked when
+    # its distance is at most 1.02 times the k-th.  1.015 and 1.019 are in
+    # (their squares, 1.030 and 1.038, are under 1.0404), 1.0205 and 1.03
+    # are out.  A threshold that scaled the squared k-th value by 1.02
+    # instead of 1.02^2 would drop 1.015 and 1.019.
+    base = 0.37
+    rel = np.array([0.55, 0.80, 1.0, 1.015, 1.019, 1.0205, 1.03])
+    ids = np.array([40, 12, 7, 3, 29, 5, 18])
+    ah2 = (rel * base) ** 2
+    got = lowp.select_recheck(ids, ah2, 3, 0.02)
+    assert got.tolist() == [40, 12, 7, 3, 29]
+    # the same values in another input order give the same selection
+    perm = np.array([6, 2, 4, 0, 5, 1, 3])
+    assert lowp.select_recheck(ids[perm], ah2[perm], 3, 0.02).tolist() == [40, 12, 7, 3, 29]
+    # margin 0 keeps the first k and any value equal to the k-th
+    assert lowp.select_recheck(ids, ah2, 3, 0.0).tolist() == [40, 12, 7]
+    tie = np.array([0.1, 0.2, 0.3, 0.3, 0.4])
+    assert lowp.select_recheck(np.array([1, 2, 4, 3, 5]), tie, 3, 0.0).tolist() == [1, 2, 3, 4]
+    # fewer than k candidates: all of them, in order
+    assert lowp.select_recheck(np.array([9, 8]), np.array([0.5, 0.2]), 3, 0.02).tolist() == [8, 9]
+
+
+def test_recheck_threshold_closed_form():
+    # threshold(v, m) = v (1 + m)^2 up to float32 rounding, and exactly v
+    # for m = 0; increasing in the margin
+    for v in (1e-6, 0.013, 0.5, 3.7, 11.0):
+        assert lowp.recheck_threshold(v, 0.0) == np.float32(v)
+        for m in (0.01, 0.02, 0.1, 1.0):
+            t = float(lowp.recheck_threshold(v, m))
+            assert abs(t - v * (1 + m) ** 2) <= 4 * np.spacing(np.float32(v * (1 + m) ** 2))
+        ts = [float(lowp.recheck_threshold(v, m)) for m in (0.0, 0.01, 0.02, 0.05)]
+        assert ts == sorted(ts) and len(set(ts)) == 4
