@@ -32,7 +32,9 @@
 // product.  Each row carries |hi|^2 and r = |e| / 64 rounded up (written at
 // conversion); a pair is provably farther than sqrt(bound) when
 //   |hi_a - hi_b|^2 > (sqrt(bound) / 64 + r_a + r_b)^2,
-// evaluated in float with the right-hand side rounded up.  If some vector
+// evaluated in float with the right-hand side rounded up (every rounding of
+// sqrt(bound) / 64 + r_a + r_b is covered by a relative bump, so the float
+// threshold is at least the real one whatever the bound).  If some vector
 // of the set's first tile is that far from every query row, or (for sets of
 // one tile) some query row from every vector of the set, the Hausdorff
 // distance exceeds the bound and the set is rejected without its low planes
@@ -97,11 +99,19 @@ __device__ __forceinline__ void tile_products(const v4i (&ah)[KS], const v4i (&a
   }
 }
 
-// sqrt(bound) / 64 rounded up: the factor covers the int -> float and the
-// square-root roundings, and the additions of the screen.
+// sqrt(bound) / 64 rounded up: the factor covers the int -> float
+// conversion (2^-24 relative), a square root within one ulp (2^-23) and the
+// two multiplications' roundings.
 __device__ __forceinline__ float screen_scale(uint32_t bound) {
   return sqrtf((float)bound) * (1.0f / 64.0f) * (1.0f + 0x1p-19f);
 }
+
+// Factor applied to the rounded sum tb + r_q + r_v: each of the two
+// round-to-nearest additions of non-negative terms loses at most 2^-24 of
+// the sum, and so does the multiplication by the factor itself, so
+// fl(fl(fl(tb + r_q) + r_v) * (1 + 2^-21)) >= (tb + r_q + r_v) (1 - 2^-24)^3
+// (1 + 2^-21) > tb + r_q + r_v whatever the sizes of the three terms.
+static constexpr float kScreenSumUp = 1.0f + 0x1p-21f;
 
 // Screen of the first database tile (rows [0, min(16, m)) of a set, whose
 // high planes are in ah and whose screening pairs are sv[r] for the tile's
@@ -152,7 +162,7 @@ __device__ __forceinline__ bool screen_first_tile(uint32_t m, const QView& q, co
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int h2 = (int)(sv[r].x + sq.x) - 2 * hh[r];
-        const float x = tq + __uint_as_float(sv[r].y);
+        const float x = (tq + __uint_as_float(sv[r].y)) * kScreenSumUp;
         const float mf = fmaf(-x, x, (float)h2);
         rowm = fminf(rowm, mf);
         colm[r] = fminf(colm[r], mf);

@@ -138,6 +138,63 @@ def test_screen_keeps_results(tiny, monkeypatch):
     assert on["rerank_candidates"] == off["rerank_candidates"]
 
 
+def _near_duplicate_case():
+    """300 clusters of 12 near-copies of one base set (copies differ by
+    noise of norm 0.004 per vector, so Hausdorff distances within a cluster
+    are about 0.006) and 8 queries that are noisy copies of a cluster: the
+    10th distance is far below 0.02, the regime where the screen's bound is
+    small against the residual terms."""
+    from oracle import prng
+    from paper_2412_03301_amd import bvs
+    rng = np.random.default_rng(11)
+    d, n_cl, copies = 128, 300, 12
+
+    def grid(x):
+        x = x / np.linalg.norm(x, axis=1, keepdims=True)
+        return (np.rint(x * 4096) / 4096).astype(np.float32)
+
+    sets, bases = [], []
+    for c in range(n_cl):
+        base = rng.normal(size=(int(rng.integers(3, 20)), d))
+        base /= np.linalg.norm(base, axis=1, keepdims=True)
+        bases.append(base)
+        for _ in range(copies):
+            sets.append(grid(base + rng.normal(size=base.shape) * 0.004 / np.sqrt(d)))
+    off = np.concatenate([[0], np.cumsum([len(x) for x in sets])]).astype(np.int64)
+    X = np.concatenate(sets)
+    qs = [grid(bases[c] + rng.normal(size=bases[c].shape) * 0.004 / np.sqrt(d)) for c in range(0, n_cl, 37)]
+    q_off = np.concatenate([[0], np.cumsum([len(x) for x in qs])]).astype(np.int64)
+    Q = np.concatenate(qs)
+    p = bvs.Params.make(dim=d, code_bits=1024, fan_in=8, wta_k=32, access_lists=3, min_count=1, top_t=200, seed=2)
+    ix_g = bvs.Index(p, torch.from_numpy(X).cuda(), off)
+    ix_o = search.build_index(X.astype(np.float64), off, prng.projection_rows(2, d, 1024, 8), 32)
+    return ix_g, ix_o, torch.from_numpy(Q).cuda().contiguous(), Q.astype(np.float64), q_off
+
+
+def test_screen_near_duplicates(monkeypatch):
+    """With a 10th distance below 0.02 the screen still keeps every result:
+    screen on and off agree with each other and with the oracle."""
+    from paper_2412_03301_amd import bvs
+    _print_case("near-duplicate clusters, screen on and off")
+    ix_g, ix_o, q, Q, q_off = _near_duplicate_case()
+    runs = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BVS_SCREEN", flag)
+        bvs.profile_enable(False, counters=True)
+        runs[flag] = ([to_np(t) for t in ix_g.search(q, q_off, 10)], bvs.profile_counters())
+        bvs.profile_enable(False)
+    for x, y in zip(runs["1"][0], runs["0"][0]):
+        assert np.array_equal(x, y)
+    assert runs["1"][1]["rerank_screen_vectors"] > 0
+    ids, dist, cnt = runs["1"][0]
+    ids = ids.view(np.uint32)
+    for i in range(len(q_off) - 1):
+        r = search.search(ix_o, Q[q_off[i]:q_off[i + 1]], A=3, M=1, T=200, k=10)
+        assert np.sqrt(r["h2"][-1]) < 0.02
+        assert ids[i].astype(np.int64).tolist() == r["ids"].tolist()
+        np.testing.assert_allclose(dist[i], np.sqrt(r["h2"]), rtol=REL_TOL, atol=0)
+
+
 def test_hausdorff_all_exact(tiny):
     h2 = to_np(tiny.ix_gpu.hausdorff_all(tiny.q, tiny.q_off)).astype(np.int64)
     for i in range(4):
