@@ -10,6 +10,9 @@ This module defines the learned form used here, in float64:
   inference    as the GPU computes it: x, W1, relu(...) and W2 rounded to
                bfloat16 before each product (float32 accumulation on the
                GPU), y rounded to bfloat16 before the winner-take-all
+  training     the gradients by the chain rule, in float64 or, to compare
+               with the GPU element by element, with every product operand
+               rounded to bfloat16 where the GPU rounds it
 
 Training objective (the paper gives none; this is the build's reading):
   soft code     c_j(x) = sigmoid((y_j - t(x)) / tau), t(x) the midpoint of
@@ -95,15 +98,34 @@ def triplet_loss(weights, sets, triplets, k: int, tau: float, margin: float, t_f
     return total / len(triplets)
 
 
-def triplet_grads(weights, sets, triplets, k: int, tau: float, margin: float):
+def triplet_grads(weights, sets, triplets, k: int, tau: float, margin: float, quantised: bool = False,
+                  trace: list | None = None):
     """Mean loss and its gradients (dW1, db1, dW2, db2), by the chain rule
-    (thresholds held constant)."""
+    (thresholds held constant).
+
+    quantised: the operands of every product are rounded to bfloat16 as on
+    the GPU -- x, W1, relu(...) and W2 in the forward pass, and the output
+    gradient dy and the pre-activation gradient dpre before the products
+    that take them (dh = dy W2, dW2 = dy^T h, dW1 = dpre^T x); the bias
+    gradients sum the unrounded dy and dpre.  trace (a list) receives, per
+    set, the operands of those products and the soft quantities behind dy:
+    (x, pre, h, dy, dy_q, dpre, dpre_q, W2_q, c, others, S) with the rounded
+    ones as used (others: the product over the other members of 1 - c)."""
     W1, b1, W2, b2 = weights
+    if quantised:
+        rnd = bf16
+    else:
+        def rnd(a):
+            return np.asarray(a, dtype=np.float64)
+    W1q, W2q = rnd(W1), rnd(W2)
     fw = []
     for V in sets:
-        pre, h, y = mlp(V, W1, b1, W2, b2)
+        Vq = rnd(V)
+        pre = Vq @ W1q.T + b1
+        hq = rnd(np.maximum(pre, 0.0))
+        y = hq @ W2q.T + b2
         c = soft_codes(y, k, tau)
-        fw.append((np.asarray(V, dtype=np.float64), pre, h, c, soft_sketch(c)))
+        fw.append((Vq, pre, hq, c, soft_sketch(c)))
     dS = [np.zeros_like(f[4]) for f in fw]
     loss = 0.0
     nt = len(triplets)
@@ -128,10 +150,14 @@ def triplet_grads(weights, sets, triplets, k: int, tau: float, margin: float):
             others[i] = np.prod(np.delete(one_minus, i, axis=0), axis=0)
         dc = g[None, :] * others
         dy = dc * c * (1.0 - c) / tau
-        gW2 += dy.T @ h
+        dyq = rnd(dy)
+        gW2 += dyq.T @ h
         gb2 += dy.sum(axis=0)
-        dh = dy @ W2
+        dh = dyq @ W2q
         dpre = dh * (pre > 0)
-        gW1 += dpre.T @ V
+        dpreq = rnd(dpre)
+        gW1 += dpreq.T @ V
         gb1 += dpre.sum(axis=0)
+        if trace is not None:
+            trace.append((V, pre, h, dy, dyq, dpre, dpreq, W2q, c, others, S))
     return loss, (gW1, gb1, gW2, gb2)

@@ -74,3 +74,51 @@ def test_gradients_match_finite_differences():
             flat[e] = old
             num = (lp - lm) / (2 * eps)
             assert abs(num - g[e]) <= 1e-6 + 1e-5 * abs(num), (wi, e, num, g[e])
+
+
+def _exact_forward_case(rng, d, H, L, sizes, nnz):
+    """Inputs with entries in {0, +-1/4} (nnz per row) and weights that are
+    multiples of 1/16 in [-1/2, 1/2]: every product operand is a bfloat16
+    value and every forward sum is exact in float32 in any order."""
+    W = [rng.integers(-8, 9, (H, d)) / 16.0, rng.integers(-4, 5, H) / 16.0,
+         rng.integers(-8, 9, (L, H)) / 16.0, rng.integers(-4, 5, L) / 16.0]
+    sets = []
+    for m in sizes:
+        X = np.zeros((m, d))
+        for r in range(m):
+            X[r, rng.choice(d, nnz, replace=False)] = rng.choice([-0.25, 0.25], nnz)
+        sets.append(X)
+    return W, sets
+
+
+def test_quantised_gradients_within_rounding_of_float64_chain_rule():
+    # On bfloat16-exact operands the quantised mode differs from the plain
+    # chain rule (pinned by finite differences above) only by the bfloat16
+    # rounding of dy and dpre before their products: at most one half-ulp,
+    # 2^-8 of each rounded term, propagated through the sums of absolute
+    # products.  A dropped rounding, a transposed operand or a wrong mask
+    # would break either the bound or the equality below.
+    rng = np.random.default_rng(4)
+    d, H, L, k = 24, 16, 64, 8
+    W, sets = _exact_forward_case(rng, d, H, L, (3, 5, 2, 4, 1), 6)
+    trip = [(0, 1, 2), (3, 2, 4), (1, 0, 3), (4, 3, 0)]
+    tau, margin = 0.5, 6.0
+    trace = []
+    lq, gq = learned.triplet_grads(W, sets, trip, k, tau, margin, quantised=True, trace=trace)
+    lf, gf = learned.triplet_grads(W, sets, trip, k, tau, margin)
+    assert lq == lf and lq > 0                  # the forward pass is exact: same loss
+    u = 2.0 ** -8
+    aW2 = sum(np.abs(t[3]).T @ np.abs(t[2]) for t in trace)
+    # dpre differs by its own rounding (u |dpre|) and by dh's share of the
+    # rounding of dy (u |dy| |W2|)
+    aW1 = sum((np.abs(t[5]) + np.abs(t[3]) @ np.abs(t[7])).T @ np.abs(t[0]) for t in trace)
+    ab1 = sum((u * (np.abs(t[3]) @ np.abs(t[7]))).sum(axis=0) for t in trace)
+    assert np.all(np.abs(gq[2] - gf[2]) <= u * aW2 + 1e-15)
+    assert np.all(np.abs(gq[0] - gf[0]) <= u * aW1 + 1e-15)
+    assert np.all(np.abs(gq[1] - gf[1]) <= ab1 + 1e-15)
+    assert np.array_equal(gq[3], gf[3])         # the b2 gradient sums unrounded dy
+    # the rounding is real: the two modes are not identical
+    assert not np.array_equal(gq[2], gf[2])
+    # the rounded operands are bfloat16 values
+    for t in trace:
+        assert np.array_equal(t[4], learned.bf16(t[3])) and np.array_equal(t[6], learned.bf16(t[5]))
