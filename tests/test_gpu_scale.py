@@ -18,7 +18,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 N_SETS, LO, HI, D, TOPICS = 1_000_000, 5, 100, 384, 10_000
 L, S, K_WTA, T, K = 4096, 16, 64, 1000, 10
 N_Q = 1024
-CHECK_Q = (3, 700)
+CHECK_Q = (3, 255, 700, 1021)
 
 
 @pytest.fixture(scope="module")
@@ -99,17 +99,15 @@ def test_candidates_and_results_sampled(big):
             C, B = _oracle_sketch(big, j)
             if flt.first_filter(C[None], P, 1)[0]:
                 assert (int(flt.hamming(S_Q, B[None])[0]), j) > last
-        # results: exact distances, sorted, and no sampled candidate closer
+        # results: the first K of the candidate list by (exact Hausdorff^2,
+        # id), the oracle's exact value computed for every one of the T
+        # candidates (this is where the screen and the bound phases discard
+        # most of them), with exact distances
         assert cnt[i] == K
-        h2 = [hausdorff.hausdorff_sq(Q, _set_vectors(big, int(j))) for j in ids[i]]
-        np.testing.assert_allclose(dist[i], np.sqrt(h2), rtol=1e-5, atol=0)
-        res = list(zip(h2, ids[i].astype(int).tolist()))
-        assert res == sorted(res)
-        chosen = set(ids[i].tolist())
-        for t in rng.choice(T, 80, replace=False).tolist():
-            j = int(f2[i, t])
-            if j not in chosen:
-                assert (hausdorff.hausdorff_sq(Q, _set_vectors(big, j)), j) > res[-1]
+        h2_all = np.array([hausdorff.hausdorff_sq(Q, _set_vectors(big, int(j))) for j in f2[i]])
+        order = np.lexsort((f2[i].astype(np.int64), h2_all))[:K]
+        assert ids[i].astype(np.int64).tolist() == f2[i][order].astype(np.int64).tolist()
+        np.testing.assert_allclose(dist[i], np.sqrt(h2_all[order]), rtol=1e-5, atol=0)
 
 
 def test_bruteforce_sampled(big):
@@ -129,3 +127,19 @@ def test_bruteforce_sampled(big):
         for j in rng.choice(N_SETS, 400, replace=False).tolist():
             if j not in chosen:
                 assert (hausdorff.hausdorff_sq(Q, _set_vectors(big, j)), j) > res[-1]
+
+
+def test_screen_identity_whole_batch(big, monkeypatch):
+    """Every one of the 1,024 queries gets the same results with the
+    high-plane screen on and off."""
+    from paper_2412_03301_amd import bvs
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BVS_SCREEN", flag)
+        bvs.profile_enable(False, counters=True)
+        out[flag] = [t.cpu().numpy() for t in big["ix"].search(big["q"], big["q_off"], K)]
+        out[flag + "c"] = bvs.profile_counters()
+        bvs.profile_enable(False)
+    assert out["1c"]["rerank_screened"] > 0 and out["0c"]["rerank_screened"] == 0
+    for a, b in zip(out["1"], out["0"]):
+        assert np.array_equal(a, b)
