@@ -26,6 +26,9 @@ text by eye:
   learned    the learned projection (two-layer network before the
              winner-take-all) and its triplet training objective with
              gradients
+  biovss     the full-scan search of Alg. 2: Hausdorff distance over
+             Hamming distances of the codes for every set, the first c,
+             then the exact re-rank
 
 Parity status: every function is pinned by tests under tests/ (worked
 examples printed in the paper, closed forms, invariants, brute force on
@@ -33,4 +36,4 @@ tiny inputs).  `prng.projection_rows` follows a construction the paper
 leaves open (it only says W is random); it is pinned by a published
 splitmix64 test vector and by distribution invariants.
 """
-from . import prng, flyhash, sketch, filter, hausdorff, search, index, lowp, learned  # noqa: F401
+from . import prng, flyhash, sketch, filter, hausdorff, search, index, lowp, learned, biovss  # noqa: F401
