@@ -214,6 +214,37 @@ bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q,
                              uint32_t* d_h2, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Other set measures in the re-rank (Sec. 3.2, where the paper compares
+ * them with the Hausdorff distance; Sec. 6 reports search with MeanMin).
+ * Only the aggregation of the exact pairwise distances changes:
+ *   BVS_METRIC_HAUSDORFF  Def. 4 (what bvs_search and bvs_bruteforce use)
+ *   BVS_METRIC_MEANMIN    (1 / |Q|) sum over q in Q of min over v in V of
+ *                         |q - v|: the MeanMin distance from the query set
+ *                         to the database set (not symmetric)
+ *   BVS_METRIC_MIN        min over q in Q, v in V of |q - v|
+ * The filter layers are unchanged (F2 as for bvs_search); every candidate of
+ * F2 is measured in full (no bound or screen applies to these measures).
+ * Min distances are exact (the square root of an exact integer, as for
+ * Hausdorff).  MeanMin is a mean of square roots: each sqrt of the exact
+ * 2^24-scaled squared distance is taken in float64, summed in float64 and
+ * divided by |Q|, then rounded once to float32; results are ranked by that
+ * float32 value, ties to the lower id.  Outputs, workspaces and errors as
+ * for bvs_search / bvs_bruteforce; BVS_EINVAL for an unknown metric. */
+#define BVS_METRIC_HAUSDORFF 0
+#define BVS_METRIC_MEANMIN 1
+#define BVS_METRIC_MIN 2
+bvs_status bvs_search_metric(const bvs_index* ix, int metric, const float* d_q,
+                             const uint64_t* h_q_offsets, uint32_t n_q, uint32_t k,
+                             void* d_workspace, uint64_t workspace_bytes,
+                             uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                             void* stream);
+bvs_status bvs_bruteforce_metric(const bvs_index* ix, int metric, const float* d_q,
+                                 const uint64_t* h_q_offsets, uint32_t n_q, uint32_t k,
+                                 void* d_workspace, uint64_t workspace_bytes,
+                                 uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                                 void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched search: many query sets of uneven size through the whole cascade
  * (Alg. 6) with no host round trip.  The exact re-rank of every query runs
  * in ONE persistent launch: resident workgroups take (query, 64-candidate

@@ -6,6 +6,9 @@ search        one query: query sketches, top-A positions, first filter,
               Hamming scores, the first T by (score, id), exact Hausdorff
               on those T, and the first k by (distance, id)
 bruteforce    exact Hausdorff against every set, first k by (distance, id)
+search_metric, bruteforce_metric
+              the same with F2 (or every set) measured by MeanMin or Min
+              distance (Sec. 3.2) instead of the Hausdorff distance
 
 Ranking uses the squared Hausdorff distance in float64, which is exact for
 inputs on the 2^-12 grid; reported distances are float32(sqrt(H^2)).  The
@@ -22,7 +25,7 @@ import numpy as np
 
 from . import filter as flt
 from .flyhash import codes
-from .hausdorff import hausdorff_sq
+from .hausdorff import hausdorff_from_matrix, hausdorff_sq, mean_min_from_matrix, min_from_matrix, pairwise_sq
 from .sketch import binary_bloom, count_bloom
 
 
@@ -104,3 +107,56 @@ def recall_at_k(found, truth) -> float:
     """|R_k ∩ G_k| / |G_k| (Sec. 6.1.3)."""
     truth = set(int(t) for t in truth)
     return len(truth & set(int(f) for f in found)) / max(1, len(truth))
+
+
+# ---------------------------------------------------------------------------
+# Other set measures in the re-rank (Sec. 3.2 defines Min and MeanMin beside
+# the Hausdorff distance; Sec. 6 searches with MeanMin in place of it).  The
+# filter layers are the same; only the measure of F2's sets changes.
+
+METRICS = ("hausdorff", "meanmin", "min")
+
+
+def set_key(Q, V, metric: str) -> float:
+    """Ranking key of set V for query set Q.
+
+    hausdorff: squared Hausdorff distance (Def. 4), exact on the grid
+    min:       smallest squared distance between the sets, exact on the grid
+    meanmin:   MeanMin from Q to V, the mean over q in Q of min over v of
+               |q - v| (not squared), rounded to float32: the measure is a
+               mean of square roots, so the ranking decision is taken on the
+               float32 value (ties to the lower id), the precision of the
+               reported distance."""
+    D2 = pairwise_sq(Q, V)
+    if metric == "hausdorff":
+        return hausdorff_from_matrix(D2)
+    if metric == "min":
+        return min_from_matrix(D2)
+    if metric == "meanmin":
+        return float(np.float32(mean_min_from_matrix(np.sqrt(D2))))
+    raise ValueError(metric)
+
+
+def key_to_distance(key: np.ndarray, metric: str) -> np.ndarray:
+    key = np.asarray(key, dtype=np.float64)
+    return (key if metric == "meanmin" else np.sqrt(key)).astype(np.float32)
+
+
+def search_metric(index: Index, Q, A: int, M: int, T: int, k: int, metric: str) -> dict:
+    """Alg. 6 with the last steps measuring F2's sets by `metric`."""
+    Q = np.asarray(Q, dtype=np.float64)
+    r = search_codes(index, Q, codes(Q, index.idx, index.wta_k), A, M, T, k)
+    keys = np.array([set_key(Q, index.members(j), metric) for j in r["f2_ids"]], dtype=np.float64)
+    ids, top = rank_by_distance(r["f2_ids"], keys, k)
+    r.update(f2_keys=keys, ids=ids, keys=top, dist=key_to_distance(top, metric))
+    return r
+
+
+def bruteforce_metric(X, offsets, Q, k: int, metric: str):
+    """Exact top-k over all sets by `metric`: (ids, keys, float32 distances)."""
+    X = np.asarray(X, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    n = len(offsets) - 1
+    keys = np.array([set_key(Q, X[offsets[j]:offsets[j + 1]], metric) for j in range(n)], dtype=np.float64)
+    ids, top = rank_by_distance(np.arange(n), keys, k)
+    return ids, top, key_to_distance(top, metric)

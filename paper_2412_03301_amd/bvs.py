@@ -32,7 +32,9 @@ EXPORTED = [
     "bvs_hausdorff_lowp", "bvs_mlp_weight_count", "bvs_mlp_init", "bvs_learned_index_bytes",
     "bvs_learned_build_workspace_bytes", "bvs_build_index_learned", "bvs_train_workspace_bytes",
     "bvs_train_gradients", "bvs_train_projection",
+    "bvs_search_metric", "bvs_bruteforce_metric",
 ]
+METRIC = {"hausdorff": 0, "meanmin": 1, "min": 2}
 LOWP = {"bf16": 1, "fp8": 2}
 TUNE_MAX = 16
 N_STAGES = 12
@@ -117,6 +119,8 @@ def lib():
             "bvs_query_sketch": (C.c_int, [P, P, P, U32, P, U64, P, P, P, P]),
             "bvs_search_candidates": (C.c_int, [P, P, P, U32, P, U64, P, P, P, P]),
             "bvs_search": (C.c_int, [P, P, P, U32, U32, P, U64, P, P, P, P]),
+            "bvs_search_metric": (C.c_int, [P, C.c_int, P, P, U32, U32, P, U64, P, P, P, P]),
+            "bvs_bruteforce_metric": (C.c_int, [P, C.c_int, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_bruteforce_workspace_bytes": (C.c_int, [P, U32, U64, PU64]),
             "bvs_bruteforce": (C.c_int, [P, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_hausdorff_all": (C.c_int, [P, P, P, U32, P, U64, P, P]),
@@ -392,6 +396,31 @@ class Index:
         ids, dist, cnt = out
         check(lib().bvs_bruteforce(self._h, _ptr(q), _u64p(off), n_q, k, _ptr(ws), ws.numel(), _ptr(ids),
                                    _ptr(dist), _ptr(cnt), _stream(stream)))
+        return ids, dist, cnt
+
+    def _outs(self, n_q, k):
+        return (torch.empty(n_q, k, dtype=torch.int32, device=self.device),
+                torch.empty(n_q, k, dtype=torch.float32, device=self.device),
+                torch.empty(n_q, dtype=torch.int32, device=self.device))
+
+    def search_metric(self, q, q_offsets, k: int, metric: str, ws: torch.Tensor | None = None, out=None,
+                      stream=None):
+        """Cascade search re-ranked by `metric` ("hausdorff", "meanmin", "min")."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        ws = self.search_workspace(n_q, NQ) if ws is None else ws
+        ids, dist, cnt = self._outs(n_q, k) if out is None else out
+        check(lib().bvs_search_metric(self._h, METRIC[metric], _ptr(q), _u64p(off), n_q, k, _ptr(ws), ws.numel(),
+                                      _ptr(ids), _ptr(dist), _ptr(cnt), _stream(stream)))
+        return ids, dist, cnt
+
+    def bruteforce_metric(self, q, q_offsets, k: int, metric: str, ws: torch.Tensor | None = None, out=None,
+                          stream=None):
+        """Exact top-k over every set by `metric`."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        ws = self.brute_workspace(n_q, NQ) if ws is None else ws
+        ids, dist, cnt = self._outs(n_q, k) if out is None else out
+        check(lib().bvs_bruteforce_metric(self._h, METRIC[metric], _ptr(q), _u64p(off), n_q, k, _ptr(ws),
+                                          ws.numel(), _ptr(ids), _ptr(dist), _ptr(cnt), _stream(stream)))
         return ids, dist, cnt
 
     def hausdorff_all(self, q, q_offsets, stream=None) -> torch.Tensor:

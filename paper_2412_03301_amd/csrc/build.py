@@ -51,9 +51,24 @@ def compile_one(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4, verbose: bool = False) -> str:
+def _fresh(src: str) -> bool:
+    """The object of src is newer than src and every header."""
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return False
+    deps = [os.path.join(HERE, src)] + [h if os.path.isabs(h) else os.path.join(HERE, h) for h in HEADERS]
+    return all(os.path.getmtime(obj) > os.path.getmtime(d) for d in deps)
+
+
+def build(jobs: int = 4, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those whose object is stale)
+    and link libbvs.so."""
+    def one(src):
+        if incremental and _fresh(src):
+            return os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+        return compile_one(src)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        objs = list(ex.map(one, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -68,9 +83,10 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=min(8, os.cpu_count() or 4))
+    ap.add_argument("--incremental", action="store_true", help="recompile only sources with stale objects")
     a = ap.parse_args()
     try:
-        build(a.j, verbose=True)
+        build(a.j, verbose=True, incremental=a.incremental)
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)

@@ -650,8 +650,9 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
   return BVS_OK;
 }
 
-HausDb haus_db(const bvs_index* ix) {
+HausDb haus_db(const bvs_index* ix, uint32_t metric = kMetricHausdorff) {
   HausDb d;
+  d.metric = metric;
   d.hi = ix->hi;
   d.lo = ix->lo;
   d.norms = ix->norms;
@@ -679,6 +680,70 @@ bvs_status need_ws(uint64_t have, uint64_t need, void* ws) {
   if (have < need)
     return fail(BVS_ENOSPC, "workspace of %llu bytes, %llu needed", (unsigned long long)have, (unsigned long long)need);
   return BVS_OK;
+}
+
+// The whole cascade search of bvs_search on a workspace of ws_bytes at d_ws;
+// prof_allowed = false records no stage events and collects no counters.
+bool metric_ok(int metric) { return metric >= 0 && metric <= (int)kMetricMin; }
+
+bvs_status search_impl(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
+                       void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                       hipStream_t st, bool prof_allowed, uint32_t metric = kMetricHausdorff) {
+  if (!metric_ok((int)metric)) return fail(BVS_EINVAL, "unknown metric %u", metric);
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
+  if (k < 1 || k > kMaxK || k > ix->g.T) return fail(BVS_EINVAL, "k %u outside 1..min(64, top_t)", k);
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_search_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  Carver c(d_ws);
+  QueryWs w;
+  layout_search(c, ix, n_q, NQ, &w);
+  CallProf prof(st, prof_allowed);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
+  BVS_TRY(run_filters(ix, n_q, NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof));
+  HIP_TRY(staged(prof, S_RERANK, [&] {
+    return launch_haus_cand(haus_db(ix, metric), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, k, w.thr,
+                            w.h2, prof.count ? w.stats : nullptr, w.surv, w.surv_count, st);
+  }));
+  HIP_TRY(staged(prof, S_TOPK, [&] {
+    return launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st,
+                       metric == kMetricMeanMin);
+  }));
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish(prof.count ? w.stats : nullptr);
+  return s;
+}
+
+// Exact top-k over every set by `metric` (bvs_bruteforce and its metric form).
+bvs_status brute_impl(const bvs_index* ix, uint32_t metric, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                      uint32_t k, void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                      hipStream_t st) {
+  if (!metric_ok((int)metric)) return fail(BVS_EINVAL, "unknown metric %u", metric);
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
+  if (k < 1 || k > kMaxK) return fail(BVS_EINVAL, "k %u outside 1..64", k);
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_bruteforce_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  Carver c(d_ws);
+  QueryWs w;
+  layout_brute(c, ix, n_q, NQ, &w);
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
+  HIP_TRY(staged(prof, S_BRUTE,
+                 [&] { return launch_haus_all(haus_db(ix, metric), haus_q(w, n_q, max_rows), w.h2, st); }));
+  HIP_TRY(staged(prof, S_TOPK, [&] {
+    return launch_topk(w.h2, nullptr, nullptr, ix->n, ix->n, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st,
+                       metric == kMetricMeanMin);
+  }));
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish();
+  return s;
 }
 
 }  // namespace
@@ -960,57 +1025,30 @@ bvs_status bvs_search_candidates(const bvs_index* ix, const float* d_q, const ui
 bvs_status bvs_search(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
                       void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist, uint32_t* d_count,
                       void* stream) {
-  uint32_t max_rows = 0;
-  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
-  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
-  if (k < 1 || k > kMaxK || k > ix->g.T) return fail(BVS_EINVAL, "k %u outside 1..min(64, top_t)", k);
-  const uint64_t NQ = h_q_off[n_q];
-  uint64_t need = 0;
-  BVS_TRY(bvs_search_workspace_bytes(ix, n_q, NQ, &need));
-  BVS_TRY(need_ws(ws_bytes, need, d_ws));
-  hipStream_t st = (hipStream_t)stream;
-  Carver c(d_ws);
-  QueryWs w;
-  layout_search(c, ix, n_q, NQ, &w);
-  CallProf prof(st);
-  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
-  BVS_TRY(run_filters(ix, n_q, NQ, w, w.f2_ids, w.f2_scores, w.f2_count, st, prof));
-  HIP_TRY(staged(prof, S_RERANK, [&] {
-    return launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, k, w.thr, w.h2,
-                            prof.count ? w.stats : nullptr, w.surv, w.surv_count, st);
-  }));
-  HIP_TRY(staged(prof, S_TOPK, [&] {
-    return launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
-  }));
-  const bvs_status s = read_status(w.status, st, "queries");
-  prof.finish(prof.count ? w.stats : nullptr);
-  return s;
+  return search_impl(ix, d_q, h_q_off, n_q, k, d_ws, ws_bytes, d_ids, d_dist, d_count, (hipStream_t)stream, true);
 }
 
 bvs_status bvs_bruteforce(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
                           void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist, uint32_t* d_count,
                           void* stream) {
-  uint32_t max_rows = 0;
-  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
-  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
-  if (k < 1 || k > kMaxK) return fail(BVS_EINVAL, "k %u outside 1..64", k);
-  const uint64_t NQ = h_q_off[n_q];
-  uint64_t need = 0;
-  BVS_TRY(bvs_bruteforce_workspace_bytes(ix, n_q, NQ, &need));
-  BVS_TRY(need_ws(ws_bytes, need, d_ws));
-  hipStream_t st = (hipStream_t)stream;
-  Carver c(d_ws);
-  QueryWs w;
-  layout_brute(c, ix, n_q, NQ, &w);
-  CallProf prof(st);
-  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
-  HIP_TRY(staged(prof, S_BRUTE, [&] { return launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), w.h2, st); }));
-  HIP_TRY(staged(prof, S_TOPK, [&] {
-    return launch_topk(w.h2, nullptr, nullptr, ix->n, ix->n, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
-  }));
-  const bvs_status s = read_status(w.status, st, "queries");
-  prof.finish();
-  return s;
+  return brute_impl(ix, kMetricHausdorff, d_q, h_q_off, n_q, k, d_ws, ws_bytes, d_ids, d_dist, d_count,
+                    (hipStream_t)stream);
+}
+
+bvs_status bvs_search_metric(const bvs_index* ix, int metric, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                             uint32_t k, void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist,
+                             uint32_t* d_count, void* stream) {
+  if (!metric_ok(metric)) return fail(BVS_EINVAL, "unknown metric %d", metric);
+  return search_impl(ix, d_q, h_q_off, n_q, k, d_ws, ws_bytes, d_ids, d_dist, d_count, (hipStream_t)stream, true,
+                     (uint32_t)metric);
+}
+
+bvs_status bvs_bruteforce_metric(const bvs_index* ix, int metric, const float* d_q, const uint64_t* h_q_off,
+                                 uint32_t n_q, uint32_t k, void* d_ws, uint64_t ws_bytes, uint32_t* d_ids,
+                                 float* d_dist, uint32_t* d_count, void* stream) {
+  if (!metric_ok(metric)) return fail(BVS_EINVAL, "unknown metric %d", metric);
+  return brute_impl(ix, (uint32_t)metric, d_q, h_q_off, n_q, k, d_ws, ws_bytes, d_ids, d_dist, d_count,
+                    (hipStream_t)stream);
 }
 
 bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,

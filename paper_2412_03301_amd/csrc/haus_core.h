@@ -207,6 +207,32 @@ __device__ __forceinline__ bool screen_set(const HausDb& db, uint64_t o0, uint32
   return screen_first_tile<KS, MAXQT, HASG>(m, q, ah, sv, screen_scale(bound));
 }
 
+// MeanMin key (Sec. 3.2, query to set) from the per-lane query-row minima
+// of haus_item: lane (g, c) holds, for query row 16 qt + c, the minimum over
+// the set rows that lane group g saw; the four groups' minima make the row's
+// distance to the set, D2_q = 2^24 min_v |q - v|^2 (exact).  The mean of
+// sqrt(D2_q) / 4096 over the m_q rows is accumulated in float64 (square roots
+// correctly rounded, one sum per lane of group 0 in row order, then a fixed
+// butterfly over the wave), divided by m_q and rounded once to float32; its
+// bits are the key.
+template <int MAXQT>
+__device__ __forceinline__ uint32_t mean_min_key(const uint32_t (&qmin)[MAXQT], const QView& q) {
+  const uint32_t lane = lane_id();
+  const uint32_t g = lane >> 4, c16 = lane & 15;
+  double sum = 0.0;
+#pragma unroll
+  for (int qt = 0; qt < MAXQT; ++qt) {
+    if ((uint32_t)qt < q.nqt) {
+      const uint32_t rm = rows4_min_u32(qmin[qt]);
+      if (g == 0 && (uint32_t)qt * 16 + c16 < q.mq) sum += sqrt((double)rm);
+    }
+  }
+#pragma unroll
+  for (int m = 1; m < 16; m <<= 1) sum += __shfl_xor(sum, m, BVS_WAVE);
+  const double mean = sum * (1.0 / 4096.0) / (double)q.mq;
+  return __float_as_uint((float)mean);
+}
+
 // Squared Hausdorff distance (2^24-scaled) of database set [o0, o0 + m)
 // against the query (HASG: some query tiles may come from global memory).
 // The set is abandoned, returning kAbandoned, as soon as a lower bound of
@@ -301,6 +327,16 @@ __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uin
     if (bounded && !last && (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_dpp_u32(colmax)) > bound)
       return kAbandoned;
   }
+  if (db.metric == kMetricMin) {
+    // every pair's value went into some lane's query-row minima (pad pairs
+    // hold all ones)
+    uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+    for (int qt = 0; qt < MAXQT; ++qt)
+      if ((uint32_t)qt < q.nqt) mn = min(mn, qmin[qt]);
+    return wave_min_dpp_u32(mn);
+  }
+  if (db.metric == kMetricMeanMin) return mean_min_key<MAXQT>(qmin, q);
   uint32_t rowmax = 0;
 #pragma unroll
   for (int qt = 0; qt < MAXQT; ++qt) {

@@ -237,6 +237,13 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
       auto kern = k_haus_cand<KS, MQ, HG>;
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
+      if (db.metric != kMetricHausdorff) {
+        // no bound applies to the other measures: every candidate in full
+        const uint32_t G = (T + kCandPerBlock - 1) / kCandPerBlock;
+        hipLaunchKernelGGL(kern, dim3(G, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids, count, T, 0u,
+                           T, (const uint32_t*)nullptr, h2, stats, (const uint32_t*)nullptr);
+        return hipGetLastError();
+      }
       // the first na candidates bound the next ones up to n0, whose k-th
       // distance then bounds the rest
       const uint32_t na = std::min(n0, std::max(k, sel ? 32u : 16u));
@@ -326,7 +333,7 @@ __global__ void __launch_bounds__(1024)
 k_topk(const uint32_t* __restrict__ h2, const uint32_t* __restrict__ ids_in, const uint32_t* __restrict__ count_in,
        const uint64_t* __restrict__ keys_in, uint64_t n_items, uint64_t stride, uint32_t k,
        uint64_t* __restrict__ keys_out, uint32_t* __restrict__ ids, float* __restrict__ dist,
-       uint32_t* __restrict__ count, uint32_t n_valid_total) {
+       uint32_t* __restrict__ count, uint32_t n_valid_total, uint32_t key_is_dist) {
   __shared__ uint64_t s[kTopkChunk];
   const uint32_t q = blockIdx.y, chunk = blockIdx.x;
   const uint64_t n_valid = count_in ? (uint64_t)count_in[q] : n_items;
@@ -357,7 +364,9 @@ k_topk(const uint32_t* __restrict__ h2, const uint32_t* __restrict__ ids_in, con
       const uint64_t key = s[i];
       const bool ok = key != ~0ull;
       ids[(uint64_t)q * k + i] = ok ? (uint32_t)key : 0xFFFFFFFFu;
-      dist[(uint64_t)q * k + i] = ok ? sqrtf((float)(uint32_t)(key >> 32)) * (1.0f / 4096.0f) : __builtin_inff();
+      const uint32_t hk = (uint32_t)(key >> 32);
+      dist[(uint64_t)q * k + i] =
+          !ok ? __builtin_inff() : key_is_dist ? __uint_as_float(hk) : sqrtf((float)hk) * (1.0f / 4096.0f);
     }
     if (threadIdx.x == 0) count[q] = min(k, nv);
   } else {
@@ -373,15 +382,16 @@ uint64_t topk_tmp_words(uint64_t n_items, uint32_t n_q, uint32_t k) {
 
 hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_t* count_in, uint64_t n_items,
                        uint64_t stride, uint32_t n_q, uint32_t k, uint64_t* tmp, uint32_t* ids, float* dist,
-                       uint32_t* count, hipStream_t st) {
+                       uint32_t* count, hipStream_t st, bool key_is_dist) {
   if (n_q == 0) return hipSuccess;
+  const uint32_t kd = key_is_dist ? 1u : 0u;
   const uint32_t n_valid_total = (uint32_t)std::min<uint64_t>(n_items, 0xFFFFFFFFull);
   uint64_t chunks = (n_items + kTopkChunk - 1) / kTopkChunk;
   if (chunks == 0) chunks = 1;
   if (count_in && chunks != 1) return hipErrorInvalidValue;   // candidate lists hold at most 4096 items
   if (chunks == 1) {
     hipLaunchKernelGGL(k_topk, dim3(1, n_q), dim3(1024), 0, st, h2, ids_in, count_in, (const uint64_t*)nullptr,
-                       n_items, stride, k, (uint64_t*)nullptr, ids, dist, count, n_valid_total);
+                       n_items, stride, k, (uint64_t*)nullptr, ids, dist, count, n_valid_total, kd);
     return hipGetLastError();
   }
   // First pass: per chunk top-k keys into tmp[0 ..], then merge passes.
@@ -390,7 +400,7 @@ hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_
   uint64_t* b = tmp + half;
   hipLaunchKernelGGL(k_topk, dim3((uint32_t)chunks, n_q), dim3(1024), 0, st, h2, ids_in, count_in,
                      (const uint64_t*)nullptr, n_items, stride, k, a, (uint32_t*)nullptr, (float*)nullptr,
-                     (uint32_t*)nullptr, n_valid_total);
+                     (uint32_t*)nullptr, n_valid_total, kd);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   uint64_t n_in = chunks * k;
@@ -400,14 +410,14 @@ hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_
       // Padding keys (all ones) sort last; count = min(k, n_items).
       hipLaunchKernelGGL(k_topk, dim3(1, n_q), dim3(1024), 0, st, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
                          (const uint32_t*)nullptr, a, n_in, n_in, k, (uint64_t*)nullptr, ids, dist, count,
-                         n_valid_total);
+                         n_valid_total, kd);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       return hipSuccess;
     }
     hipLaunchKernelGGL(k_topk, dim3((uint32_t)c2, n_q), dim3(1024), 0, st, (const uint32_t*)nullptr,
                        (const uint32_t*)nullptr, (const uint32_t*)nullptr, a, n_in, n_in, k, b, (uint32_t*)nullptr,
-                       (float*)nullptr, (uint32_t*)nullptr, n_valid_total);
+                       (float*)nullptr, (uint32_t*)nullptr, n_valid_total, kd);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     std::swap(a, b);

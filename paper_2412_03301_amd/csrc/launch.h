@@ -128,10 +128,19 @@ hipError_t launch_select(const uint16_t* scores, uint64_t ld, uint32_t L, uint32
 // scr: per-row screening pairs written by launch_convert; bounded re-ranks
 // screen with the high planes first when both sides have them (null: no
 // screening).
+// Set measure of the re-rank (Sec. 3.2): the Hausdorff distance of Def. 4,
+// the mean over the query's vectors of their distance to the set (MeanMin,
+// query to set), or the smallest distance between the two sets (Min).
+enum : uint32_t { kMetricHausdorff = 0, kMetricMeanMin = 1, kMetricMin = 2 };
 struct HausDb {
   const int8_t* hi; const uint8_t* lo; const uint32_t* norms; const uint64_t* offsets;
   uint64_t n_sets; uint32_t dp;
   const uint2* scr;
+  // Result key of a set: Hausdorff and Min give 2^24 times the squared
+  // distance (an integer); MeanMin gives the float32 bits of the distance
+  // (a mean of square roots, accumulated in float64), which order like
+  // the values.  Metrics other than Hausdorff are never bounded or screened.
+  uint32_t metric = kMetricHausdorff;
 };
 struct HausQ {
   const int8_t* hi; const uint8_t* lo; const uint32_t* norms; const uint64_t* offsets;
@@ -179,11 +188,13 @@ hipError_t launch_haus_queue(const HausDb& db, const HausQ& q, const QueueArgs& 
                              uint32_t blocks, hipStream_t st);
 
 // First k by (h2, id) of each query.  ids_in may be NULL (item index = id).
-// tmp must hold 2 * n_q * ceil(n_items / 4096) * k uint64.
+// tmp must hold 2 * n_q * ceil(n_items / 4096) * k uint64.  Reported
+// distances are sqrt(h2) / 4096, or the float32 whose bits are h2 when
+// key_is_dist (MeanMin keys).
 hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_t* count_in,
                        uint64_t n_items, uint64_t stride, uint32_t n_q, uint32_t k,
                        uint64_t* tmp, uint32_t* ids, float* dist, uint32_t* count,
-                       hipStream_t st);
+                       hipStream_t st, bool key_is_dist = false);
 uint64_t topk_tmp_words(uint64_t n_items, uint32_t n_q, uint32_t k);
 
 // Precision form (BVS_LOWP_BF16 / BVS_LOWP_FP8 copies of the vectors).

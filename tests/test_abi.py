@@ -143,3 +143,11 @@ def test_batch_calls_reject_null_handles(bvs):
     info = bvs.BatchInfo()
     assert L.bvs_batch_get_info(None, C.byref(info)) == bvs.BVS_EINVAL
     L.bvs_batch_destroy(None)
+
+
+def test_metric_calls_reject_unknown_metric_on_the_host(bvs):
+    lib = bvs.lib()
+    for fn in (lib.bvs_search_metric, lib.bvs_bruteforce_metric):
+        assert fn(None, 7, None, None, 1, 10, None, 0, None, None, None, None) == bvs.BVS_EINVAL
+        assert b"metric" in lib.bvs_last_error()
+        assert fn(None, -1, None, None, 1, 10, None, 0, None, None, None, None) == bvs.BVS_EINVAL
