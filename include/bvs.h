@@ -23,7 +23,9 @@
  * - Pointers named d_* are device pointers, h_* are host pointers.  The
  *   library never allocates device memory: the caller passes the index
  *   memory, workspaces and outputs, sized with the *_bytes queries, and
- *   owns them.  The library keeps no host pointer after a call returns.
+ *   owns them (bvs_search_noalloc alone uses a fixed array that the
+ *   library's code object holds on each GPU).  The library keeps no host
+ *   pointer after a call returns.
  * - Every call returns a bvs_status; bvs_last_error() gives a thread-local
  *   message for the last non-OK status.  Argument errors are detected on
  *   the host before anything is launched.
@@ -193,6 +195,26 @@ bvs_status bvs_search(const bvs_index* ix, const float* d_q,
                       void* d_workspace, uint64_t workspace_bytes,
                       uint32_t* d_ids, float* d_dist, uint32_t* d_count,
                       void* stream);
+
+/* bvs_search for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same search, identical outputs, with its workspace taken from a fixed
+ * array of bvs_search_noalloc_max_bytes() = 64 MiB that the library holds in
+ * device memory on every GPU it runs on until the process ends.  No device
+ * or host-pinned memory is allocated, no stage events are recorded and no
+ * work counters are collected.  The call runs on the current device, which
+ * must be the index's (BVS_ESTATE otherwise); a batch whose bvs_search
+ * workspace (bvs_search_workspace_bytes) exceeds 64 MiB is rejected with
+ * BVS_ENOSPC before anything is launched.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap in time on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller; each call
+ * clears what it needs before use, so successive calls are independent.
+ * Synchronises `stream` like bvs_search. */
+uint64_t bvs_search_noalloc_max_bytes(void);
+bvs_status bvs_search_noalloc(const bvs_index* ix, const float* d_q,
+                              const uint64_t* h_q_offsets, uint32_t n_q, uint32_t k,
+                              uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                              void* stream);
 
 /* Workspace bytes for bvs_bruteforce / bvs_hausdorff_all. */
 bvs_status bvs_bruteforce_workspace_bytes(const bvs_index* ix, uint32_t n_q,

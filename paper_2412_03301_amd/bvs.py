@@ -31,7 +31,7 @@ EXPORTED = [
     "bvs_batch_destroy", "bvs_lowp_bytes", "bvs_lowp_attach", "bvs_lowp_workspace_bytes", "bvs_search_lowp",
     "bvs_hausdorff_lowp", "bvs_mlp_weight_count", "bvs_mlp_init", "bvs_learned_index_bytes",
     "bvs_learned_build_workspace_bytes", "bvs_build_index_learned", "bvs_train_workspace_bytes",
-    "bvs_train_gradients", "bvs_train_projection",
+    "bvs_train_gradients", "bvs_train_projection", "bvs_search_noalloc_max_bytes", "bvs_search_noalloc",
     "bvs_search_metric", "bvs_bruteforce_metric",
 ]
 METRIC = {"hausdorff": 0, "meanmin": 1, "min": 2}
@@ -119,8 +119,10 @@ def lib():
             "bvs_query_sketch": (C.c_int, [P, P, P, U32, P, U64, P, P, P, P]),
             "bvs_search_candidates": (C.c_int, [P, P, P, U32, P, U64, P, P, P, P]),
             "bvs_search": (C.c_int, [P, P, P, U32, U32, P, U64, P, P, P, P]),
+            "bvs_search_noalloc_max_bytes": (U64, []),
             "bvs_search_metric": (C.c_int, [P, C.c_int, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_bruteforce_metric": (C.c_int, [P, C.c_int, P, P, U32, U32, P, U64, P, P, P, P]),
+            "bvs_search_noalloc": (C.c_int, [P, P, P, U32, U32, P, P, P, P]),
             "bvs_bruteforce_workspace_bytes": (C.c_int, [P, U32, U64, PU64]),
             "bvs_bruteforce": (C.c_int, [P, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_hausdorff_all": (C.c_int, [P, P, P, U32, P, U64, P, P]),
@@ -343,6 +345,19 @@ class Index:
         ids, dist, cnt = out
         check(lib().bvs_search(self._h, _ptr(q), _u64p(off), n_q, k, _ptr(ws), ws.numel(), _ptr(ids),
                                _ptr(dist), _ptr(cnt), _stream(stream)))
+        return ids, dist, cnt
+
+    def search_noalloc(self, q, q_offsets, k: int, out=None, stream=None):
+        """bvs_search_noalloc: the search of `search` on the library's fixed
+        device scratch (no workspace argument; outputs as for `search`)."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        if out is None:
+            out = (torch.empty(n_q, k, dtype=torch.int32, device=self.device),
+                   torch.empty(n_q, k, dtype=torch.float32, device=self.device),
+                   torch.empty(n_q, dtype=torch.int32, device=self.device))
+        ids, dist, cnt = out
+        check(lib().bvs_search_noalloc(self._h, _ptr(q), _u64p(off), n_q, k, _ptr(ids), _ptr(dist), _ptr(cnt),
+                                       _stream(stream)))
         return ids, dist, cnt
 
     # -- precision form

@@ -2000,3 +2000,62 @@ bvs_status bvs_train_projection(const bvs_train_config* t, const float* d_vector
 }
 
 }  // extern "C"
+
+// ====================================================================== no-allocation search
+// bvs_search for callers that cannot allocate: its workspace is a fixed
+// array in device memory that the library's code object holds on every GPU
+// it runs on, for the life of the process.  Host code never passes the
+// array's name to a kernel: the name is a host-side stand-in, so the device
+// address of each GPU's copy is looked up once per device and kept.
+static constexpr uint64_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of `scratch` (looked up on the
+// first call on that device).
+bvs_status scratch_for_device(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(BVS_ENOTSUP, "device %d outside 0..%d", dev,
+                                                         kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(BVS_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t bvs_search_noalloc_max_bytes(void) { return kScratchBytes; }
+
+bvs_status bvs_search_noalloc(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                              uint32_t k, uint32_t* d_ids, float* d_dist, uint32_t* d_count, void* stream) {
+  uint32_t max_rows = 0;
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, &max_rows));
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BVS_EDEVICE, "hipGetDevice failed");
+  if (dev != ix->device)
+    return fail(BVS_ESTATE, "current device %d is not the index's device %d", dev, ix->device);
+  uint64_t need = 0;
+  BVS_TRY(bvs_search_workspace_bytes(ix, n_q, h_q_off[n_q], &need));
+  if (need > kScratchBytes)
+    return fail(BVS_ENOSPC, "search needs %llu bytes of workspace, above the %llu of the no-allocation scratch",
+                (unsigned long long)need, (unsigned long long)kScratchBytes);
+  void* ws = nullptr;
+  BVS_TRY(scratch_for_device(dev, &ws));
+  return search_impl(ix, d_q, h_q_off, n_q, k, ws, kScratchBytes, d_ids, d_dist, d_count, (hipStream_t)stream,
+                     false);
+}
+
+}  // extern "C"
