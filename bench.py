@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scale", choices=["scale", "tiny", "batched", "precision", "learned"])
+    ap.add_argument("--workload", default="scale", choices=["scale", "tiny", "batched", "precision", "learned", "full", "metrics"])
     ap.add_argument("--train-epochs", type=int, default=1)
     ap.add_argument("--train-batch", type=int, default=256)
     ap.add_argument("--train-lr", type=float, default=3e-4)
@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--cpu-sample-queries", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-brute", action="store_true")
+    ap.add_argument("--full-queries", type=int, default=64,
+                    help="full workload: queries per step of the full scan (Alg. 2)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration runs)")
     return ap.parse_args()
@@ -690,6 +692,116 @@ def learned_bench(args, w, cfg, dev):
     }
 
 
+def full_scan(args, w, ix, q, q_off, n_vec, build_s):
+    """The full-scan search of Alg. 2 on the scale database: Haus^H of the
+    query codes to every set, the first c = T sets, exact re-rank; compared
+    with the cascade (Alg. 6) and the exact brute force on the same queries."""
+    import numpy as np
+    import torch
+
+    from paper_2412_03301_amd import bvs
+
+    dev = q.device
+    k = w["k"]
+    n_q = min(args.full_queries, w["n_queries"])
+    qf = q[: int(q_off[n_q])].contiguous()
+    of = q_off[: n_q + 1]
+    NQ = int(of[-1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nbytes = ix.attach_codes()
+    torch.cuda.synchronize()
+    attach_s = time.perf_counter() - t0
+    log(f"attached sparse codes ({nbytes / 2**30:.1f} GiB) in {attach_s:.2f} s")
+    ws = ix.full_workspace(n_q, NQ)
+    out = ix._outs(n_q, k)
+    for i in range(args.warmup):
+        ix.search_full(qf, of, k, ws=ws, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ix.search_full(qf, of, k, ws=ws, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    qps = n_q * args.steps / el
+    bvs.profile_enable(True)
+    for i in range(args.steps):
+        ix.search_full(qf, of, k, ws=ws, out=out)
+    torch.cuda.synchronize()
+    per_step = {nm: ms / max(1, c) for nm, (ms, c) in bvs.profile_read().items() if c}
+    bvs.profile_enable(False)
+    ids = out[0].cpu().numpy().view(np.uint32)
+    log(f"full scan: {qps:.1f} q/s on {n_q} queries per step; stages {per_step}")
+    # the cascade on the same queries
+    wsc = ix.search_workspace(n_q, NQ)
+    outc = ix._outs(n_q, k)
+    ix.search(qf, of, k, ws=wsc, out=outc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ix.search(qf, of, k, ws=wsc, out=outc)
+    torch.cuda.synchronize()
+    cascade_qps = n_q * args.steps / (time.perf_counter() - t0)
+    cids = outc[0].cpu().numpy().view(np.uint32)
+    recall = recall_c = brute_qps = None
+    if not args.no_brute:
+        recall, brute_qps = brute_recall(ix, q, q_off, ids, k, n_q)
+        bids = ix.bruteforce(qf, of, k)[0].cpu().numpy().view(np.uint32)
+        recall_c = float(np.mean([len(set(cids[i].tolist()) & set(bids[i].tolist())) / k for i in range(n_q)]))
+        log(f"recall@10: full scan {recall:.4f}, cascade {recall_c:.4f}; brute force {brute_qps:.1f} q/s")
+    # scan work: every database vector against every query; positions are
+    # read from HBM once per (query, set) pair
+    L, K = w["code_bits"], w["wta_k"]
+    KP = -(-K // 8) * 8
+    scan_ms = per_step.get("fullscan")
+    scan_bytes = n_vec * KP * 2 * n_q
+    groups = (np.minimum(np.diff(of), 256) + 63) // 64
+    # one table lookup and one 64-slot carry-save step (3 ops on each of 2
+    # words) per code position, per vector and group of 64 query vectors
+    ops = float(n_vec) * K * 7 * float(groups.sum())
+    roof = None
+    if scan_ms:
+        ach_gbs = scan_bytes / (scan_ms / 1e3) / 1e9
+        ach_ops = ops / (scan_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": ach_ops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": ach_ops / ALU_PEAK_TOPS, "kernel": "k_full_scan<7,1> (full-scan stage)",
+                "algorithmic": (f"{ops:.4g} int32 ops per step: n_vectors x wta_k x 7 (one LDS lookup, 6 carry-save "
+                                f"ops) x query groups of 64"),
+                "hbm_gbs": ach_gbs, "hbm_frac": ach_gbs / HBM_PEAK_GBS, "hbm_bytes_per_step": scan_bytes,
+                "traffic": None}
+    return {
+        "metric": "queries/sec of the full-scan search (Alg. 2) on 1M sets",
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 bit-sliced counts; exact integer re-rank",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={w['dim']}, "
+                         f"{w['n_topics']} topics; FlyHash L={L}, s={w['fan_in']}, wta_k={K}; c=T={w['top_t']}; "
+                         f"{n_q} subset queries per step; top-{k}"),
+            "n_sets": w["n_sets"], "n_vectors": n_vec, "n_queries": n_q, "query_vectors": NQ,
+        },
+        "recall_at_10": recall,
+        "cascade_recall_at_10": recall_c,
+        "cascade_qps_same_queries": cascade_qps,
+        "bruteforce_qps": brute_qps,
+        "speedup_vs_bruteforce": (qps / brute_qps) if brute_qps else None,
+        "stages_ms_per_step": per_step,
+        "codes_attach_s": attach_s,
+        "codes_bytes": nbytes,
+        "index_build_s": build_s,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -759,6 +871,9 @@ def main():
     if args.workload == "precision":
         res = precision(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db.offsets)
         print(json.dumps(res), flush=True)
+        return
+    if args.workload == "full":
+        print(json.dumps(full_scan(args, w, ix, q, q_off, n_vec, build_s)), flush=True)
         return
 
     n_q = w["n_queries"]

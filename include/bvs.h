@@ -145,6 +145,16 @@ bvs_status bvs_build_index(const bvs_params* p, const float* d_vectors,
 /* Releases the host handle (the caller frees the device memory). */
 void bvs_index_destroy(bvs_index* ix);
 
+/* Changes the search-time parameters of Alg. 6 of a built index: A
+ * (access_lists), M (min_count) and T (top_t).  The sketches and bitmaps of
+ * the index do not depend on them, so no rebuild is needed; they are
+ * validated as by bvs_params_check (BVS_EINVAL / BVS_ENOTSUP, index
+ * unchanged).  The index is otherwise immutable: this call must not overlap
+ * any other call on the index, workspaces must be sized again afterwards,
+ * and batched plans created before it must be created again. */
+bvs_status bvs_index_set_search_params(bvs_index* ix, uint32_t access_lists, uint32_t min_count,
+                                       uint32_t top_t);
+
 bvs_status bvs_index_get_info(const bvs_index* ix, bvs_index_info* info);
 bvs_status bvs_index_get_params(const bvs_index* ix, bvs_params* p);
 
@@ -265,6 +275,51 @@ bvs_status bvs_bruteforce_metric(const bvs_index* ix, int metric, const float* d
                                  void* d_workspace, uint64_t workspace_bytes,
                                  uint32_t* d_ids, float* d_dist, uint32_t* d_count,
                                  void* stream);
+
+/* ------------------------------------------------------------------------
+ * Full-scan search (Alg. 2, the paper's first method): every set is scored
+ * by Haus^H, Def. 4 with the Hamming distance between FlyHash codes (Def. 7)
+ * in place of the Euclidean distance, the first c = top_t sets by
+ * (Haus^H, id) are kept (Alg. 2 keeps every set at most the c-th smallest;
+ * ties beyond c go to the lower ids), and those are re-ranked by the exact
+ * Hausdorff distance as in bvs_search.  It needs the codes of every database
+ * vector, kept in sparse form (the wta_k positions of each code, uint16,
+ * rows padded to a multiple of 8) in caller memory attached to the index:
+ *   bvs_codes_bytes      device bytes of that memory: N rows of the padded
+ *                        positions, and the set ids ordered by size
+ *   bvs_codes_attach     encodes every vector of the index (random or
+ *                        learned projection) into d_mem, using a workspace of
+ *                        bvs_codes_attach_workspace_bytes; synchronises; the
+ *                        memory must outlive the index's use of the full
+ *                        scan; attaching again replaces it.  wta_k must be at
+ *                        most 255 (BVS_ENOTSUP).
+ * The search calls return BVS_ESTATE when nothing is attached and take a
+ * workspace of bvs_search_full_workspace_bytes.
+ *   bvs_full_scores            Haus^H of every query to every set:
+ *                              d_scores uint16 [n_q][n_sets]
+ *   bvs_search_full_candidates F of every query: ids, scores and count as
+ *                              for bvs_search_candidates (top_t slots)
+ *   bvs_search_full            the whole of Alg. 2; outputs as bvs_search */
+bvs_status bvs_codes_bytes(const bvs_index* ix, uint64_t* out_bytes);
+bvs_status bvs_codes_attach_workspace_bytes(const bvs_index* ix, uint64_t* out_bytes);
+bvs_status bvs_codes_attach(bvs_index* ix, void* d_mem, uint64_t bytes,
+                            void* d_workspace, uint64_t workspace_bytes, void* stream);
+bvs_status bvs_search_full_workspace_bytes(const bvs_index* ix, uint32_t n_q,
+                                           uint64_t n_q_vectors, uint64_t* out_bytes);
+bvs_status bvs_full_scores(const bvs_index* ix, const float* d_q,
+                           const uint64_t* h_q_offsets, uint32_t n_q,
+                           void* d_workspace, uint64_t workspace_bytes,
+                           uint16_t* d_scores, void* stream);
+bvs_status bvs_search_full_candidates(const bvs_index* ix, const float* d_q,
+                                      const uint64_t* h_q_offsets, uint32_t n_q,
+                                      void* d_workspace, uint64_t workspace_bytes,
+                                      uint32_t* d_ids, uint16_t* d_scores,
+                                      uint32_t* d_count, void* stream);
+bvs_status bvs_search_full(const bvs_index* ix, const float* d_q,
+                           const uint64_t* h_q_offsets, uint32_t n_q, uint32_t k,
+                           void* d_workspace, uint64_t workspace_bytes,
+                           uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                           void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched search: many query sets of uneven size through the whole cascade
@@ -485,7 +540,8 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
  * and histogram selection, used when the sampled cutoff did not hold T
  * candidates or overflowed its buffer), 10 approximate re-rank of the
  * precision form (encoding of the queries, approximate values, selection
- * of the candidates to re-check), 11 exact re-check of the precision form.
+ * of the candidates to re-check), 11 exact re-check of the precision form,
+ * 12 full scan (query tables and the Hamming-Hausdorff score of every set).
  * Work counters (summed over calls): 0 first-layer member pairs scored by
  * the filter stage, 1 database vectors read in full (both planes) by the
  * re-rank stage, 2 re-rank candidates abandoned early (screened ones
@@ -499,7 +555,7 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
  * (their atomics slow the counted kernels somewhat), 0 turns both off. */
 #define BVS_PROFILE_TIMING 1
 #define BVS_PROFILE_COUNTERS 2
-#define BVS_N_STAGES 12
+#define BVS_N_STAGES 13
 #define BVS_N_COUNTERS 7
 typedef struct bvs_stage_times {
   double ms[BVS_N_STAGES];

@@ -32,12 +32,14 @@ EXPORTED = [
     "bvs_hausdorff_lowp", "bvs_mlp_weight_count", "bvs_mlp_init", "bvs_learned_index_bytes",
     "bvs_learned_build_workspace_bytes", "bvs_build_index_learned", "bvs_train_workspace_bytes",
     "bvs_train_gradients", "bvs_train_projection", "bvs_search_noalloc_max_bytes", "bvs_search_noalloc",
-    "bvs_search_metric", "bvs_bruteforce_metric",
+    "bvs_search_metric", "bvs_bruteforce_metric", "bvs_codes_bytes", "bvs_codes_attach_workspace_bytes",
+    "bvs_codes_attach", "bvs_search_full_workspace_bytes", "bvs_full_scores", "bvs_search_full_candidates",
+    "bvs_search_full", "bvs_index_set_search_params",
 ]
 METRIC = {"hausdorff": 0, "meanmin": 1, "min": 2}
 LOWP = {"bf16": 1, "fp8": 2}
 TUNE_MAX = 16
-N_STAGES = 12
+N_STAGES = 13
 N_COUNTERS = 7
 COUNTER_NAMES = ("filter_pairs", "rerank_vectors", "rerank_abandoned", "rerank_candidates",
                  "rerank_screen_vectors", "rerank_screened", "lowp_vectors")
@@ -123,6 +125,14 @@ def lib():
             "bvs_search_metric": (C.c_int, [P, C.c_int, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_bruteforce_metric": (C.c_int, [P, C.c_int, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_search_noalloc": (C.c_int, [P, P, P, U32, U32, P, P, P, P]),
+            "bvs_index_set_search_params": (C.c_int, [P, U32, U32, U32]),
+            "bvs_codes_bytes": (C.c_int, [P, PU64]),
+            "bvs_codes_attach_workspace_bytes": (C.c_int, [P, PU64]),
+            "bvs_codes_attach": (C.c_int, [P, P, U64, P, U64, P]),
+            "bvs_search_full_workspace_bytes": (C.c_int, [P, U32, U64, PU64]),
+            "bvs_full_scores": (C.c_int, [P, P, P, U32, P, U64, P, P]),
+            "bvs_search_full_candidates": (C.c_int, [P, P, P, U32, P, U64, P, P, P, P]),
+            "bvs_search_full": (C.c_int, [P, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_bruteforce_workspace_bytes": (C.c_int, [P, U32, U64, PU64]),
             "bvs_bruteforce": (C.c_int, [P, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_hausdorff_all": (C.c_int, [P, P, P, U32, P, U64, P, P]),
@@ -358,6 +368,55 @@ class Index:
         ids, dist, cnt = out
         check(lib().bvs_search_noalloc(self._h, _ptr(q), _u64p(off), n_q, k, _ptr(ids), _ptr(dist), _ptr(cnt),
                                        _stream(stream)))
+        return ids, dist, cnt
+
+    def set_search_params(self, access_lists: int, min_count: int, top_t: int):
+        """A, M and T of later searches (no rebuild; workspaces must be sized again)."""
+        check(lib().bvs_index_set_search_params(self._h, access_lists, min_count, top_t))
+        self.params.access_lists, self.params.min_count, self.params.top_t = access_lists, min_count, top_t
+
+    # -- full scan (Alg. 2)
+    def attach_codes(self, stream=None) -> int:
+        """Encode every database vector into sparse codes for the full scan."""
+        nbytes = _bytes(lib().bvs_codes_bytes, self._h)
+        wbytes = _bytes(lib().bvs_codes_attach_workspace_bytes, self._h)
+        mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ws = _workspace(wbytes, self.device)
+        check(lib().bvs_codes_attach(self._h, _ptr(mem), nbytes, _ptr(ws), ws.numel(), _stream(stream)))
+        self._codes = mem
+        return nbytes
+
+    def full_workspace(self, n_q: int, n_q_vectors: int) -> torch.Tensor:
+        return _workspace(_bytes(lib().bvs_search_full_workspace_bytes, self._h, n_q, n_q_vectors), self.device)
+
+    def full_scores(self, q, q_offsets, stream=None) -> torch.Tensor:
+        """Haus^H of every query to every set, int16 [n_q, n_sets] (uint16 values)."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        out = torch.empty(n_q, self.n_sets, dtype=torch.int16, device=self.device)
+        ws = self.full_workspace(n_q, NQ)
+        check(lib().bvs_full_scores(self._h, _ptr(q), _u64p(off), n_q, _ptr(ws), ws.numel(), _ptr(out),
+                                    _stream(stream)))
+        return out
+
+    def full_candidates(self, q, q_offsets, stream=None):
+        """F of Alg. 2 per query: ids int32 [n_q, T], scores int16 [n_q, T], count int32 [n_q]."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        T = self.params.top_t
+        ids = torch.empty(n_q, T, dtype=torch.int32, device=self.device)
+        sc = torch.empty(n_q, T, dtype=torch.int16, device=self.device)
+        cnt = torch.empty(n_q, dtype=torch.int32, device=self.device)
+        ws = self.full_workspace(n_q, NQ)
+        check(lib().bvs_search_full_candidates(self._h, _ptr(q), _u64p(off), n_q, _ptr(ws), ws.numel(), _ptr(ids),
+                                               _ptr(sc), _ptr(cnt), _stream(stream)))
+        return ids, sc, cnt
+
+    def search_full(self, q, q_offsets, k: int, ws: torch.Tensor | None = None, out=None, stream=None):
+        """Alg. 2 top-k per query; outputs as for `search`."""
+        off, n_q, NQ = self._qargs(q, q_offsets)
+        ws = self.full_workspace(n_q, NQ) if ws is None else ws
+        ids, dist, cnt = self._outs(n_q, k) if out is None else out
+        check(lib().bvs_search_full(self._h, _ptr(q), _u64p(off), n_q, k, _ptr(ws), ws.numel(), _ptr(ids),
+                                    _ptr(dist), _ptr(cnt), _stream(stream)))
         return ids, dist, cnt
 
     # -- precision form

@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(HERE, "_obj")
 OUT = os.path.join(PKG, "libbvs.so")
 
-SOURCES = ["capi.cpp", "k_encode.hip", "k_filter.hip", "k_sliced.hip", "k_haus.hip", "k_batch.hip", "k_lowp.hip", "k_learn.hip"]
+SOURCES = ["capi.cpp", "k_encode.hip", "k_filter.hip", "k_sliced.hip", "k_haus.hip", "k_batch.hip", "k_lowp.hip", "k_learn.hip",
+           "k_full.hip"]
 HEADERS = ["device.h", "launch.h", "haus_core.h", os.path.join(INCLUDE, "bvs.h")]
 ARCH = "gfx950"
 

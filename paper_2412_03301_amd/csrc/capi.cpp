@@ -169,7 +169,8 @@ bvs_status read_status(uint32_t* d_status, hipStream_t st, const char* what) {
 // ------------------------------------------------------------------ stage timing
 const char* const kStageNames[BVS_N_STAGES] = {"convert",  "encode",   "query_sketch", "cutoff",
                                                "filter",   "select",   "rerank",       "topk",
-                                               "bruteforce", "fallback", "approx",     "recheck"};
+                                               "bruteforce", "fallback", "approx",     "recheck",
+                                               "fullscan"};
 
 struct ProfTable {
   std::mutex mu;
@@ -262,7 +263,7 @@ hipError_t staged(CallProf& p, int stage, F&& f) {
 }
 
 enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_CUTOFF, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE, S_FALLBACK,
-       S_APPROX, S_RECHECK };
+       S_APPROX, S_RECHECK, S_FULLSCAN };
 
 }  // namespace
 
@@ -291,6 +292,10 @@ struct bvs_index {
   uint16_t* w16 = nullptr;   // packed bfloat16 [W1 | b1 | W2 | b2]
   float* b1 = nullptr;       // [hidden]
   float* b2 = nullptr;       // [L]
+  // attached sparse codes for the full scan (Alg. 2)
+  uint16_t* fpos = nullptr;  // [N][KP] code positions of every vector
+  uint32_t* forder = nullptr;  // [n] set ids by decreasing size (ties: lower id first)
+  uint32_t fKP = 0;
 };
 
 namespace {
@@ -909,6 +914,23 @@ bvs_status bvs_index_get_info(const bvs_index* ix, bvs_index_info* info) {
 bvs_status bvs_index_get_params(const bvs_index* ix, bvs_params* p) {
   if (!ix || !p) return fail(BVS_EINVAL, "NULL argument");
   *p = ix->p;
+  return BVS_OK;
+}
+
+bvs_status bvs_index_set_search_params(bvs_index* ix, uint32_t access_lists, uint32_t min_count, uint32_t top_t) {
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  bvs_params p = ix->p;
+  p.access_lists = access_lists;
+  p.min_count = min_count;
+  p.top_t = top_t;
+  Geometry g;
+  BVS_TRY(derive(&p, &g));
+  ix->p.access_lists = access_lists;
+  ix->p.min_count = min_count;
+  ix->p.top_t = top_t;
+  ix->g.A = g.A;
+  ix->g.M = g.M;
+  ix->g.T = g.T;
   return BVS_OK;
 }
 
@@ -2056,6 +2078,232 @@ bvs_status bvs_search_noalloc(const bvs_index* ix, const float* d_q, const uint6
   BVS_TRY(scratch_for_device(dev, &ws));
   return search_impl(ix, d_q, h_q_off, n_q, k, ws, kScratchBytes, d_ids, d_dist, d_count, (hipStream_t)stream,
                      false);
+}
+
+}  // extern "C"
+
+// ====================================================================== full scan (Alg. 2)
+namespace {
+
+constexpr uint64_t kFullChunk = 1ull << 20;   // vectors encoded per attach step
+constexpr uint32_t kFullGroups = 4;           // query vectors up to 256, 64 per group
+
+uint32_t full_kp(const Geometry& g) { return (uint32_t)align_up(g.wta_k, 8); }
+
+void layout_codes(Carver& c, const bvs_index* ix, uint16_t** pos, uint32_t** order) {
+  *pos = c.take<uint16_t>(ix->N * full_kp(ix->g));
+  *order = c.take<uint32_t>(ix->n);
+}
+
+struct FullWs {
+  QueryWs w;
+  uint64_t* table;   // [n_q][G][L]
+  uint32_t G;
+};
+
+uint32_t full_groups(uint64_t max_rows) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kFullGroups, (max_rows + 63) / 64));
+}
+
+void layout_full(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, uint32_t G, FullWs* f) {
+  layout_search(c, ix, n_q, NQ, &f->w);
+  f->G = G;
+  f->table = c.take<uint64_t>((uint64_t)n_q * G * ix->g.L);
+}
+
+bvs_status full_ready(const bvs_index* ix) {
+  if (!ix->fpos) return fail(BVS_ESTATE, "no codes attached for the full scan (bvs_codes_attach)");
+  return BVS_OK;
+}
+
+// Haus^H scores of every set into w.scores, then F = the first T by (score, id).
+bvs_status full_filter(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const FullWs& f, uint32_t* ids,
+                       uint16_t* scores, uint32_t* count, hipStream_t st, CallProf& prof) {
+  const Geometry& g = ix->g;
+  const QueryWs& w = f.w;
+  if (prof.count) HIP_TRY(launch_fill_u32((uint32_t*)w.stats, 2ull * kStatSlots * kStatCounters, 0, st));
+  HIP_TRY(staged(prof, S_ENCODE, [&] { return encode_planes(ix, w.qhi, w.qlo, NQ, w.codes, w.lx16, w.lh16, w.ly, st); }));
+  HIP_TRY(staged(prof, S_FULLSCAN, [&]() -> hipError_t {
+    hipError_t e = launch_query_table(w.codes, w.qoff, n_q, g.L, g.R, f.G, f.table, st);
+    if (e != hipSuccess) return e;
+    // sets past n (the padding of ld) stay excluded
+    e = launch_fill_u32((uint32_t*)w.scores, (uint64_t)n_q * ix->ld / 2, 0xFFFFFFFFu, st);
+    if (e != hipSuccess) return e;
+    return launch_full_scan(ix->fpos, ix->offsets, ix->forder, ix->n, g.wta_k, ix->fKP, g.L, f.table, w.qoff, n_q,
+                            f.G, w.scores, ix->ld, st);
+  }));
+  HIP_TRY(staged(prof, S_SELECT, [&] {
+    return launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, ids, scores, count, nullptr, st);
+  }));
+  return BVS_OK;
+}
+
+// Common prologue of the full-scan calls.
+bvs_status full_begin(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, void* d_ws,
+                      uint64_t ws_bytes, uint32_t* max_rows, FullWs* f) {
+  BVS_TRY(check_queries(ix, d_q, h_q_off, n_q, max_rows));
+  BVS_TRY(full_ready(ix));
+  const uint64_t NQ = h_q_off[n_q];
+  uint64_t need = 0;
+  BVS_TRY(bvs_search_full_workspace_bytes(ix, n_q, NQ, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  Carver c(d_ws);
+  layout_full(c, ix, n_q, NQ, full_groups(std::min<uint64_t>(NQ, 256)), f);
+  return BVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bvs_status bvs_codes_bytes(const bvs_index* ix, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  Carver c(nullptr);
+  uint16_t* p;
+  uint32_t* o;
+  layout_codes(c, ix, &p, &o);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_codes_attach_workspace_bytes(const bvs_index* ix, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  const uint64_t rows = std::max<uint64_t>(1, std::min<uint64_t>(ix->N, kFullChunk));
+  Carver c(nullptr);
+  c.take<uint64_t>(rows * ix->g.R);
+  if (ix->learned) {
+    c.take<uint16_t>(rows * ix->g.d);
+    c.take<uint16_t>(rows * ix->hidden);
+    c.take<float>(rows * ix->g.L);
+  }
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_codes_attach(bvs_index* ix, void* d_mem, uint64_t bytes, void* d_ws, uint64_t ws_bytes, void* stream) {
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (ix->g.wta_k > 255) return fail(BVS_ENOTSUP, "the full scan counts overlaps of up to 255 positions (wta_k %u)",
+                                     ix->g.wta_k);
+  uint64_t need = 0, wneed = 0;
+  BVS_TRY(bvs_codes_bytes(ix, &need));
+  BVS_TRY(bvs_codes_attach_workspace_bytes(ix, &wneed));
+  if (!d_mem) return fail(BVS_EINVAL, "code memory is NULL");
+  if (bytes < need)
+    return fail(BVS_ENOSPC, "code memory of %llu bytes, %llu needed", (unsigned long long)bytes,
+                (unsigned long long)need);
+  BVS_TRY(need_ws(ws_bytes, wneed, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  const Geometry& g = ix->g;
+  const uint32_t KP = full_kp(g);
+  Carver c(d_mem);
+  uint16_t* pos;
+  uint32_t* order;
+  layout_codes(c, ix, &pos, &order);
+  // sets by decreasing size, ties to the lower id (counting sort on the host)
+  std::vector<uint64_t> off(ix->n + 1);
+  HIP_TRY(hipMemcpyAsync(off.data(), ix->offsets, off.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<uint64_t> start(257, 0);
+  for (uint64_t j = 0; j < ix->n; ++j) ++start[255 - (off[j + 1] - off[j]) + 1];
+  for (int b = 1; b <= 256; ++b) start[b] += start[b - 1];
+  std::vector<uint32_t> ord(ix->n);
+  for (uint64_t j = 0; j < ix->n; ++j) ord[start[255 - (off[j + 1] - off[j])]++] = (uint32_t)j;
+  HIP_TRY(hipMemcpyAsync(order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, st));
+  Carver wc(d_ws);
+  const uint64_t rows = std::max<uint64_t>(1, std::min<uint64_t>(ix->N, kFullChunk));
+  uint64_t* codes = wc.take<uint64_t>(rows * g.R);
+  uint16_t* x16 = ix->learned ? wc.take<uint16_t>(rows * g.d) : nullptr;
+  uint16_t* h16 = ix->learned ? wc.take<uint16_t>(rows * ix->hidden) : nullptr;
+  float* y = ix->learned ? wc.take<float>(rows * g.L) : nullptr;
+  for (uint64_t r0 = 0; r0 < ix->N; r0 += rows) {
+    const uint64_t nr = std::min<uint64_t>(rows, ix->N - r0);
+    HIP_TRY(encode_planes(ix, ix->hi + r0 * g.dp, ix->lo + r0 * g.dp, nr, codes, x16, h16, y, st));
+    HIP_TRY(launch_code_positions(codes, nr, g.R, g.wta_k, KP, pos + r0 * KP, ix->n_cu, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  ix->fpos = pos;
+  ix->forder = order;
+  ix->fKP = KP;
+  return BVS_OK;
+}
+
+bvs_status bvs_search_full_workspace_bytes(const bvs_index* ix, uint32_t n_q, uint64_t n_q_vectors, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  Carver c(nullptr);
+  FullWs f;
+  layout_full(c, ix, n_q, n_q_vectors, full_groups(std::min<uint64_t>(n_q_vectors, 256)), &f);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_full_scores(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, void* d_ws,
+                           uint64_t ws_bytes, uint16_t* d_scores, void* stream) {
+  if (!d_scores) return fail(BVS_EINVAL, "NULL output");
+  uint32_t max_rows = 0;
+  FullWs f;
+  BVS_TRY(full_begin(ix, d_q, h_q_off, n_q, d_ws, ws_bytes, &max_rows, &f));
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t NQ = h_q_off[n_q];
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, f.w, st, prof));
+  HIP_TRY(staged(prof, S_ENCODE,
+                 [&] { return encode_planes(ix, f.w.qhi, f.w.qlo, NQ, f.w.codes, f.w.lx16, f.w.lh16, f.w.ly, st); }));
+  HIP_TRY(staged(prof, S_FULLSCAN, [&]() -> hipError_t {
+    hipError_t e = launch_query_table(f.w.codes, f.w.qoff, n_q, ix->g.L, ix->g.R, f.G, f.table, st);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32((uint32_t*)f.w.scores, (uint64_t)n_q * ix->ld / 2, 0xFFFFFFFFu, st);
+    if (e != hipSuccess) return e;
+    return launch_full_scan(ix->fpos, ix->offsets, ix->forder, ix->n, ix->g.wta_k, ix->fKP, ix->g.L, f.table,
+                            f.w.qoff, n_q, f.G, f.w.scores, ix->ld, st);
+  }));
+  for (uint32_t q = 0; q < n_q; ++q)
+    HIP_TRY(hipMemcpyAsync(d_scores + (uint64_t)q * ix->n, f.w.scores + (uint64_t)q * ix->ld, ix->n * 2,
+                           hipMemcpyDeviceToDevice, st));
+  const bvs_status s = read_status(f.w.status, st, "queries");
+  prof.finish();
+  return s;
+}
+
+bvs_status bvs_search_full_candidates(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
+                                      void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, uint16_t* d_scores,
+                                      uint32_t* d_count, void* stream) {
+  if (!d_ids || !d_scores || !d_count) return fail(BVS_EINVAL, "NULL output");
+  uint32_t max_rows = 0;
+  FullWs f;
+  BVS_TRY(full_begin(ix, d_q, h_q_off, n_q, d_ws, ws_bytes, &max_rows, &f));
+  hipStream_t st = (hipStream_t)stream;
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, f.w, st, prof));
+  BVS_TRY(full_filter(ix, n_q, h_q_off[n_q], f, d_ids, d_scores, d_count, st, prof));
+  const bvs_status s = read_status(f.w.status, st, "queries");
+  prof.finish();
+  return s;
+}
+
+bvs_status bvs_search_full(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q, uint32_t k,
+                           void* d_ws, uint64_t ws_bytes, uint32_t* d_ids, float* d_dist, uint32_t* d_count,
+                           void* stream) {
+  if (!d_ids || !d_dist || !d_count) return fail(BVS_EINVAL, "NULL output");
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (k < 1 || k > kMaxK || k > ix->g.T) return fail(BVS_EINVAL, "k %u outside 1..min(64, top_t)", k);
+  uint32_t max_rows = 0;
+  FullWs f;
+  BVS_TRY(full_begin(ix, d_q, h_q_off, n_q, d_ws, ws_bytes, &max_rows, &f));
+  hipStream_t st = (hipStream_t)stream;
+  const QueryWs& w = f.w;
+  CallProf prof(st);
+  BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
+  BVS_TRY(full_filter(ix, n_q, h_q_off[n_q], f, w.f2_ids, w.f2_scores, w.f2_count, st, prof));
+  HIP_TRY(staged(prof, S_RERANK, [&] {
+    return launch_haus_cand(haus_db(ix), haus_q(w, n_q, max_rows), w.f2_ids, w.f2_count, ix->g.T, k, w.thr, w.h2,
+                            prof.count ? w.stats : nullptr, w.surv, w.surv_count, st);
+  }));
+  HIP_TRY(staged(prof, S_TOPK, [&] {
+    return launch_topk(w.h2, w.f2_ids, w.f2_count, ix->g.T, ix->g.T, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st);
+  }));
+  const bvs_status s = read_status(w.status, st, "queries");
+  prof.finish(prof.count ? w.stats : nullptr);
+  return s;
 }
 
 }  // extern "C"

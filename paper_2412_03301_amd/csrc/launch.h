@@ -187,6 +187,20 @@ hipError_t haus_queue_occupancy(uint32_t dp, uint32_t lds_rows, uint32_t waves, 
 hipError_t launch_haus_queue(const HausDb& db, const HausQ& q, const QueueArgs& a, uint32_t waves,
                              uint32_t blocks, hipStream_t st);
 
+// Full-scan search (Alg. 2).  pos [n][KP] uint16: the K code positions of
+// every vector (from codes [n][R] uint64).  table [n_q][G][L] uint64: bit i
+// of entry (q, g, p) says whether vector 64 g + i of query q has position p.
+// Scan: scores[q][j] = Haus^H (Hamming form of Def. 4) of query q to set j
+// for the n_sets sets listed in order [n_sets] (any order; by size keeps
+// the lanes of a wave together).
+hipError_t launch_code_positions(const uint64_t* codes, uint64_t n, uint32_t R, uint32_t K, uint32_t KP,
+                                 uint16_t* pos, int n_cu, hipStream_t st);
+hipError_t launch_query_table(const uint64_t* codes, const uint64_t* q_off, uint32_t n_q, uint32_t L, uint32_t R,
+                              uint32_t G, uint64_t* table, hipStream_t st);
+hipError_t launch_full_scan(const uint16_t* pos, const uint64_t* offsets, const uint32_t* order, uint64_t n_sets,
+                            uint32_t K, uint32_t KP, uint32_t L, const uint64_t* table, const uint64_t* q_off,
+                            uint32_t n_q, uint32_t G, uint16_t* scores, uint64_t ld, hipStream_t st);
+
 // First k by (h2, id) of each query.  ids_in may be NULL (item index = id).
 // tmp must hold 2 * n_q * ceil(n_items / 4096) * k uint64.  Reported
 // distances are sqrt(h2) / 4096, or the float32 whose bits are h2 when

@@ -191,6 +191,12 @@ WORKLOADS = {
     "learned": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=768, n_topics=10_000,
                     code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10,
                     hidden=1024, train_sets=100_000, train_seed=100, mine_queries=20_000, negatives=10),
+    # the scale database searched by the full scan of Alg. 2, and by the
+    # re-rank with other set measures
+    "full": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
+                 code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10),
+    "metrics": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
+                    code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10),
     # the scale database, searched by fresh-entity queries of 1-256 vectors
     "batched": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
                     code_bits=4096, fan_in=16, wta_k=64, n_queries=4096, max_query=256, top_t=1000, k=10),

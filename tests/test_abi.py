@@ -151,3 +151,8 @@ def test_metric_calls_reject_unknown_metric_on_the_host(bvs):
         assert fn(None, 7, None, None, 1, 10, None, 0, None, None, None, None) == bvs.BVS_EINVAL
         assert b"metric" in lib.bvs_last_error()
         assert fn(None, -1, None, None, 1, 10, None, 0, None, None, None, None) == bvs.BVS_EINVAL
+
+
+def test_search_params_setter_validates_on_the_host(bvs):
+    lib = bvs.lib()
+    assert lib.bvs_index_set_search_params(None, 3, 1, 1000) == bvs.BVS_EINVAL
