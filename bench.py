@@ -34,6 +34,8 @@ METRIC = "queries/sec at recall@10>=0.95 on 1M sets vs GPU brute-force Hausdorff
 HBM_PEAK_GBS = 8000.0
 # Integer VALU lanes: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Dense int8 matrix-core peak of MI355X (TOP/s), the brute force's roof.
+INT8_PEAK_TOPS = 5000.0
 
 
 def log(msg):
@@ -45,7 +47,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scale", choices=["scale", "tiny", "batched", "precision", "learned", "full", "metrics"])
+    ap.add_argument("--workload", default="scale", choices=["scale", "tiny", "batched", "precision", "learned", "full", "metrics",
+                                                       "trends"])
     ap.add_argument("--train-epochs", type=int, default=1)
     ap.add_argument("--train-batch", type=int, default=256)
     ap.add_argument("--train-lr", type=float, default=3e-4)
@@ -61,9 +64,13 @@ def parse():
     ap.add_argument("--n-sets", type=int, default=None, help="override the set count (for quick runs)")
     ap.add_argument("--queries", type=int, default=None)
     ap.add_argument("--top-t", type=int, default=None)
-    ap.add_argument("--brute-queries", type=int, default=128)
+    ap.add_argument("--brute-queries", type=int, default=256)
+    ap.add_argument("--op-sweep", default="100,200,300,500,1000",
+                    help="scale workload: T values for the recall/throughput operating points ('' to skip)")
+    ap.add_argument("--bf16-brute", type=int, default=16,
+                    help="scale workload: queries of the bfloat16 brute force (0 to skip)")
     ap.add_argument("--cpu-sample-sets", type=int, default=1000)
-    ap.add_argument("--cpu-sample-queries", type=int, default=3)
+    ap.add_argument("--cpu-sample-queries", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-brute", action="store_true")
     ap.add_argument("--full-queries", type=int, default=64,
@@ -99,53 +106,99 @@ def traffic_from_profiles(kernel_file, kernel_prefix):
         return None
 
 
-def cpu_baseline(db_cpu, offsets, q_cpu, q_off, cfg, n_sets_full, sample_sets, sample_queries):
-    """The oracle as it stands, on the host: a slice of the first sample_sets
-    sets (same generator and parameters) and a few queries.  Per query the
-    filter steps are timed on the slice and scaled to the full set count;
-    the exact re-rank is timed on the slice's F2 and scaled to T sets."""
+_CPU = {}
+
+
+def _cpu_query(i):
+    """One query of the oracle on the slice (runs in a pool worker; the
+    slice index is inherited from the parent).  Returns the seconds spent in
+    query encoding, in the filter steps and in the exact re-rank, and the
+    vectors of the slice's F2 that the re-rank measured."""
     import numpy as np
-    from threadpoolctl import threadpool_info
 
     from oracle import filter as flt
-    from oracle import flyhash, hausdorff, prng, search
+    from oracle import flyhash, hausdorff, search
 
+    st = _CPU
+    cfg, ix = st["cfg"], st["ix"]
+    Q = st["q"][st["q_off"][i]:st["q_off"][i + 1]].astype(np.float64)
+    t0 = time.perf_counter()
+    HQ = flyhash.codes(Q, ix.idx, cfg["wta_k"])
+    C_Q, S_Q = flt.query_sketches(HQ)
+    P = flt.top_positions(C_Q, cfg["A"])
+    t1 = time.perf_counter()
+    member = flt.first_filter(ix.C, P, cfg["M"])
+    scores = flt.hamming(S_Q, ix.B)
+    f2, _ = flt.second_filter(member, scores, cfg["top_t"])
+    t2 = time.perf_counter()
+    h2 = np.array([hausdorff.hausdorff_sq(Q, ix.members(j)) for j in f2])
+    search.rank_by_distance(f2, h2, cfg["k"])
+    t3 = time.perf_counter()
+    vec = int(sum(ix.offsets[j + 1] - ix.offsets[j] for j in f2))
+    return t1 - t0, t2 - t1, t3 - t2, vec
+
+
+def cpu_baseline(db_cpu, offsets, q_cpu, q_off, cfg, n_sets_full, sample_sets, sample_queries, f2_vectors):
+    """The oracle as it stands, on the host cores: a slice of the first
+    sample_sets sets (same generator and parameters) and sample_queries
+    queries spread over a process pool with one worker per core (one BLAS
+    thread each).  Per query: encoding as measured; the filter steps (linear
+    in the set count) scaled from the slice to the full set count; the exact
+    re-rank scaled from its time per vector on the slice's F2 to the number
+    of vectors in that query's F2 on the full database (f2_vectors, from the
+    GPU's F2).  Throughput = workers / mean scaled seconds per query."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import prng, search
+
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
     n_s = min(sample_sets, len(offsets) - 1)
     X = db_cpu[: offsets[n_s]].astype(np.float64)
     off = offsets[: n_s + 1]
     idx = prng.projection_rows(cfg["seed"], cfg["dim"], cfg["code_bits"], cfg["fan_in"])
     t0 = time.perf_counter()
-    ix = search.build_index(X, off, idx, cfg["wta_k"])
+    with threadpool_limits(cores):
+        ix = search.build_index(X, off, idx, cfg["wta_k"])
     build_s = time.perf_counter() - t0
+    _CPU.update(cfg=cfg, ix=ix, q=q_cpu, q_off=q_off)
+    nq = min(sample_queries, len(q_off) - 1, len(f2_vectors))
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        with mp.get_context("fork").Pool(cores) as pool:
+            res = pool.map(_cpu_query, range(nq), chunksize=1)
+    wall = time.perf_counter() - t0
     per_q = []
-    for i in range(sample_queries):
-        Q = q_cpu[q_off[i]:q_off[i + 1]].astype(np.float64)
-        t0 = time.perf_counter()
-        HQ = flyhash.codes(Q, idx, cfg["wta_k"])
-        C_Q, S_Q = flt.query_sketches(HQ)
-        P = flt.top_positions(C_Q, cfg["A"])
-        t1 = time.perf_counter()
-        member = flt.first_filter(ix.C, P, cfg["M"])
-        scores = flt.hamming(S_Q, ix.B)
-        f2, _ = flt.second_filter(member, scores, cfg["top_t"])
-        t2 = time.perf_counter()
-        h2 = np.array([hausdorff.hausdorff_sq(Q, ix.members(j)) for j in f2])
-        search.rank_by_distance(f2, h2, cfg["k"])
-        t3 = time.perf_counter()
-        scale_filter = n_sets_full / n_s
-        scale_rerank = cfg["top_t"] / max(1, len(f2))
-        per_q.append((t1 - t0) + (t2 - t1) * scale_filter + (t3 - t2) * scale_rerank)
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    for i, (te, tf, tr, vec) in enumerate(res):
+        per_q.append(te + tf * n_sets_full / n_s + tr / max(1, vec) * float(f2_vectors[i]))
     return {
-        "value": 1.0 / (sum(per_q) / len(per_q)),
+        "value": cores / (sum(per_q) / len(per_q)),
         "unit": "queries/s",
-        "cores": threads,
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"oracle search of {sample_queries} queries against the first {n_s} sets of the workload "
-                   f"(index of the slice built untimed in {build_s:.1f} s); filter steps scaled by "
-                   f"{n_sets_full}/{n_s}, re-rank scaled to T={cfg['top_t']} candidates; BLAS stages use "
-                   f"{threads} threads, the rest of numpy one"),
+        "sample": (f"oracle search of {nq} queries against the first {n_s} sets of the workload (slice index built "
+                   f"in {build_s:.1f} s, untimed), in a pool of {cores} worker processes with one BLAS thread each "
+                   f"({wall:.1f} s wall); per query the filter steps are scaled by {n_sets_full}/{n_s} and the "
+                   f"exact re-rank from its time per vector to the {np.mean(f2_vectors[:nq]):.0f} vectors (mean) "
+                   f"of that query's F2 on the full database; throughput = workers / mean scaled time"),
+        "mean_s_per_query": {"encode": float(np.mean([r[0] for r in res])),
+                             "filter_scaled": float(np.mean([r[1] * n_sets_full / n_s for r in res])),
+                             "rerank_scaled": float(np.mean([r[2] / max(1, r[3]) * float(f2_vectors[i])
+                                                             for i, r in enumerate(res)]))},
     }
+
+
+def f2_vectors_per_query(ix, q, q_off, db_offsets):
+    """Vectors in each query's F2 (sum of the member sets' sizes), from the
+    GPU's candidate lists (outside any timed region)."""
+    import numpy as np
+    ids, _, cnt = ix.candidates(q, q_off)
+    ids = ids.cpu().numpy().view(np.uint32)
+    cnt = cnt.cpu().numpy()
+    sizes = np.diff(np.asarray(db_offsets, dtype=np.int64))
+    return np.array([int(sizes[ids[i, :cnt[i]].astype(np.int64)].sum()) for i in range(len(cnt))], dtype=np.int64)
 
 
 def sketch_rows(ix, q, q_off):
@@ -199,6 +252,108 @@ def rooflines(per_step, work, L, dim_padded, rerank_kernel, rerank_file, n_sets=
                    "candidates": work["rerank_candidates"], "abandoned": work["rerank_abandoned"],
                    "screened_out": work.get("rerank_screened", 0.0)}
     return roof, rerank_roof
+
+
+def bf16_bruteforce(ix, q, q_off, k, nq, truth, n_vec):
+    """Brute force through the bfloat16 copy of the vectors on the matrix
+    cores (approximate Hausdorff values of every set, then the k smallest):
+    throughput and recall against the exact brute force."""
+    import numpy as np
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nbytes = ix.attach_lowp("bf16")
+    torch.cuda.synchronize()
+    attach_s = time.perf_counter() - t0
+    n = ix.n_sets
+    qb = q[: int(q_off[nq])].contiguous()
+    ob = q_off[: nq + 1]
+    ids = torch.arange(n, dtype=torch.int32, device=q.device).repeat(nq, 1)
+    ix.hausdorff_lowp(qb[: int(ob[1])].contiguous(), ob[:2], ids[:1], "bf16")   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h2 = ix.hausdorff_lowp(qb, ob, ids, "bf16")
+    top = torch.topk(h2, k, dim=1, largest=False, sorted=True).indices
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    top = top.cpu().numpy()
+    recall = float(np.mean([len(set(top[i].tolist()) & set(truth[i].tolist())) / k for i in range(nq)]))
+    qsz = np.diff(ob).astype(np.float64)
+    flops = float((2.0 * qsz * n_vec * ix.dim_padded).sum())
+    del h2, ids
+    ix.__dict__.get("_lowp", {}).pop("bf16", None)
+    torch.cuda.empty_cache()
+    return {"qps": nq / el, "queries": nq, "recall_at_10": recall, "kernel": "k_haus_lp<bf16> over every set + topk",
+            "attach_s": attach_s, "copy_bytes": nbytes,
+            "roofline": {"bound": "mfma", "achieved": flops / el / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": flops / el / 1e12 / 2500.0,
+                         "algorithmic": f"{flops:.4g} bf16 flops (2 m_q N dp) over {nq} queries"}}
+
+
+def stage_rooflines(per_step, work, w, n_q, NQ, ix):
+    """HBM and ALU figures of the filter and the query encode beside the
+    re-rank's: the filter streams the position-major bitmap planes of every
+    set once per step (L x ld / 8 bytes) and does 2 int32 ops per query row
+    and 32-set word; the encode reads 2 dp bytes and writes L / 8 per query
+    vector and does L s adds and about 30 L compares of its threshold search."""
+    L, s = w["code_bits"], w["fan_in"]
+    out = {}
+    if per_step.get("filter"):
+        t = per_step["filter"] / 1e3
+        words = -(-w["n_sets"] // 32)
+        ops = work["sketch_rows"] * words * 2
+        byts = L * ix.ld / 8 + 2 * ix.ld
+        out["filter"] = {"kernel": "k_filter_sliced", "alu_achieved_tops": ops / t / 1e12,
+                         "alu_frac": ops / t / 1e12 / ALU_PEAK_TOPS, "hbm_gbs": byts / t / 1e9,
+                         "hbm_frac": byts / t / 1e9 / HBM_PEAK_GBS,
+                         "note": (f"{ops:.4g} int32 ops ({work['sketch_rows']:.4g} query rows x {words} words x 2) "
+                                  f"and {byts:.4g} bytes of bitmap planes per step; the kernel is bound by VALU "
+                                  f"issue, not HBM")}
+    if per_step.get("encode"):
+        t = per_step["encode"] / 1e3
+        byts = NQ * (2 * ix.dim_padded + L / 8)
+        ops = NQ * (L * s + 30 * L)
+        out["encode"] = {"kernel": "k_encode_vectors", "hbm_gbs": byts / t / 1e9, "hbm_frac": byts / t / 1e9 / HBM_PEAK_GBS,
+                         "alu_achieved_tops": ops / t / 1e12, "alu_frac": ops / t / 1e12 / ALU_PEAK_TOPS,
+                         "note": f"{NQ} query vectors: {byts:.4g} bytes and about {ops:.4g} int32 ops per step"}
+    return out
+
+
+def operating_points(ix, q, q_off, k, truth, nb, args, w):
+    """Throughput and recall@10 (first nb queries, against the exact brute
+    force) at each T of --op-sweep; the cheapest T reaching 0.95."""
+    import numpy as np
+    import torch
+
+    from paper_2412_03301_amd import bvs
+    n_q = len(q_off) - 1
+    NQ = int(q_off[-1])
+    rows = []
+    for T in [int(x) for x in args.op_sweep.split(",") if x]:
+        ix.set_search_params(3, 1, T)
+        ws = ix.search_workspace(n_q, NQ)
+        out = ix._outs(n_q, k)
+        ix.search(q, q_off, k, ws=ws, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ix.search(q, q_off, k, ws=ws, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ids = out[0].cpu().numpy().view(np.uint32)
+        rec = float(np.mean([len(set(ids[i].tolist()) & set(truth[i].tolist())) / k for i in range(nb)]))
+        # stage times of one more call (the dense fallback shows up as its own stage)
+        bvs.profile_enable(True)
+        ix.search(q, q_off, k, ws=ws, out=out)
+        torch.cuda.synchronize()
+        st = {nm: round(ms, 4) for nm, (ms, c) in bvs.profile_read().items() if c}
+        bvs.profile_enable(False)
+        rows.append({"top_t": T, "qps": n_q * args.steps / el, "recall_at_10": rec, "stages_ms": st})
+        log(f"T={T}: {rows[-1]['qps']:.0f} q/s, recall@10 {rec:.4f}; stages {st}")
+        del ws, out
+    ok = [r for r in rows if r["recall_at_10"] >= 0.95]
+    best = max(ok, key=lambda r: r["qps"]) if ok else None
+    return {"rows": rows, "recall_queries": nb, "cheapest_at_0.95": best}
 
 
 def brute_recall(ix, q, q_off, ids, k, nb):
@@ -321,9 +476,10 @@ def batched(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
-        qc = q[: int(q_off[args.cpu_sample_queries])].cpu().numpy()
-        cpu = cpu_baseline(cpu_db, db_offsets, qc, q_off, cfg, w["n_sets"], args.cpu_sample_sets,
-                           args.cpu_sample_queries)
+        ncq = min(args.cpu_sample_queries, len(q_off) - 1)
+        qc = q[: int(q_off[ncq])].cpu().numpy()
+        f2v = f2_vectors_per_query(ix, q[: int(q_off[ncq])].contiguous(), q_off[: ncq + 1], db_offsets)
+        cpu = cpu_baseline(cpu_db, db_offsets, qc, q_off, cfg, w["n_sets"], args.cpu_sample_sets, ncq, f2v)
     L = w["code_bits"]
     return {
         "metric": METRIC,
@@ -496,9 +652,10 @@ def precision(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
-        qc = q[: int(q_off[args.cpu_sample_queries])].cpu().numpy()
-        cpu = cpu_baseline(cpu_db, db_offsets, qc, q_off, cfg, w["n_sets"], args.cpu_sample_sets,
-                           args.cpu_sample_queries)
+        ncq = min(args.cpu_sample_queries, len(q_off) - 1)
+        qc = q[: int(q_off[ncq])].cpu().numpy()
+        f2v = f2_vectors_per_query(ix, q[: int(q_off[ncq])].contiguous(), q_off[: ncq + 1], db_offsets)
+        cpu = cpu_baseline(cpu_db, db_offsets, qc, q_off, cfg, w["n_sets"], args.cpu_sample_sets, ncq, f2v)
     L = w["code_bits"]
     return {
         "metric": METRIC,
@@ -802,6 +959,204 @@ def full_scan(args, w, ix, q, q_off, n_vec, build_s):
     }
 
 
+def metrics_bench(args, w, ix, q, q_off, n_vec, build_s):
+    """The cascade re-ranked by MeanMin (query to set) and by Min distance
+    (Sec. 3.2) beside Hausdorff: throughput of the whole search, recall@10
+    against the exact brute force by the same measure, and that brute
+    force's throughput."""
+    import numpy as np
+    import torch
+
+    from paper_2412_03301_amd import bvs
+
+    k = w["k"]
+    n_q = w["n_queries"]
+    NQ = int(q_off[-1])
+    nb = min(args.brute_queries, n_q)
+    ws = ix.search_workspace(n_q, NQ)
+    rows = {}
+    for metric in ("hausdorff", "meanmin", "min"):
+        out = ix._outs(n_q, k)
+        for i in range(args.warmup):
+            ix.search_metric(q, q_off, k, metric, ws=ws, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ix.search_metric(q, q_off, k, metric, ws=ws, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        bvs.profile_enable(True)
+        for i in range(args.steps):
+            ix.search_metric(q, q_off, k, metric, ws=ws, out=out)
+        torch.cuda.synchronize()
+        per_step = {nm: ms / max(1, c) for nm, (ms, c) in bvs.profile_read().items() if c}
+        bvs.profile_enable(False)
+        ids = out[0].cpu().numpy().view(np.uint32)
+        row = {"qps": n_q * args.steps / el, "ms_per_step": el * 1e3 / args.steps, "stages_ms_per_step": per_step}
+        if not args.no_brute:
+            qb, ob = q[: int(q_off[nb])].contiguous(), q_off[: nb + 1]
+            bws = ix.brute_workspace(nb, int(ob[-1]))
+            ix.bruteforce_metric(q[: int(q_off[2])].contiguous(), q_off[:3], k, metric)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bids = ix.bruteforce_metric(qb, ob, k, metric, ws=bws)[0]
+            torch.cuda.synchronize()
+            row["bruteforce_qps"] = nb / (time.perf_counter() - t0)
+            bids = bids.cpu().numpy().view(np.uint32)
+            row["recall_at_10"] = float(np.mean([len(set(ids[i].tolist()) & set(bids[i].tolist())) / k
+                                                 for i in range(nb)]))
+            row["speedup_vs_bruteforce"] = row["qps"] / row["bruteforce_qps"]
+            del bws
+        rows[metric] = row
+        log(f"{metric}: {row['qps']:.0f} q/s, recall@10 {row.get('recall_at_10')}, brute {row.get('bruteforce_qps')}")
+    mm = rows["meanmin"]
+    return {
+        "metric": "queries/sec of the cascade re-ranked by MeanMin on 1M sets (recall@10 against the MeanMin brute force)",
+        "value": mm["qps"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mm["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "exact int16 grid values as int8 hi/lo planes; MeanMin summed in f64, ranked in f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={w['dim']}, "
+                         f"{w['n_topics']} topics; FlyHash L={w['code_bits']}, s={w['fan_in']}, wta_k={w['wta_k']}; "
+                         f"A=3, M=1, T={w['top_t']}; {n_q} subset queries per step; top-{k}; re-rank by MeanMin, "
+                         f"Min and Hausdorff"),
+            "n_sets": w["n_sets"], "n_vectors": n_vec, "n_queries": n_q, "query_vectors": NQ,
+        },
+        "recall_at_10": mm.get("recall_at_10"),
+        "recall_sample_queries": None if args.no_brute else nb,
+        "by_metric": rows,
+        "index_build_s": build_s,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
+def trends_bench(args, w, dev):
+    """The paper's parameter study (Sec. 6.3) on the scale generator: recall
+    at 3, 5 and 10 against the exact brute force and throughput while
+    sweeping the winner-take-all count k_wta and the Bloom filter size L
+    (index rebuilt), the lists accessed A, the minimum count M and the
+    candidate count T (search-time parameters of the same index)."""
+    import numpy as np
+    import torch
+
+    from paper_2412_03301_amd import bvs, synth
+
+    t_start = time.perf_counter()
+    db = synth.make_database(w["n_sets"], w["size_lo"], w["size_hi"], w["dim"], w["n_topics"], seed=0, device=dev)
+    q, q_off, _ = synth.make_subset_queries(db, w["n_queries"], seed=1)
+    q = q.contiguous()
+    n_q = w["n_queries"]
+    NQ = int(q_off[-1])
+    k = 10
+
+    def build(L, wta):
+        p = bvs.Params.make(dim=w["dim"], code_bits=L, fan_in=w["fan_in"], wta_k=wta, access_lists=3, min_count=1,
+                            top_t=1000, seed=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ix = bvs.Index(p, db.vectors, db.offsets)
+        torch.cuda.synchronize()
+        return ix, time.perf_counter() - t0
+
+    ix, _ = build(4096, 64)
+    truth = ix.bruteforce(q, q_off, k)[0].cpu().numpy().view(np.uint32)
+    log(f"ground truth of {n_q} queries by brute force")
+
+    def measure(ix, A, M, T, label, first_layer="bitmaps"):
+        ix.set_search_params(A, M, T)
+        ix.set_first_layer(first_layer)
+        ws = ix.search_workspace(n_q, NQ)
+        out = ix._outs(n_q, k)
+        ix.search(q, q_off, k, ws=ws, out=out)
+        torch.cuda.synchronize()
+        bvs.profile_enable(True)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ix.search(q, q_off, k, ws=ws, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = {nm: ms / max(1, c) for nm, (ms, c) in bvs.profile_read().items() if c}
+        bvs.profile_enable(False)
+        ids = out[0].cpu().numpy().view(np.uint32)
+        rec = {f"recall_at_{r}": float(np.mean([len(set(ids[i, :r].tolist()) & set(truth[i, :r].tolist())) / r
+                                                for i in range(n_q)])) for r in (3, 5, 10)}
+        f1 = None
+        _, _, cnt = ix.candidates(q[: int(q_off[8])].contiguous(), q_off[:9])
+        ix.set_first_layer("bitmaps")
+        row = {"label": label, "A": A, "M": M, "T": T, "first_layer": first_layer, "qps": n_q * args.steps / el, **rec,
+               "first_layer_ms": st.get("cutoff", 0.0) + st.get("filter", 0.0) + st.get("select", 0.0)
+               + st.get("fallback", 0.0), "rerank_ms": st.get("rerank"),
+               "f2_count_mean_first8": float(cnt.float().mean().item())}
+        del ws, out, f1
+        log(f"{label} A={A} M={M} T={T} {first_layer}: {row['qps']:.0f} q/s, recall@3/5/10 {rec['recall_at_3']:.3f} "
+            f"{rec['recall_at_5']:.3f} {rec['recall_at_10']:.3f}")
+        return row
+
+    rows = []
+    for L in (1024, 2048, 4096):
+        for wta in (16, 32, 48, 64):
+            del ix
+            torch.cuda.empty_cache()
+            ix, bs = build(L, wta)
+            r = measure(ix, 3, 1, 1000, f"L={L} k_wta={wta}")
+            r.update(L=L, k_wta=wta, build_s=bs)
+            rows.append(r)
+            if wta == 64 and L in (1024, 4096):
+                for A in (1, 2):
+                    r = measure(ix, A, 1, 1000, f"L={L} k_wta=64")
+                    r.update(L=L, k_wta=64)
+                    rows.append(r)
+                r = measure(ix, 3, 2, 1000, f"L={L} k_wta=64")
+                r.update(L=L, k_wta=64)
+                rows.append(r)
+                for T in (200, 500, 2000, 4000):
+                    r = measure(ix, 3, 1, T, f"L={L} k_wta=64")
+                    r.update(L=L, k_wta=64)
+                    rows.append(r)
+                # the first layer from inverted lists (Def. 9, Alg. 4) against bitmaps / count columns
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lb = ix.attach_lists()
+                torch.cuda.synchronize()
+                attach_s = time.perf_counter() - t0
+                log(f"L={L}: inverted lists {lb / 2**30:.2f} GiB built in {attach_s:.2f} s")
+                for A, M in ((3, 1), (3, 2), (1, 1), (1, 2), (1, 3)):
+                    for fl in (("bitmaps", "lists") if (A, M) in ((1, 2), (1, 3)) else ("lists",)):
+                        r = measure(ix, A, M, 1000, f"L={L} k_wta=64", first_layer=fl)
+                        r.update(L=L, k_wta=64, lists_bytes=lb, lists_build_s=attach_s)
+                        rows.append(r)
+    return {
+        "metric": "recall@3/5/10 and queries/sec across the parameter study (Sec. 6.3) on 1M sets",
+        "value": None,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "exact int16 grid values as int8 hi/lo planes",
+        "data": "synthetic",
+        "config": {"workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={w['dim']}, "
+                                f"{w['n_topics']} topics; s={w['fan_in']}; {n_q} subset queries; recall against "
+                                f"the exact brute force"),
+                   "n_sets": w["n_sets"], "n_queries": n_q},
+        "rows": rows,
+        "total_s": time.perf_counter() - t_start,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -833,6 +1188,9 @@ def main():
 
     if args.workload == "learned":
         print(json.dumps(learned_bench(args, w, cfg, dev)), flush=True)
+        return
+    if args.workload == "trends":
+        print(json.dumps(trends_bench(args, w, dev)), flush=True)
         return
 
     log(f"generating {w['n_sets']} sets (d={w['dim']}) on the GPU")
@@ -875,6 +1233,9 @@ def main():
     if args.workload == "full":
         print(json.dumps(full_scan(args, w, ix, q, q_off, n_vec, build_s)), flush=True)
         return
+    if args.workload == "metrics":
+        print(json.dumps(metrics_bench(args, w, ix, q, q_off, n_vec, build_s)), flush=True)
+        return
 
     n_q = w["n_queries"]
     k = w["k"]
@@ -916,6 +1277,8 @@ def main():
     qps = n_q * args.steps / elapsed_s
     ids = out[0].cpu().numpy().view(np.uint32)
 
+    f2v_all = f2_vectors_per_query(ix, q, q_off, db.offsets)
+    f2_vectors = float(f2v_all.sum())
     f2_ids, _, f2_cnt = ix.candidates(q, q_off)
     f1_note = float(f2_cnt.float().mean().item())
 
@@ -924,27 +1287,63 @@ def main():
     _, _, pos = ix.query_sketch(q[: int(q_off[16])].contiguous(), q_off[:17])
     f1_frac = float(np.mean([((cnt_view[pos[i].long()] > 0).any(0)[: w["n_sets"]]).float().mean().item()
                              for i in range(16)]))
-    log(f"mean first-layer fraction {f1_frac:.4f}")
+    log(f"mean first-layer fraction {f1_frac:.4f}; F2 holds {f2_vectors / n_q:.1f} vectors per query")
 
-    recall = None
-    brute_qps = None
+    recall = brute_qps = truth = brute = None
+    nb = min(args.brute_queries, n_q)
     if not args.no_brute:
-        nb = min(args.brute_queries, n_q)
         recall, brute_qps = brute_recall(ix, q, q_off, ids, k, nb)
+        truth = ix.bruteforce(q[: int(q_off[nb])].contiguous(), q_off[: nb + 1], k)[0].cpu().numpy().view(np.uint32)
         log(f"brute force on {nb} queries: {brute_qps:.1f} q/s; recall@10 {recall:.4f}")
+        # exact brute force: 2 m_q N dp multiply-adds per query, each as four
+        # int8 matrix-core products (hi/lo split)
+        qsz = np.diff(q_off[: nb + 1]).astype(np.float64)
+        ops = float((2.0 * qsz * n_vec * ix.dim_padded * 4).sum())
+        t_b = nb / brute_qps
+        brute = {"qps": brute_qps, "queries": nb, "kernel": "k_haus_all",
+                 "roofline": {"bound": "mfma", "achieved": ops / t_b / 1e12, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                              "frac": ops / t_b / 1e12 / INT8_PEAK_TOPS,
+                              "algorithmic": f"{ops:.4g} int8 ops (2 m_q N dp x 4 products) over {nb} queries"}}
+        if args.bf16_brute:
+            brute["bf16"] = bf16_bruteforce(ix, q, q_off, k, min(args.bf16_brute, nb), truth, n_vec)
+            log(f"bf16 brute force: {brute['bf16']['qps']:.1f} q/s, recall@10 {brute['bf16']['recall_at_10']:.4f}")
 
     per_step = {name: ms / max(1, calls) for name, (ms, calls) in stages.items() if calls}
     work = {k2: v / args.steps for k2, v in counters.items()}
     L = w["code_bits"]
     work["sketch_rows"] = sketch_rows(ix, q, q_off)
-    roof, rerank_roof = rooflines(per_step, work, L, ix.dim_padded, "k_haus_cand", "k_haus.hip", w["n_sets"])
+    work["f2_vectors"] = f2_vectors
+    _, rerank_roof = rooflines(per_step, work, L, ix.dim_padded, "k_haus_cand", "k_haus.hip", w["n_sets"])
+    # the re-rank against its algorithmic bytes: every vector of every F2
+    # set, d int16 elements
+    alg_bytes = f2_vectors * w["dim"] * 2
+    rr_s = per_step["rerank"] / 1e3
+    roof = {"bound": "hbm", "achieved": alg_bytes / rr_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": alg_bytes / rr_s / 1e9 / HBM_PEAK_GBS,
+            "kernel": "k_haus_screen + k_haus_cand (re-rank stage)",
+            "algorithmic": (f"{alg_bytes:.4g} bytes per step: the {f2_vectors:.4g} vectors of all F2 sets "
+                            f"({f2_vectors / n_q:.1f} per query) x d = {w['dim']} int16 elements"),
+            "post_pruning": {"bytes": rerank_roof["achieved_gbs"] * rr_s * 1e9,
+                             "achieved": rerank_roof["achieved_gbs"],
+                             "frac": rerank_roof["achieved_gbs"] / HBM_PEAK_GBS,
+                             "note": "bytes the kernels read after abandoning and screening: vectors read in full "
+                                     "x (2 dp + 4) + first-tile rows screened x (dp + 8)"},
+            "traffic": traffic_from_profiles(os.path.join(ROOT, "paper_2412_03301_amd", "csrc", "k_haus.hip"),
+                                             "k_haus_cand")}
+    other_roofs = stage_rooflines(per_step, work, w, n_q, NQ, ix)
+
+    sweep = None
+    if args.op_sweep and truth is not None:
+        sweep = operating_points(ix, q, q_off, k, truth, nb, args, w)
+        ix.set_search_params(3, 1, w["top_t"])
 
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
-        qc = q[: int(q_off[args.cpu_sample_queries])].cpu().numpy()
-        cpu = cpu_baseline(cpu_db, db.offsets, qc, q_off, cfg, w["n_sets"], args.cpu_sample_sets,
-                           args.cpu_sample_queries)
+        ncq = min(args.cpu_sample_queries, len(q_off) - 1)
+        qc = q[: int(q_off[ncq])].cpu().numpy()
+        cpu = cpu_baseline(cpu_db, db.offsets, qc, q_off, cfg, w["n_sets"], args.cpu_sample_sets, ncq,
+                           f2v_all[:ncq])
 
     if args.copy_probe_mb:
         a = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
@@ -963,7 +1362,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "exact int16 grid values as int8 hi/lo planes (4 int8 MFMA products, int32 accumulation)",
         "data": "synthetic",
         "config": {
             "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={w['dim']}, "
@@ -972,13 +1371,17 @@ def main():
             "n_sets": w["n_sets"], "n_vectors": n_vec, "n_queries": n_q, "query_vectors": NQ,
         },
         "recall_at_10": recall,
-        "recall_sample_queries": None if args.no_brute else min(args.brute_queries, n_q),
+        "recall_sample_queries": None if args.no_brute else nb,
         "bruteforce_qps": brute_qps,
         "speedup_vs_bruteforce": (qps / brute_qps) if brute_qps else None,
+        "operating_point": sweep,
+        "bruteforce": brute,
         "stages_ms_per_step": per_step,
+        "stage_rooflines": other_roofs,
         "work_per_step": work,
         "rerank": rerank_roof,
         "mean_f2_size": f1_note,
+        "mean_f2_vectors": f2_vectors / n_q,
         "mean_f1_fraction": f1_frac,
         "index_build_s": build_s,
         "roofline": roof,

@@ -322,6 +322,38 @@ bvs_status bvs_search_full(const bvs_index* ix, const float* d_q,
                            void* stream);
 
 /* ------------------------------------------------------------------------
+ * Inverted lists (Def. 9, Alg. 4) as the first filter layer.  By default the
+ * first layer is read from position-major bitmaps (M = 1) or count columns
+ * (M >= 2) of every set; with lists attached and BVS_FIRST_LAYER_LISTS
+ * chosen, it is the union over the query's A positions of the prefixes of
+ * count >= M of the inverted lists, which reads only those entries (the
+ * difference matters when A times the list length is far below n).  Both
+ * give the same F1 and therefore the same results.  List p holds the sets
+ * with C^(j)[p] >= 1 ordered by decreasing count (equal counts in no
+ * particular order, as in Alg. 4):
+ *   cum   uint32 [L][257]   cum[p][c] = entries of list p with count >= c
+ *   start uint64 [L + 1]    list p is ids[start[p] .. start[p + 1])
+ *   ids   uint32 [nnz]      set ids; nnz = sum over sets of |B|
+ * bvs_lists_bytes runs the counting pass (workspace of
+ * bvs_lists_workspace_bytes; synchronises) and returns the device bytes of
+ * the lists; bvs_lists_attach builds them into caller memory (which must
+ * outlive their use) and synchronises.  bvs_index_set_first_layer selects
+ * the source (BVS_ESTATE for lists when none are attached; with M = 0 every
+ * set is a member and the lists are not read); like
+ * bvs_index_set_search_params it must not overlap other calls on the index,
+ * and workspaces must be sized again (lists mode adds n_q * ld / 8 bytes). */
+#define BVS_FIRST_LAYER_BITMAPS 0
+#define BVS_FIRST_LAYER_LISTS 1
+bvs_status bvs_lists_workspace_bytes(const bvs_index* ix, uint64_t* out_bytes);
+bvs_status bvs_lists_bytes(const bvs_index* ix, void* d_workspace, uint64_t workspace_bytes,
+                           void* stream, uint64_t* out_bytes);
+bvs_status bvs_lists_attach(bvs_index* ix, void* d_mem, uint64_t bytes,
+                            void* d_workspace, uint64_t workspace_bytes, void* stream);
+bvs_status bvs_lists_views(const bvs_index* ix, const uint32_t** d_cum,
+                           const uint64_t** d_start, const uint32_t** d_ids, uint64_t* nnz);
+bvs_status bvs_index_set_first_layer(bvs_index* ix, int mode);
+
+/* ------------------------------------------------------------------------
  * Batched search: many query sets of uneven size through the whole cascade
  * (Alg. 6) with no host round trip.  The exact re-rank of every query runs
  * in ONE persistent launch: resident workgroups take (query, 64-candidate
@@ -479,7 +511,9 @@ bvs_status bvs_hausdorff_lowp(const bvs_index* ix, int fmt, const float* d_q,
  * (the OR of Def. 10); soft Hamming h(A, B) = sum S_A + S_B - 2 S_A S_B; loss
  * = mean over triplets of max(0, margin + h(q, p) - h(q, n)).  Adam (beta1
  * 0.9, beta2 0.999, eps 1e-8) on the float32 weights, batches of
- * batch_triplets triplets in a splitmix64(seed) shuffle per epoch.
+ * batch_triplets triplets; epoch e visits them in a Fisher-Yates shuffle of
+ * the identity driven by splitmix64 seeded with seed ^ (e + 1) *
+ * 0xD1B54A32D192ED03.
  */
 typedef struct bvs_train_config {
   uint32_t dim, hidden, code_bits, wta_k;
@@ -529,9 +563,32 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
                                 float* d_weights, void* d_workspace, uint64_t workspace_bytes,
                                 float* h_epoch_loss, void* stream);
 
+/* Checkpoint and resume of training.  A training state (device memory of
+ * bvs_train_state_bytes, caller owned) holds Adam's first and second moments
+ * (float32, packed like the weights) and the counts of Adam steps and of
+ * epochs done; bvs_train_state_init zeroes it (synchronises).
+ * bvs_train_projection_resume trains c->epochs more epochs continuing from the
+ * state, which it updates in place: saving the weights and the state after a
+ * call and resuming from copies of them later gives the training of one
+ * longer call (the same batches in the same order and the same Adam steps;
+ * the gradients' floating-point sums are accumulated in no fixed order, so
+ * equal up to rounding). */
+bvs_status bvs_train_state_bytes(const bvs_train_config* c, uint64_t* out_bytes);
+bvs_status bvs_train_state_init(const bvs_train_config* c, void* d_state, void* stream);
+bvs_status bvs_train_projection_resume(const bvs_train_config* c, const float* d_vectors,
+                                       const uint64_t* h_offsets, uint64_t n_sets,
+                                       const uint32_t* h_triplets, uint64_t n_triplets,
+                                       float* d_weights, void* d_state, void* d_workspace,
+                                       uint64_t workspace_bytes, float* h_epoch_loss, void* stream);
+
 /* Stage timing.  When enabled, the library records a pair of HIP events on
  * the call's stream around every stage it launches and, after the call's
  * final synchronisation, adds the elapsed time to a process-wide table.
+ * Every stage also runs inside a roctx range named after it (visible to a
+ * profiler's marker trace).  Test hook: when the environment variable
+ * BVS_TEST_FAIL names a stage (e.g. "rerank"), every call reaching that
+ * stage returns BVS_EDEVICE without launching it; the index stays valid and
+ * the next call without the variable succeeds.
  * Stages: 0 convert, 1 encode (query vectors), 2 query sketch, 3 cutoff
  * (first-layer bitmaps, sampled scores and the per-query score cutoff),
  * 4 filter (member-only scoring with bounded append), 5 select (top-T of the
@@ -541,7 +598,8 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
  * candidates or overflowed its buffer), 10 approximate re-rank of the
  * precision form (encoding of the queries, approximate values, selection
  * of the candidates to re-check), 11 exact re-check of the precision form,
- * 12 full scan (query tables and the Hamming-Hausdorff score of every set).
+ * 12 full scan (query tables and the Hamming-Hausdorff score of every set),
+ * 13 lists (first-layer membership gathered from the inverted lists).
  * Work counters (summed over calls): 0 first-layer member pairs scored by
  * the filter stage, 1 database vectors read in full (both planes) by the
  * re-rank stage, 2 re-rank candidates abandoned early (screened ones
@@ -555,7 +613,7 @@ bvs_status bvs_train_projection(const bvs_train_config* c, const float* d_vector
  * (their atomics slow the counted kernels somewhat), 0 turns both off. */
 #define BVS_PROFILE_TIMING 1
 #define BVS_PROFILE_COUNTERS 2
-#define BVS_N_STAGES 13
+#define BVS_N_STAGES 14
 #define BVS_N_COUNTERS 7
 typedef struct bvs_stage_times {
   double ms[BVS_N_STAGES];

@@ -34,12 +34,15 @@ EXPORTED = [
     "bvs_train_gradients", "bvs_train_projection", "bvs_search_noalloc_max_bytes", "bvs_search_noalloc",
     "bvs_search_metric", "bvs_bruteforce_metric", "bvs_codes_bytes", "bvs_codes_attach_workspace_bytes",
     "bvs_codes_attach", "bvs_search_full_workspace_bytes", "bvs_full_scores", "bvs_search_full_candidates",
-    "bvs_search_full", "bvs_index_set_search_params",
+    "bvs_search_full", "bvs_index_set_search_params", "bvs_lists_workspace_bytes", "bvs_lists_bytes",
+    "bvs_lists_attach", "bvs_lists_views", "bvs_index_set_first_layer", "bvs_train_state_bytes",
+    "bvs_train_state_init", "bvs_train_projection_resume",
 ]
+FIRST_LAYER = {"bitmaps": 0, "lists": 1}
 METRIC = {"hausdorff": 0, "meanmin": 1, "min": 2}
 LOWP = {"bf16": 1, "fp8": 2}
 TUNE_MAX = 16
-N_STAGES = 13
+N_STAGES = 14
 N_COUNTERS = 7
 COUNTER_NAMES = ("filter_pairs", "rerank_vectors", "rerank_abandoned", "rerank_candidates",
                  "rerank_screen_vectors", "rerank_screened", "lowp_vectors")
@@ -126,6 +129,11 @@ def lib():
             "bvs_bruteforce_metric": (C.c_int, [P, C.c_int, P, P, U32, U32, P, U64, P, P, P, P]),
             "bvs_search_noalloc": (C.c_int, [P, P, P, U32, U32, P, P, P, P]),
             "bvs_index_set_search_params": (C.c_int, [P, U32, U32, U32]),
+            "bvs_lists_workspace_bytes": (C.c_int, [P, PU64]),
+            "bvs_lists_bytes": (C.c_int, [P, P, U64, P, PU64]),
+            "bvs_lists_attach": (C.c_int, [P, P, U64, P, U64, P]),
+            "bvs_lists_views": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), PU64]),
+            "bvs_index_set_first_layer": (C.c_int, [P, C.c_int]),
             "bvs_codes_bytes": (C.c_int, [P, PU64]),
             "bvs_codes_attach_workspace_bytes": (C.c_int, [P, PU64]),
             "bvs_codes_attach": (C.c_int, [P, P, U64, P, U64, P]),
@@ -160,6 +168,9 @@ def lib():
             "bvs_train_workspace_bytes": (C.c_int, [P, U64, PU64]),
             "bvs_train_gradients": (C.c_int, [P, P, P, U64, P, U32, P, P, C.POINTER(C.c_float), P, U64, P]),
             "bvs_train_projection": (C.c_int, [P, P, P, U64, P, U64, P, P, U64, P, P]),
+            "bvs_train_state_bytes": (C.c_int, [P, PU64]),
+            "bvs_train_state_init": (C.c_int, [P, P, P]),
+            "bvs_train_projection_resume": (C.c_int, [P, P, P, U64, P, U64, P, P, P, U64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -374,6 +385,37 @@ class Index:
         """A, M and T of later searches (no rebuild; workspaces must be sized again)."""
         check(lib().bvs_index_set_search_params(self._h, access_lists, min_count, top_t))
         self.params.access_lists, self.params.min_count, self.params.top_t = access_lists, min_count, top_t
+
+    # -- inverted lists (Def. 9, Alg. 4)
+    def attach_lists(self, stream=None) -> int:
+        """Build the inverted lists of the count Bloom filters into new device memory."""
+        wb = _bytes(lib().bvs_lists_workspace_bytes, self._h)
+        ws = _workspace(wb, self.device)
+        out = C.c_uint64(0)
+        check(lib().bvs_lists_bytes(self._h, _ptr(ws), ws.numel(), _stream(stream), C.byref(out)))
+        nbytes = int(out.value)
+        mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        check(lib().bvs_lists_attach(self._h, _ptr(mem), nbytes, _ptr(ws), ws.numel(), _stream(stream)))
+        self._lists = mem
+        return nbytes
+
+    def lists_views(self):
+        """(cum int32 [L, 257], start int64 [L + 1], ids int32 [nnz]) views of the attached lists."""
+        a, b, c, n = C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_uint64(0)
+        check(lib().bvs_lists_views(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(n)))
+        base = self._lists.data_ptr()
+        L = self.params.code_bits
+        nnz = int(n.value)
+
+        def view(ptr, count, dtype, size):
+            off = ptr - base
+            return self._lists[off: off + count * size].view(dtype)
+        return (view(a.value, L * 257, torch.int32, 4).view(L, 257), view(b.value, L + 1, torch.int64, 8),
+                view(c.value, nnz, torch.int32, 4))
+
+    def set_first_layer(self, mode: str):
+        """"bitmaps" (default) or "lists" (needs attach_lists)."""
+        check(lib().bvs_index_set_first_layer(self._h, FIRST_LAYER[mode]))
 
     # -- full scan (Alg. 2)
     def attach_codes(self, stream=None) -> int:
@@ -630,6 +672,23 @@ class Trainer:
                                         trip.ctypes.data_as(C.c_void_p), len(trip), _ptr(weights), _ptr(grads),
                                         C.byref(loss), _ptr(self.ws), self.ws.numel(), _stream(None)))
         return float(loss.value), grads
+
+    def new_state(self) -> torch.Tensor:
+        """A zeroed training state (Adam moments, step and epoch counts)."""
+        st = torch.empty(_bytes(lib().bvs_train_state_bytes, C.byref(self.cfg)), dtype=torch.uint8,
+                         device=self.vectors.device)
+        check(lib().bvs_train_state_init(C.byref(self.cfg), _ptr(st), _stream(None)))
+        return st
+
+    def train_resume(self, weights: torch.Tensor, triplets: np.ndarray, state: torch.Tensor):
+        """cfg.epochs more epochs from `state` (updated in place)."""
+        trip = np.ascontiguousarray(np.asarray(triplets, np.uint32))
+        losses = (C.c_float * max(1, self.cfg.epochs))()
+        check(lib().bvs_train_projection_resume(C.byref(self.cfg), _ptr(self.vectors), _u64p(self.off),
+                                                len(self.off) - 1, trip.ctypes.data_as(C.c_void_p), len(trip),
+                                                _ptr(weights), _ptr(state), _ptr(self.ws), self.ws.numel(), losses,
+                                                _stream(None)))
+        return [float(x) for x in losses[: self.cfg.epochs]]
 
     def train(self, weights: torch.Tensor, triplets: np.ndarray):
         trip = np.ascontiguousarray(np.asarray(triplets, np.uint32))

@@ -22,7 +22,7 @@ OBJ = os.path.join(HERE, "_obj")
 OUT = os.path.join(PKG, "libbvs.so")
 
 SOURCES = ["capi.cpp", "k_encode.hip", "k_filter.hip", "k_sliced.hip", "k_haus.hip", "k_batch.hip", "k_lowp.hip", "k_learn.hip",
-           "k_full.hip"]
+           "k_full.hip", "k_lists.hip"]
 HEADERS = ["device.h", "launch.h", "haus_core.h", os.path.join(INCLUDE, "bvs.h")]
 ARCH = "gfx950"
 
@@ -71,7 +71,8 @@ def build(jobs: int = 4, verbose: bool = False, incremental: bool = False) -> st
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(one, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-L/opt/rocm/lib",
+           "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -16,6 +16,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "bvs.h"
 #include "device.h"
 #include "launch.h"
@@ -170,7 +172,7 @@ bvs_status read_status(uint32_t* d_status, hipStream_t st, const char* what) {
 const char* const kStageNames[BVS_N_STAGES] = {"convert",  "encode",   "query_sketch", "cutoff",
                                                "filter",   "select",   "rerank",       "topk",
                                                "bruteforce", "fallback", "approx",     "recheck",
-                                               "fullscan"};
+                                               "fullscan", "lists"};
 
 struct ProfTable {
   std::mutex mu;
@@ -254,16 +256,31 @@ struct CallProf {
   ~CallProf() { release(); }
 };
 
+// Test hook: with BVS_TEST_FAIL set to a stage name, launching that stage
+// reports a launch failure without launching anything, so that the error
+// path (BVS_EDEVICE, the index left valid for the next call) can be tested
+// without a faulting kernel.
+bool test_fail_at(int stage) {
+  const char* e = std::getenv("BVS_TEST_FAIL");
+  return e && *e && std::strcmp(e, kStageNames[stage]) == 0;
+}
+
+// One stage of a call: the stage's launches between its HIP events (when
+// timing) and inside a roctx range named after the stage (seen by a
+// profiler's marker trace).
 template <class F>
 hipError_t staged(CallProf& p, int stage, F&& f) {
+  if (test_fail_at(stage)) return hipErrorLaunchFailure;
   p.begin(stage);
+  roctxRangePushA(kStageNames[stage]);
   const hipError_t e = f();
+  roctxRangePop();
   p.end();
   return e;
 }
 
 enum { S_CONVERT = 0, S_ENCODE, S_QSKETCH, S_CUTOFF, S_FILTER, S_SELECT, S_RERANK, S_TOPK, S_BRUTE, S_FALLBACK,
-       S_APPROX, S_RECHECK, S_FULLSCAN };
+       S_APPROX, S_RECHECK, S_FULLSCAN, S_LISTS };
 
 }  // namespace
 
@@ -296,6 +313,12 @@ struct bvs_index {
   uint16_t* fpos = nullptr;  // [N][KP] code positions of every vector
   uint32_t* forder = nullptr;  // [n] set ids by decreasing size (ties: lower id first)
   uint32_t fKP = 0;
+  // attached inverted lists (Def. 9, Alg. 4) and the first layer's source
+  uint32_t* lcum = nullptr;    // [L][257]
+  uint64_t* lstart = nullptr;  // [L + 1]
+  uint32_t* lids = nullptr;    // [nnz]
+  uint64_t lnnz = 0;
+  int first_layer = BVS_FIRST_LAYER_BITMAPS;
 };
 
 namespace {
@@ -357,6 +380,7 @@ struct QueryWs {
   uint32_t* sbits;        // [n_q]
   uint32_t* gsteps;       // [n_q rounded up to 32, / 16]
   uint32_t* any_long;     // [1]
+  uint64_t* member;       // [n_q][ld / 64] first layer from the inverted lists (lists mode only)
   uint32_t* f2_ids;
   uint16_t* f2_scores;
   uint32_t* f2_count;
@@ -375,6 +399,7 @@ struct QueryWs {
 constexpr uint32_t kMaxK = 64;
 constexpr uint32_t kSampleBlocks = 64;   // blocks of 256 sets scored to pick the cutoff
 constexpr uint32_t kCutoffAlpha = 3;     // the cutoff aims at about 3 T appended sets
+constexpr uint32_t kMinSampleRank = 24;  // ... from at least this many sampled members
 
 // Capacity of the append buffer per query: 8 T rounded up to a power of two,
 // within 4096..16384 (it is sorted in LDS).  BVS_APPEND_CAP overrides it
@@ -419,6 +444,12 @@ bool force_dense_select() {
   return e && std::strcmp(e, "dense") == 0;
 }
 
+// The first layer comes from the attached inverted lists (M >= 1 only: with
+// M = 0 every set is a member).
+bool lists_first_layer(const bvs_index* ix) {
+  return ix->first_layer == BVS_FIRST_LAYER_LISTS && ix->lids && ix->g.M >= 1;
+}
+
 void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, QueryWs* w) {
   const Geometry& g = ix->g;
   w->status = c.take<uint32_t>(4);
@@ -450,6 +481,7 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->sbits = c.take<uint32_t>(n_q);
   w->gsteps = c.take<uint32_t>(align_up(n_q, 32) / 16);
   w->any_long = c.take<uint32_t>(1);
+  w->member = lists_first_layer(ix) ? c.take<uint64_t>((uint64_t)n_q * (ix->ld / 64)) : nullptr;
   w->f2_ids = c.take<uint32_t>((uint64_t)n_q * g.T);
   w->f2_scores = c.take<uint16_t>((uint64_t)n_q * g.T);
   w->f2_count = c.take<uint32_t>(n_q);
@@ -573,6 +605,7 @@ FilterArgs filter_args(const bvs_index* ix, uint32_t n_q, const QueryWs& w) {
   a.any_long = w.any_long;
   a.fail = w.status + 1;   // raised when the dense path must answer
   a.stats = nullptr;   // set by the caller when profiling
+  a.member = w.member;
   return a;
 }
 
@@ -590,10 +623,16 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
     HIP_TRY(launch_fill_u32((uint32_t*)w.stats, 2ull * kStatSlots * kStatCounters, 0, st));
     a.stats = w.stats;
   }
+  if (w.member) {
+    // first layer from the inverted lists: membership bitmaps before scoring
+    HIP_TRY(staged(prof, S_LISTS, [&] {
+      return launch_list_gather(ix->lids, ix->lstart, ix->lcum, w.pos, g.A, g.M, n_q, ix->ld, w.member, ix->n_cu, st);
+    }));
+  }
   if (!force_dense_select()) {
     const uint32_t n_blocks = (uint32_t)(ix->ld / 256);
-    const bool sparse = use_sparse_filter(g.M);
-    const bool sliced = use_sliced_filter(g);
+    const bool sparse = w.member || use_sparse_filter(g.M);
+    const bool sliced = !w.member && use_sliced_filter(g);
     uint32_t* d_fail = w.status + 1;
     HIP_TRY(launch_fill_u32(w.cand_count, n_q, 0, st));
     HIP_TRY(launch_fill_u32(d_fail, 1, 0, st));
@@ -621,7 +660,13 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
       if (e != hipSuccess) return e;
       const uint64_t S = (uint64_t)nsb * 256;
       const uint64_t sampled = std::min<uint64_t>(S, ix->n);
-      const uint32_t r = (uint32_t)std::max<uint64_t>(1, (kCutoffAlpha * (uint64_t)g.T * sampled + ix->n - 1) / ix->n);
+      // the cutoff is the r-th smallest sampled score: r aims at about 3T
+      // appended sets, but at least kMinSampleRank sampled members (a rank of a
+      // few samples is too noisy to hold T sets reliably, and a miss costs the
+      // dense path), as long as the sets it admits fit half the buffer
+      const uint64_t r_aim = (kCutoffAlpha * (uint64_t)g.T * sampled + ix->n - 1) / ix->n;
+      const uint64_t r_fit = std::max<uint64_t>(1, (uint64_t)w.cap * sampled / (2 * ix->n));
+      const uint32_t r = (uint32_t)std::max<uint64_t>(1, std::max(r_aim, std::min<uint64_t>(kMinSampleRank, r_fit)));
       return launch_cutoff(w.sample, (uint32_t)S, g.L, r, n_q, w.cutoff, st);
     }));
     HIP_TRY(staged(prof, S_FILTER, [&]() -> hipError_t {
@@ -1775,6 +1820,12 @@ bvs_status train_batch(const bvs_train_config& t, const float* d_vectors, const 
   return BVS_OK;
 }
 
+// Offset of the header (step and epoch counts, uint64 each) in a training
+// state: after Adam's two moment arrays.
+uint64_t train_state_header(const bvs_train_config& t) {
+  return align_up(2 * mlp_floats(t.dim, t.hidden, t.code_bits) * 4, 256);
+}
+
 uint64_t train_capacity(const bvs_train_config& t, uint64_t ws_bytes) {
   // largest row capacity whose layout fits ws_bytes
   uint64_t lo = 0, hi = 1ull << 26;
@@ -1787,6 +1838,90 @@ uint64_t train_capacity(const bvs_train_config& t, uint64_t ws_bytes) {
     else hi = mid - 1;
   }
   return lo;
+}
+
+}  // namespace
+
+namespace {
+
+// Epochs of triplet training from the Adam state in d_state (moments, then the
+// step and epoch counts; updated in place), or from a fresh state in the
+// workspace when d_state is null.  Epoch e (counted over all calls on one
+// state) visits the triplets in the order of a Fisher-Yates shuffle of the
+// identity driven by splitmix64 from seed ^ (e + 1) * 0xD1B54A32D192ED03, so a
+// run split over several calls visits the same batches as one call.
+bvs_status train_impl(const bvs_train_config* t, const float* d_vectors, const uint64_t* h_offsets, uint64_t n_sets,
+                      const uint32_t* h_triplets, uint64_t n_triplets, float* d_weights, void* d_state, void* d_ws,
+                      uint64_t ws_bytes, float* h_epoch_loss, hipStream_t st) {
+  BVS_TRY(check_train_config(t));
+  if (!d_vectors || !d_weights || !h_triplets) return fail(BVS_EINVAL, "NULL argument");
+  if (n_triplets == 0) return fail(BVS_EINVAL, "no triplets");
+  uint32_t max_m = 0;
+  BVS_TRY(check_offsets(h_offsets, n_sets, 65535, "training", &max_m));
+  const uint64_t cap = train_capacity(*t, ws_bytes);
+  if (!d_ws || cap == 0) return fail(BVS_ENOSPC, "workspace too small");
+  Carver c(d_ws);
+  TrainWs w;
+  layout_train(c, *t, cap, &w);
+  const uint64_t nw = mlp_floats(t->dim, t->hidden, t->code_bits);
+  uint64_t hdr[2] = {0, 0};   // step, epoch
+  float* adam_m = w.adam_m;
+  float* adam_v = w.adam_v;
+  uint64_t* d_hdr = nullptr;
+  if (d_state) {
+    adam_m = (float*)d_state;
+    adam_v = adam_m + nw;
+    d_hdr = (uint64_t*)((uint8_t*)d_state + train_state_header(*t));
+    HIP_TRY(hipMemcpyAsync(hdr, d_hdr, sizeof hdr, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hdr[0] > 0xFFFFFFFFull) return fail(BVS_EINVAL, "training state holds step %llu", (unsigned long long)hdr[0]);
+  } else {
+    HIP_TRY(launch_fill_u32((uint32_t*)adam_m, nw, 0u, st));
+    HIP_TRY(launch_fill_u32((uint32_t*)adam_v, nw, 0u, st));
+  }
+  HIP_TRY(launch_f32_to_bf16(d_weights, nw, w.w16, st));
+  std::vector<uint64_t> order(n_triplets);
+  std::vector<uint32_t> batch;
+  std::vector<uint64_t> rows;
+  std::vector<uint32_t> roff, tl;
+  uint32_t step = (uint32_t)hdr[0];
+  for (uint32_t ep = 0; ep < t->epochs; ++ep) {
+    const uint64_t e_abs = hdr[1] + ep;
+    uint64_t rng = t->seed ^ ((e_abs + 1) * 0xD1B54A32D192ED03ull);
+    auto next = [&rng]() {
+      rng += 0x9E3779B97F4A7C15ull;
+      uint64_t z = rng;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      return z ^ (z >> 31);
+    };
+    for (uint64_t i = 0; i < n_triplets; ++i) order[i] = i;
+    for (uint64_t i = n_triplets - 1; i > 0; --i) std::swap(order[i], order[next() % (i + 1)]);
+    double ep_loss = 0.0;
+    uint64_t n_batches = 0;
+    for (uint64_t b0 = 0; b0 < n_triplets; b0 += t->batch_triplets) {
+      const uint32_t nt = (uint32_t)std::min<uint64_t>(t->batch_triplets, n_triplets - b0);
+      batch.resize(3ull * nt);
+      for (uint32_t i = 0; i < nt; ++i)
+        for (int k = 0; k < 3; ++k) batch[3ull * i + k] = h_triplets[3 * order[b0 + i] + k];
+      BVS_TRY(train_batch(*t, d_vectors, h_offsets, n_sets, batch.data(), nt, cap, w.w16, d_weights, w, st, rows,
+                          roff, tl));
+      HIP_TRY(launch_adam(d_weights, w.grad, adam_m, adam_v, nw, t->lr, 0.9f, 0.999f, 1e-8f, ++step, w.w16, st));
+      float l = 0.f;
+      HIP_TRY(hipMemcpyAsync(&l, w.loss, 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      ep_loss += l;
+      ++n_batches;
+    }
+    if (h_epoch_loss) h_epoch_loss[ep] = (float)(ep_loss / std::max<uint64_t>(1, n_batches));
+  }
+  if (d_hdr) {
+    hdr[0] = step;
+    hdr[1] += t->epochs;
+    HIP_TRY(hipMemcpyAsync(d_hdr, hdr, sizeof hdr, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return BVS_OK;
 }
 
 }  // namespace
@@ -1967,58 +2102,35 @@ bvs_status bvs_train_gradients(const bvs_train_config* t, const float* d_vectors
 bvs_status bvs_train_projection(const bvs_train_config* t, const float* d_vectors, const uint64_t* h_offsets,
                                 uint64_t n_sets, const uint32_t* h_triplets, uint64_t n_triplets, float* d_weights,
                                 void* d_ws, uint64_t ws_bytes, float* h_epoch_loss, void* stream) {
+  return train_impl(t, d_vectors, h_offsets, n_sets, h_triplets, n_triplets, d_weights, nullptr, d_ws, ws_bytes,
+                    h_epoch_loss, (hipStream_t)stream);
+}
+
+bvs_status bvs_train_state_bytes(const bvs_train_config* t, uint64_t* out) {
   BVS_TRY(check_train_config(t));
-  if (!d_vectors || !d_weights || !h_triplets) return fail(BVS_EINVAL, "NULL argument");
-  if (n_triplets == 0) return fail(BVS_EINVAL, "no triplets");
-  uint32_t max_m = 0;
-  BVS_TRY(check_offsets(h_offsets, n_sets, 65535, "training", &max_m));
-  const uint64_t cap = train_capacity(*t, ws_bytes);
-  if (!d_ws || cap == 0) return fail(BVS_ENOSPC, "workspace too small");
-  hipStream_t st = (hipStream_t)stream;
-  Carver c(d_ws);
-  TrainWs w;
-  layout_train(c, *t, cap, &w);
-  const uint64_t nw = mlp_floats(t->dim, t->hidden, t->code_bits);
-  HIP_TRY(launch_fill_u32((uint32_t*)w.adam_m, nw, 0u, st));
-  HIP_TRY(launch_fill_u32((uint32_t*)w.adam_v, nw, 0u, st));
-  HIP_TRY(launch_f32_to_bf16(d_weights, nw, w.w16, st));
-  // triplet order: a splitmix64-driven shuffle per epoch
-  std::vector<uint64_t> order(n_triplets);
-  for (uint64_t i = 0; i < n_triplets; ++i) order[i] = i;
-  uint64_t rng = t->seed;
-  auto next = [&rng]() {
-    rng += 0x9E3779B97F4A7C15ull;
-    uint64_t z = rng;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-  };
-  std::vector<uint32_t> batch;
-  std::vector<uint64_t> rows;
-  std::vector<uint32_t> roff, tl;
-  uint32_t step = 0;
-  for (uint32_t ep = 0; ep < t->epochs; ++ep) {
-    for (uint64_t i = n_triplets - 1; i > 0; --i) std::swap(order[i], order[next() % (i + 1)]);
-    double ep_loss = 0.0;
-    uint64_t n_batches = 0;
-    for (uint64_t b0 = 0; b0 < n_triplets; b0 += t->batch_triplets) {
-      const uint32_t nt = (uint32_t)std::min<uint64_t>(t->batch_triplets, n_triplets - b0);
-      batch.resize(3ull * nt);
-      for (uint32_t i = 0; i < nt; ++i)
-        for (int k = 0; k < 3; ++k) batch[3ull * i + k] = h_triplets[3 * order[b0 + i] + k];
-      BVS_TRY(train_batch(*t, d_vectors, h_offsets, n_sets, batch.data(), nt, cap, w.w16, d_weights, w, st, rows,
-                          roff, tl));
-      HIP_TRY(launch_adam(d_weights, w.grad, w.adam_m, w.adam_v, nw, t->lr, 0.9f, 0.999f, 1e-8f, ++step, w.w16,
-                          st));
-      float l = 0.f;
-      HIP_TRY(hipMemcpyAsync(&l, w.loss, 4, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      ep_loss += l;
-      ++n_batches;
-    }
-    if (h_epoch_loss) h_epoch_loss[ep] = (float)(ep_loss / std::max<uint64_t>(1, n_batches));
-  }
+  if (!out) return fail(BVS_EINVAL, "out is NULL");
+  *out = train_state_header(*t) + 256;
   return BVS_OK;
+}
+
+bvs_status bvs_train_state_init(const bvs_train_config* t, void* d_state, void* stream) {
+  BVS_TRY(check_train_config(t));
+  if (!d_state) return fail(BVS_EINVAL, "state is NULL");
+  uint64_t bytes = 0;
+  BVS_TRY(bvs_train_state_bytes(t, &bytes));
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_fill_u32((uint32_t*)d_state, bytes / 4, 0u, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return BVS_OK;
+}
+
+bvs_status bvs_train_projection_resume(const bvs_train_config* t, const float* d_vectors, const uint64_t* h_offsets,
+                                       uint64_t n_sets, const uint32_t* h_triplets, uint64_t n_triplets,
+                                       float* d_weights, void* d_state, void* d_ws, uint64_t ws_bytes,
+                                       float* h_epoch_loss, void* stream) {
+  if (!d_state) return fail(BVS_EINVAL, "state is NULL");
+  return train_impl(t, d_vectors, h_offsets, n_sets, h_triplets, n_triplets, d_weights, d_state, d_ws, ws_bytes,
+                    h_epoch_loss, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -2086,7 +2198,7 @@ bvs_status bvs_search_noalloc(const bvs_index* ix, const float* d_q, const uint6
 namespace {
 
 constexpr uint64_t kFullChunk = 1ull << 20;   // vectors encoded per attach step
-constexpr uint32_t kFullGroups = 4;           // query vectors up to 256, 64 per group
+constexpr uint32_t kPackCap = 2;              // groups of 64 slots a pack of several queries may fill
 
 uint32_t full_kp(const Geometry& g) { return (uint32_t)align_up(g.wta_k, 8); }
 
@@ -2097,22 +2209,57 @@ void layout_codes(Carver& c, const bvs_index* ix, uint16_t** pos, uint32_t** ord
 
 struct FullWs {
   QueryWs w;
-  uint64_t* table;   // [n_q][G][L]
-  uint32_t G;
+  uint4* packs;      // [n_q] {first query, queries, groups, 0}
+  uint64_t* table;   // [n_q][kPackGroups][L] (the first n_packs * GP * L used)
+  uint32_t n_packs, GP;
+  std::vector<uint32_t> h_packs;
 };
 
-uint32_t full_groups(uint64_t max_rows) {
-  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kFullGroups, (max_rows + 63) / 64));
+void layout_full(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, FullWs* f) {
+  layout_search(c, ix, n_q, NQ, &f->w);
+  f->packs = c.take<uint4>(n_q);
+  f->table = c.take<uint64_t>((uint64_t)n_q * kPackGroups * ix->g.L);
 }
 
-void layout_full(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, uint32_t G, FullWs* f) {
-  layout_search(c, ix, n_q, NQ, &f->w);
-  f->G = G;
-  f->table = c.take<uint64_t>((uint64_t)n_q * G * ix->g.L);
+// Runs of consecutive queries whose vectors fit kPackCap groups of 64 (at most
+// kPackQ queries); a query of more than 64 kPackCap vectors takes a pack of
+// its own with as many groups as it needs (at most kPackGroups: queries hold
+// at most 256 vectors).  GP = the launch's groups per pack (1, 2 or 4).
+void make_packs(const uint64_t* h_q_off, uint32_t n_q, FullWs* f) {
+  f->h_packs.clear();
+  uint32_t q0 = 0, nq = 0;
+  uint64_t total = 0;
+  uint32_t gmax = 1;
+  auto close = [&]() {
+    if (!nq) return;
+    const uint32_t groups = (uint32_t)((total + 63) / 64);
+    gmax = std::max(gmax, groups);
+    f->h_packs.insert(f->h_packs.end(), {q0, nq, groups, 0u});
+    nq = 0;
+    total = 0;
+  };
+  for (uint32_t q = 0; q < n_q; ++q) {
+    const uint64_t m = h_q_off[q + 1] - h_q_off[q];
+    if (nq && (nq == (uint32_t)kPackQ || total + m > 64ull * kPackCap)) close();
+    if (!nq) q0 = q;
+    ++nq;
+    total += m;
+    if (m > 64ull * kPackCap) close();
+  }
+  close();
+  f->n_packs = (uint32_t)(f->h_packs.size() / 4);
+  f->GP = gmax <= 1 ? 1 : gmax <= 2 ? 2 : 4;
 }
 
 bvs_status full_ready(const bvs_index* ix) {
   if (!ix->fpos) return fail(BVS_ESTATE, "no codes attached for the full scan (bvs_codes_attach)");
+  return BVS_OK;
+}
+
+// Upload the pack list (after prepare_queries, on the call's stream; the host
+// copy lives in FullWs until the call synchronises).
+bvs_status upload_packs(const FullWs& f, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(f.packs, f.h_packs.data(), f.h_packs.size() * 4, hipMemcpyHostToDevice, st));
   return BVS_OK;
 }
 
@@ -2122,15 +2269,16 @@ bvs_status full_filter(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Ful
   const Geometry& g = ix->g;
   const QueryWs& w = f.w;
   if (prof.count) HIP_TRY(launch_fill_u32((uint32_t*)w.stats, 2ull * kStatSlots * kStatCounters, 0, st));
+  BVS_TRY(upload_packs(f, st));
   HIP_TRY(staged(prof, S_ENCODE, [&] { return encode_planes(ix, w.qhi, w.qlo, NQ, w.codes, w.lx16, w.lh16, w.ly, st); }));
   HIP_TRY(staged(prof, S_FULLSCAN, [&]() -> hipError_t {
-    hipError_t e = launch_query_table(w.codes, w.qoff, n_q, g.L, g.R, f.G, f.table, st);
+    hipError_t e = launch_query_table(w.codes, w.qoff, f.packs, f.n_packs, g.L, g.R, f.GP, f.table, st);
     if (e != hipSuccess) return e;
     // sets past n (the padding of ld) stay excluded
     e = launch_fill_u32((uint32_t*)w.scores, (uint64_t)n_q * ix->ld / 2, 0xFFFFFFFFu, st);
     if (e != hipSuccess) return e;
-    return launch_full_scan(ix->fpos, ix->offsets, ix->forder, ix->n, g.wta_k, ix->fKP, g.L, f.table, w.qoff, n_q,
-                            f.G, w.scores, ix->ld, st);
+    return launch_full_scan(ix->fpos, ix->offsets, ix->forder, ix->n, g.wta_k, ix->fKP, g.L, f.table, w.qoff,
+                            f.packs, f.n_packs, f.GP, w.scores, ix->ld, st);
   }));
   HIP_TRY(staged(prof, S_SELECT, [&] {
     return launch_select(w.scores, ix->ld, g.L, g.T, n_q, w.sel, ids, scores, count, nullptr, st);
@@ -2148,9 +2296,11 @@ bvs_status full_begin(const bvs_index* ix, const float* d_q, const uint64_t* h_q
   BVS_TRY(bvs_search_full_workspace_bytes(ix, n_q, NQ, &need));
   BVS_TRY(need_ws(ws_bytes, need, d_ws));
   Carver c(d_ws);
-  layout_full(c, ix, n_q, NQ, full_groups(std::min<uint64_t>(NQ, 256)), f);
+  layout_full(c, ix, n_q, NQ, f);
+  make_packs(h_q_off, n_q, f);
   return BVS_OK;
 }
+
 
 }  // namespace
 
@@ -2231,7 +2381,7 @@ bvs_status bvs_search_full_workspace_bytes(const bvs_index* ix, uint32_t n_q, ui
   if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
   Carver c(nullptr);
   FullWs f;
-  layout_full(c, ix, n_q, n_q_vectors, full_groups(std::min<uint64_t>(n_q_vectors, 256)), &f);
+  layout_full(c, ix, n_q, n_q_vectors, &f);
   *out = align_up(c.off, 256);
   return BVS_OK;
 }
@@ -2248,13 +2398,14 @@ bvs_status bvs_full_scores(const bvs_index* ix, const float* d_q, const uint64_t
   BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, f.w, st, prof));
   HIP_TRY(staged(prof, S_ENCODE,
                  [&] { return encode_planes(ix, f.w.qhi, f.w.qlo, NQ, f.w.codes, f.w.lx16, f.w.lh16, f.w.ly, st); }));
+  BVS_TRY(upload_packs(f, st));
   HIP_TRY(staged(prof, S_FULLSCAN, [&]() -> hipError_t {
-    hipError_t e = launch_query_table(f.w.codes, f.w.qoff, n_q, ix->g.L, ix->g.R, f.G, f.table, st);
+    hipError_t e = launch_query_table(f.w.codes, f.w.qoff, f.packs, f.n_packs, ix->g.L, ix->g.R, f.GP, f.table, st);
     if (e != hipSuccess) return e;
     e = launch_fill_u32((uint32_t*)f.w.scores, (uint64_t)n_q * ix->ld / 2, 0xFFFFFFFFu, st);
     if (e != hipSuccess) return e;
     return launch_full_scan(ix->fpos, ix->offsets, ix->forder, ix->n, ix->g.wta_k, ix->fKP, ix->g.L, f.table,
-                            f.w.qoff, n_q, f.G, f.w.scores, ix->ld, st);
+                            f.w.qoff, f.packs, f.n_packs, f.GP, f.w.scores, ix->ld, st);
   }));
   for (uint32_t q = 0; q < n_q; ++q)
     HIP_TRY(hipMemcpyAsync(d_scores + (uint64_t)q * ix->n, f.w.scores + (uint64_t)q * ix->ld, ix->n * 2,
@@ -2304,6 +2455,129 @@ bvs_status bvs_search_full(const bvs_index* ix, const float* d_q, const uint64_t
   const bvs_status s = read_status(w.status, st, "queries");
   prof.finish(prof.count ? w.stats : nullptr);
   return s;
+}
+
+}  // extern "C"
+
+// ====================================================================== inverted lists (Def. 9, Alg. 4)
+namespace {
+
+struct ListWs {
+  uint32_t* hist;
+  uint32_t* cursor;
+  uint64_t* len;
+  uint32_t* cum;     // counting pass only
+  uint64_t* start;   // counting pass only
+};
+
+void layout_list_ws(Carver& c, const bvs_index* ix, ListWs* w) {
+  const uint32_t L = ix->g.L;
+  w->hist = c.take<uint32_t>((uint64_t)L * 256);
+  w->cursor = c.take<uint32_t>((uint64_t)L * 256);
+  w->len = c.take<uint64_t>(L);
+  w->cum = c.take<uint32_t>((uint64_t)L * 257);
+  w->start = c.take<uint64_t>(L + 1ull);
+}
+
+void layout_lists(Carver& c, const bvs_index* ix, uint64_t nnz, uint32_t** cum, uint64_t** start, uint32_t** ids) {
+  *cum = c.take<uint32_t>((uint64_t)ix->g.L * 257);
+  *start = c.take<uint64_t>(ix->g.L + 1ull);
+  *ids = c.take<uint32_t>(nnz);
+}
+
+}  // namespace
+
+extern "C" {
+
+bvs_status bvs_lists_workspace_bytes(const bvs_index* ix, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  Carver c(nullptr);
+  ListWs w;
+  layout_list_ws(c, ix, &w);
+  *out = align_up(c.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_lists_bytes(const bvs_index* ix, void* d_ws, uint64_t ws_bytes, void* stream, uint64_t* out) {
+  if (!ix || !out) return fail(BVS_EINVAL, "NULL argument");
+  uint64_t need = 0;
+  BVS_TRY(bvs_lists_workspace_bytes(ix, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  ListWs w;
+  layout_list_ws(c, ix, &w);
+  HIP_TRY(launch_list_build(ix->cnt, ix->ld, ix->n, ix->g.L, w.hist, w.cursor, w.len, w.cum, w.start, nullptr, st,
+                            false));
+  uint64_t nnz = 0;
+  HIP_TRY(hipMemcpyAsync(&nnz, w.start + ix->g.L, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  Carver m(nullptr);
+  uint32_t* a;
+  uint64_t* b;
+  uint32_t* d;
+  layout_lists(m, ix, nnz, &a, &b, &d);
+  *out = align_up(m.off, 256);
+  return BVS_OK;
+}
+
+bvs_status bvs_lists_attach(bvs_index* ix, void* d_mem, uint64_t bytes, void* d_ws, uint64_t ws_bytes, void* stream) {
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (!d_mem) return fail(BVS_EINVAL, "list memory is NULL");
+  uint64_t need = 0;
+  BVS_TRY(bvs_lists_workspace_bytes(ix, &need));
+  BVS_TRY(need_ws(ws_bytes, need, d_ws));
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(d_ws);
+  ListWs w;
+  layout_list_ws(c, ix, &w);
+  // counting pass straight into the list memory's head (its layout does not
+  // depend on nnz), then the fill
+  Carver m(d_mem);
+  uint32_t* cum;
+  uint64_t* start;
+  uint32_t* ids;
+  layout_lists(m, ix, 0, &cum, &start, &ids);
+  const uint64_t head = align_up(m.off, 256);
+  if (bytes < head) return fail(BVS_ENOSPC, "list memory of %llu bytes, more needed", (unsigned long long)bytes);
+  HIP_TRY(launch_list_build(ix->cnt, ix->ld, ix->n, ix->g.L, w.hist, w.cursor, w.len, cum, start, nullptr, st,
+                            false));
+  uint64_t nnz = 0;
+  HIP_TRY(hipMemcpyAsync(&nnz, start + ix->g.L, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  Carver m2(d_mem);
+  layout_lists(m2, ix, nnz, &cum, &start, &ids);
+  if (bytes < align_up(m2.off, 256))
+    return fail(BVS_ENOSPC, "list memory of %llu bytes, %llu needed", (unsigned long long)bytes,
+                (unsigned long long)align_up(m2.off, 256));
+  HIP_TRY(launch_list_build(ix->cnt, ix->ld, ix->n, ix->g.L, w.hist, w.cursor, w.len, cum, start, ids, st, true));
+  HIP_TRY(hipStreamSynchronize(st));
+  ix->lcum = cum;
+  ix->lstart = start;
+  ix->lids = ids;
+  ix->lnnz = nnz;
+  return BVS_OK;
+}
+
+bvs_status bvs_lists_views(const bvs_index* ix, const uint32_t** d_cum, const uint64_t** d_start,
+                           const uint32_t** d_ids, uint64_t* nnz) {
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (!ix->lids) return fail(BVS_ESTATE, "no inverted lists attached (bvs_lists_attach)");
+  if (d_cum) *d_cum = ix->lcum;
+  if (d_start) *d_start = ix->lstart;
+  if (d_ids) *d_ids = ix->lids;
+  if (nnz) *nnz = ix->lnnz;
+  return BVS_OK;
+}
+
+bvs_status bvs_index_set_first_layer(bvs_index* ix, int mode) {
+  if (!ix) return fail(BVS_EINVAL, "index is NULL");
+  if (mode != BVS_FIRST_LAYER_BITMAPS && mode != BVS_FIRST_LAYER_LISTS)
+    return fail(BVS_EINVAL, "unknown first-layer mode %d", mode);
+  if (mode == BVS_FIRST_LAYER_LISTS && !ix->lids)
+    return fail(BVS_ESTATE, "no inverted lists attached (bvs_lists_attach)");
+  ix->first_layer = mode;
+  return BVS_OK;
 }
 
 }  // extern "C"

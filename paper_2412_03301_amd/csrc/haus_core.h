@@ -233,6 +233,34 @@ __device__ __forceinline__ uint32_t mean_min_key(const uint32_t (&qmin)[MAXQT], 
   return __float_as_uint((float)mean);
 }
 
+// Result key of a set from its per-lane query-row minima and the largest of
+// its vectors' distances to the query (colmax, per lane): Hausdorff (max of
+// the two directed terms), Min (smallest pair) or MeanMin, by db.metric.
+template <int MAXQT>
+__device__ __forceinline__ uint32_t set_key(const HausDb& db, const uint32_t (&qmin)[MAXQT], uint32_t colmax,
+                                            const QView& q) {
+  const uint32_t c16 = lane_id() & 15;
+  if (db.metric == kMetricMin) {
+    // every pair's value went into some lane's query-row minima (pad pairs
+    // hold all ones)
+    uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+    for (int qt = 0; qt < MAXQT; ++qt)
+      if ((uint32_t)qt < q.nqt) mn = min(mn, qmin[qt]);
+    return wave_min_dpp_u32(mn);
+  }
+  if (db.metric == kMetricMeanMin) return mean_min_key<MAXQT>(qmin, q);
+  uint32_t rowmax = 0;
+#pragma unroll
+  for (int qt = 0; qt < MAXQT; ++qt) {
+    if ((uint32_t)qt < q.nqt) {
+      const uint32_t rm = rows4_min_u32(qmin[qt]);
+      if ((uint32_t)qt * 16 + c16 < q.mq) rowmax = max(rowmax, rm);
+    }
+  }
+  return wave_max_dpp_u32(max(colmax, rowmax));
+}
+
 // Squared Hausdorff distance (2^24-scaled) of database set [o0, o0 + m)
 // against the query (HASG: some query tiles may come from global memory).
 // The set is abandoned, returning kAbandoned, as soon as a lower bound of
@@ -327,25 +355,96 @@ __device__ __forceinline__ uint32_t haus_item(const HausDb& db, uint64_t o0, uin
     if (bounded && !last && (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_dpp_u32(colmax)) > bound)
       return kAbandoned;
   }
-  if (db.metric == kMetricMin) {
-    // every pair's value went into some lane's query-row minima (pad pairs
-    // hold all ones)
-    uint32_t mn = 0xFFFFFFFFu;
+  return set_key<MAXQT>(db, qmin, colmax, q);
+}
+
+// The distances of database set [o0, o0 + m) to QT queries at once (no
+// bound): each 16-vector tile of the set is loaded into registers once and
+// multiplied against every staged query's tiles, so the set is read from
+// memory once for the QT queries.  out[i] is the result key of query i under
+// db.metric, as haus_item returns it.  Queries past the end repeat a staged
+// view; the caller ignores their keys.
+template <int KS, int MAXQT, bool HASG, int QT>
+__device__ __forceinline__ void haus_multi(const HausDb& db, uint64_t o0, uint32_t m, const QView (&q)[QT],
+                                           uint32_t (&out)[QT]) {
+  const uint32_t lane = lane_id();
+  const uint32_t g = lane >> 4, c16 = lane & 15;
+  const uint32_t dp = KS * 64;
+  const uint32_t QS = q_row_stride(dp);
+  uint32_t qmin[QT][MAXQT];
+  uint32_t colmax[QT];
 #pragma unroll
-    for (int qt = 0; qt < MAXQT; ++qt)
-      if ((uint32_t)qt < q.nqt) mn = min(mn, qmin[qt]);
-    return wave_min_dpp_u32(mn);
+  for (int i = 0; i < QT; ++i) {
+    colmax[i] = 0;
+#pragma unroll
+    for (int t = 0; t < MAXQT; ++t) qmin[i][t] = 0xFFFFFFFFu;
   }
-  if (db.metric == kMetricMeanMin) return mean_min_key<MAXQT>(qmin, q);
-  uint32_t rowmax = 0;
+  for (uint32_t vt = 0; vt < m; vt += 16) {
+    const uint32_t vrow = vt + c16;
+    const bool vrow_ok = vrow < m;
+    v4i ah[KS], al[KS];
+    {
+      const v4i* ph = (const v4i*)(db.hi + (o0 + (vrow_ok ? vrow : 0)) * dp + 16 * g);
+      const v4i* pl = (const v4i*)(db.lo + (o0 + (vrow_ok ? vrow : 0)) * dp + 16 * g);
 #pragma unroll
-  for (int qt = 0; qt < MAXQT; ++qt) {
-    if ((uint32_t)qt < q.nqt) {
-      const uint32_t rm = rows4_min_u32(qmin[qt]);
-      if ((uint32_t)qt * 16 + c16 < q.mq) rowmax = max(rowmax, rm);
+      for (int k = 0; k < KS; ++k) {
+        const v4i z = {0, 0, 0, 0};
+        ah[k] = vrow_ok ? __builtin_nontemporal_load(ph + 4 * k) : z;
+        al[k] = vrow_ok ? __builtin_nontemporal_load(pl + 4 * k) : z;
+      }
+    }
+    uint32_t nv[4];
+    bool vok[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t v = vt + 4 * g + r;
+      vok[r] = v < m;
+      nv[r] = vok[r] ? db.norms[o0 + v] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < QT; ++i) {
+      uint32_t vmin[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll
+      for (int qt = 0; qt < MAXQT; ++qt) {
+        if ((uint32_t)qt < q[i].nqt) {
+          v4i hh = {0, 0, 0, 0}, hl = {0, 0, 0, 0}, lh = {0, 0, 0, 0}, ll = {0, 0, 0, 0};
+          const uint32_t qi = qt * 16 + c16;
+          uint32_t qn;
+          if (!HASG || (uint32_t)qt < q[i].nqt_s) {
+            tile_products<KS>(ah, al, q[i].hs + qi * QS + 16 * g, q[i].ls + qi * QS + 16 * g, hh, hl, lh, ll);
+            qn = q[i].ns[qi];
+          } else {
+            asm volatile("" ::: "memory");
+            const uint8_t* hg = uniform_ptr(q[i].hg);
+            const uint8_t* lg = uniform_ptr(q[i].lg);
+            uint32_t cl = c16;
+            asm volatile("" : "+s"(hg), "+s"(lg), "+v"(cl));
+            const uint32_t r = min(qt * 16 + cl, q[i].mq - 1);
+            const uint32_t off = r * dp + 16 * g;
+            tile_products<KS>(ah, al, hg + off, lg + off, hh, hl, lh, ll);
+            qn = q[i].ng[r];
+          }
+          const bool qok = qi < q[i].mq;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint32_t dot =
+                (uint32_t)hh[r] * 4096u + ((uint32_t)hl[r] + (uint32_t)lh[r]) * 64u + (uint32_t)ll[r];
+            uint32_t d2 = nv[r] + qn - 2u * dot;
+            d2 = (qok && vok[r]) ? d2 : 0xFFFFFFFFu;
+            vmin[r] = min(vmin[r], d2);
+            qmin[i][qt] = min(qmin[i][qt], d2);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t cm = row16_min_u32(vmin[r]);
+        if (vok[r]) colmax[i] = max(colmax[i], cm);
+      }
     }
   }
-  return wave_max_dpp_u32(max(colmax, rowmax));
+#pragma unroll
+  for (int i = 0; i < QT; ++i) out[i] = set_key<MAXQT>(db, qmin[i], colmax[i], q[i]);
 }
 
 // Stage the first min(16 ceil(m_q / 16), lds_rows) rows of query q into LDS

@@ -75,7 +75,9 @@ __device__ __forceinline__ void filter_tile(const FilterArgs& a, uint32_t q0) {
     if ((uint32_t)i < nq) {
       const uint32_t q = q0 + i;
       bool member;
-      if (M == 0) {
+      if (a.member) {
+        member = (a.member[(uint64_t)q * (ld / 64) + j / 64] >> (j % 64)) & 1ull;
+      } else if (M == 0) {
         member = true;
       } else if (M == 1) {
         member = hit[i] != 0;
@@ -155,7 +157,12 @@ hipError_t launch_filter_append(FilterArgs a, hipStream_t st) {
 // 64-bit masks (uniform across the wave).
 __device__ __forceinline__ void tile_members(const FilterArgs& a, uint32_t q, uint64_t tile0, uint32_t lane,
                                              const uint64_t (&vmask)[4], uint64_t (&m)[4]) {
-  if (a.M == 0) {
+  if (a.member) {
+    // first layer read from the inverted lists
+    const cptr<uint64_t> mb = as_const(a.member) + (uint64_t)q * (a.ld / 64) + tile0 / 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = mb[i] & vmask[i];
+  } else if (a.M == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) m[i] = vmask[i];
   } else if (a.M == 1) {

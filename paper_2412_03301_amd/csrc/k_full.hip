@@ -68,30 +68,36 @@ hipError_t launch_code_positions(const uint64_t* codes, uint64_t n, uint32_t R, 
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- query table
-// table[q][g][p] for g < G (groups past the query's vectors are zero).
-// Grid (L / 256, n_q), one thread per position.
+// ---------------------------------------------------------------- query tables
+// Queries are packed: a pack is a run of consecutive queries of the batch
+// whose vectors fill consecutive slots of up to GP groups of 64 (slot of a
+// vector = its index in the batch minus that of the pack's first vector).
+// packs[k] = {first query, queries, groups, 0}.
+// table[k][g][p] for g < groups: bit i says whether the vector in slot
+// 64 g + i has position p in its code.  Grid (L / 256, n_packs).
 __global__ void __launch_bounds__(256)
-k_query_table(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ q_off, uint32_t L, uint32_t R,
-              uint32_t G, uint64_t* __restrict__ table) {
-  const uint32_t q = blockIdx.y;
+k_query_table(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ q_off, const uint4* __restrict__ packs,
+              uint32_t L, uint32_t R, uint32_t GP, uint64_t* __restrict__ table) {
+  const uint32_t k = blockIdx.y;
   const uint32_t p = blockIdx.x * 256 + threadIdx.x;
   if (p >= L) return;
-  const uint64_t o0 = q_off[q];
-  const uint32_t mq = (uint32_t)(q_off[q + 1] - o0);
+  const uint4 pk = packs[k];
+  const uint64_t v0 = q_off[pk.x];
+  const uint32_t total = (uint32_t)(q_off[pk.x + pk.y] - v0);
   const uint32_t wd = p / 64, bt = p % 64;
-  for (uint32_t g = 0; g < G; ++g) {
+  for (uint32_t g = 0; g < pk.z; ++g) {
     uint64_t m = 0;
-    const uint32_t i1 = min(mq, 64 * g + 64);
-    for (uint32_t i = 64 * g; i < i1; ++i) m |= ((codes[(o0 + i) * R + wd] >> bt) & 1ull) << (i - 64 * g);
-    table[((uint64_t)q * G + g) * L + p] = m;
+    const uint32_t i1 = min(total, 64 * g + 64);
+    for (uint32_t i = 64 * g; i < i1; ++i) m |= ((codes[(v0 + i) * R + wd] >> bt) & 1ull) << (i - 64 * g);
+    table[((uint64_t)k * GP + g) * L + p] = m;
   }
 }
 
-hipError_t launch_query_table(const uint64_t* codes, const uint64_t* q_off, uint32_t n_q, uint32_t L, uint32_t R,
-                              uint32_t G, uint64_t* table, hipStream_t st) {
-  if (n_q == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_query_table, dim3((L + 255) / 256, n_q), dim3(256), 0, st, codes, q_off, L, R, G, table);
+hipError_t launch_query_table(const uint64_t* codes, const uint64_t* q_off, const uint4* packs, uint32_t n_packs,
+                              uint32_t L, uint32_t R, uint32_t GP, uint64_t* table, hipStream_t st) {
+  if (n_packs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_query_table, dim3((L + 255) / 256, n_packs), dim3(256), 0, st, codes, q_off, packs, L, R, GP,
+                     table);
   return hipGetLastError();
 }
 
@@ -164,47 +170,69 @@ __device__ __forceinline__ uint32_t bs_min_value(const uint64_t (&a)[NB], uint64
 }
 
 // ---------------------------------------------------------------- scan
-// Haus^H of query q (blockIdx.y) to the sets order[blockIdx.x * 256 + t];
-// scores[q][set] = 2K - 2 ov (uint16).  K = 16 KB16 + KR code positions per
-// vector (row stride KP); NB >= 5 planes hold counts up to K; G groups of 64
-// query vectors.  LDS: the query's table, G * L uint64.
-template <int NB, int G>
-__global__ void __launch_bounds__(256)
+// Sets per workgroup of the scan (one per lane): eight waves share one copy
+// of the pack's tables in LDS.
+static constexpr uint32_t kScanThreads = 512;
+
+// Slots [64 g, 64 g + 64) of query i of a pack whose queries start at slots
+// s[0 .. nq] (s[nq] = the pack's vector count), as a mask of the group.
+__device__ __forceinline__ uint64_t pack_mask(uint32_t s0, uint32_t s1, uint32_t g) {
+  const uint32_t lo = max(s0, 64 * g), hi = min(s1, 64 * g + 64);
+  if (lo >= hi) return 0ull;
+  const uint32_t w = hi - lo;
+  return (w == 64 ? ~0ull : ((1ull << w) - 1)) << (lo - 64 * g);
+}
+
+// Haus^H of the queries of pack blockIdx.y to the sets order[blockIdx.x *
+// kScanThreads + t]; scores[q][set] = 2K - 2 ov (uint16).  K = 16 KB16 + KR code
+// positions per vector (row stride KP); NB >= 5 planes hold counts up to K.
+// LDS: the pack's tables, groups * L uint64.  Per vector, each group's
+// counts give ov for its 64 slots: the slot-wise maxima over the set update
+// (rowmax), and each query of the group takes the largest count among its
+// slots (vmax); at the end each query takes the smallest per-slot maximum
+// among its slots.
+template <int NB, int GP>
+__global__ void __launch_bounds__(kScanThreads)
 k_full_scan(const uint16_t* __restrict__ pos, const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ order,
             uint64_t n_sets, uint32_t K, uint32_t KP, uint32_t L, const uint64_t* __restrict__ table,
-            const uint64_t* __restrict__ q_off, uint16_t* __restrict__ scores, uint64_t ld) {
+            const uint64_t* __restrict__ q_off, const uint4* __restrict__ packs, uint16_t* __restrict__ scores,
+            uint64_t ld) {
   extern __shared__ __align__(16) uint64_t tab[];
-  const uint32_t q = blockIdx.y;
-  const uint32_t mq = (uint32_t)(q_off[q + 1] - q_off[q]);
+  const uint4 pk = packs[blockIdx.y];
+  const uint32_t q0 = pk.x, nq = pk.y, ng = pk.z;
   {
-    const uint4* src = (const uint4*)(table + (uint64_t)q * G * L);
-    for (uint32_t i = threadIdx.x; i < G * L / 2; i += blockDim.x) ((uint4*)tab)[i] = src[i];
+    const uint4* src = (const uint4*)(table + (uint64_t)blockIdx.y * GP * L);
+    for (uint32_t i = threadIdx.x; i < ng * L / 2; i += blockDim.x) ((uint4*)tab)[i] = src[i];
+  }
+  uint32_t sl[kPackQ + 1];
+  {
+    const uint64_t v0 = q_off[q0];
+#pragma unroll
+    for (int i = 0; i <= kPackQ; ++i) sl[i] = (uint32_t)(q_off[q0 + min((uint32_t)i, nq)] - v0);
   }
   __syncthreads();
-  const uint64_t i = blockIdx.x * 256ull + threadIdx.x;
-  if (i >= n_sets) return;
-  const uint32_t j = order[i];
+  const uint64_t it = (uint64_t)blockIdx.x * kScanThreads + threadIdx.x;
+  if (it >= n_sets) return;
+  const uint32_t j = order[it];
   const uint64_t o0 = offsets[j];
   const uint32_t m = (uint32_t)(offsets[j + 1] - o0);
-  uint64_t valid[G];
+  uint64_t rowmax[GP][NB];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int left = (int)mq - 64 * g;
-    valid[g] = left >= 64 ? ~0ull : left <= 0 ? 0ull : ((1ull << left) - 1);
-  }
-  uint64_t rowmax[G][NB];
-#pragma unroll
-  for (int g = 0; g < G; ++g)
+  for (int g = 0; g < GP; ++g)
 #pragma unroll
     for (int b = 0; b < NB; ++b) rowmax[g][b] = 0;
-  uint32_t colmin = 0xFFFFu;
+  uint32_t colmin[kPackQ];
+#pragma unroll
+  for (int i = 0; i < kPackQ; ++i) colmin[i] = 0xFFFFu;
   const uint32_t KB16 = K / 16, KR = K % 16;
   for (uint32_t v = 0; v < m; ++v) {
     const uint16_t* pv = pos + (o0 + v) * KP;
-    uint32_t vmax = 0;
+    uint32_t vmax[kPackQ];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if (!valid[g]) continue;
+    for (int i = 0; i < kPackQ; ++i) vmax[i] = 0;
+#pragma unroll
+    for (int g = 0; g < GP; ++g) {
+      if ((uint32_t)g >= ng) continue;
       const uint64_t* tg = tab + (uint64_t)g * L;
       uint64_t c[NB];
 #pragma unroll
@@ -240,16 +268,32 @@ k_full_scan(const uint16_t* __restrict__ pos, const uint64_t* __restrict__ offse
       }
       for (uint32_t e = 16 * KB16; e < 16 * KB16 + KR; ++e) ripple_add<NB>(c, 0, tg[pv[e]]);
       bs_max<NB>(rowmax[g], c);
-      vmax = max(vmax, bs_max_value<NB>(c, valid[g]));
-    }
-    colmin = min(colmin, vmax);
-  }
-  uint32_t rowmin = 0xFFFFu;
 #pragma unroll
-  for (int g = 0; g < G; ++g)
-    if (valid[g]) rowmin = min(rowmin, bs_min_value<NB>(rowmax[g], valid[g]));
-  const uint32_t ov = min(colmin, rowmin);
-  scores[(uint64_t)q * ld + j] = (uint16_t)(2 * K - 2 * ov);
+      for (int i = 0; i < kPackQ; ++i) {
+        if ((uint32_t)i < nq) {
+          const uint64_t mk = pack_mask(sl[i], sl[i + 1], g);
+          if (mk) vmax[i] = max(vmax[i], bs_max_value<NB>(c, mk));
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPackQ; ++i) colmin[i] = min(colmin[i], vmax[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < kPackQ; ++i) {
+    if ((uint32_t)i < nq) {
+      uint32_t rowmin = 0xFFFFu;
+#pragma unroll
+      for (int g = 0; g < GP; ++g) {
+        if ((uint32_t)g < ng) {
+          const uint64_t mk = pack_mask(sl[i], sl[i + 1], g);
+          if (mk) rowmin = min(rowmin, bs_min_value<NB>(rowmax[g], mk));
+        }
+      }
+      const uint32_t ov = min(colmin[i], rowmin);
+      scores[(uint64_t)(q0 + i) * ld + j] = (uint16_t)(2 * K - 2 * ov);
+    }
+  }
 }
 
 // Planes of the counters: enough for K, and at least the five a block of
@@ -260,32 +304,29 @@ uint32_t full_planes(uint32_t K) {
   return b;
 }
 
-size_t full_lds_bytes(uint32_t L, uint32_t G) { return (size_t)G * L * 8; }
-
 hipError_t launch_full_scan(const uint16_t* pos, const uint64_t* offsets, const uint32_t* order, uint64_t n_sets,
-                            uint32_t K, uint32_t KP, uint32_t L, const uint64_t* table, const uint64_t* q_off, uint32_t n_q,
-                            uint32_t G, uint16_t* scores, uint64_t ld, hipStream_t st) {
-  if (n_q == 0 || n_sets == 0) return hipSuccess;
+                            uint32_t K, uint32_t KP, uint32_t L, const uint64_t* table, const uint64_t* q_off,
+                            const uint4* packs, uint32_t n_packs, uint32_t GP, uint16_t* scores, uint64_t ld,
+                            hipStream_t st) {
+  if (n_packs == 0 || n_sets == 0) return hipSuccess;
   const uint32_t NB = full_planes(K);
-  if (NB > 8 || G < 1 || G > 4 || KP < K || KP % 8 != 0 || L % 2 != 0) return hipErrorInvalidValue;
-  const size_t lds = full_lds_bytes(L, G);
-  const uint64_t blocks = (n_sets + 255) / 256;
+  if (NB > 8 || GP < 1 || GP > kPackGroups || KP < K || KP % 8 != 0 || L % 2 != 0) return hipErrorInvalidValue;
+  const uint32_t gp = GP == 1 ? 1u : GP == 2 ? 2u : 4u;
+  const size_t lds = (size_t)gp * L * 8;
+  const uint64_t blocks = (n_sets + kScanThreads - 1) / kScanThreads;
   if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
   auto go = [&](auto kern) -> hipError_t {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)blocks, n_q), dim3(256), lds, st, pos, offsets, order, n_sets, K, KP,
-                       L, table, q_off, scores, ld);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)blocks, n_packs), dim3(kScanThreads), lds, st, pos, offsets, order, n_sets, K,
+                       KP, L, table, q_off, packs, scores, ld);
     return hipGetLastError();
   };
   auto by_g = [&](auto nb) -> hipError_t {
     constexpr int B = decltype(nb)::value;
-    switch (G) {
-      case 1: return go(k_full_scan<B, 1>);
-      case 2: return go(k_full_scan<B, 2>);
-      case 3: return go(k_full_scan<B, 3>);
-      default: return go(k_full_scan<B, 4>);
-    }
+    if (gp == 1) return go(k_full_scan<B, 1>);
+    if (gp == 2) return go(k_full_scan<B, 2>);
+    return go(k_full_scan<B, 4>);
   };
   switch (NB) {
     case 5: return by_g(std::integral_constant<int, 5>());

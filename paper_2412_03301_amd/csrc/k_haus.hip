@@ -172,6 +172,41 @@ k_haus_all(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, uint32_t* _
   }
 }
 
+// Query-tiled all-sets mode: a unit is (tile of QT consecutive queries, chunk
+// of kAllChunk sets); the workgroup stages the QT queries (lds_rows rows
+// each, the rest read from global memory) and each wave computes its sets
+// against all of them (haus_multi), so every set is read once per QT
+// queries.  Units are numbered over the XCDs as in k_haus_all.
+template <int KS, int MAXQT, bool HASG, int QT>
+__global__ void __launch_bounds__(64 * kHausWaves)
+k_haus_all_qt(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, uint32_t* __restrict__ h2) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint64_t b = blockIdx.x, nb = gridDim.x;   // nb is a multiple of 8
+  const uint64_t unit = (b % 8) * (nb / 8) + b / 8;
+  if (unit >= n_units) return;
+  const uint32_t n_tiles = (qs.n_q + QT - 1) / QT;
+  const uint32_t q0 = (uint32_t)(unit % n_tiles) * QT;
+  const uint32_t chunk = (uint32_t)(unit / n_tiles);
+  const uint64_t s0 = (uint64_t)chunk * kAllChunk;
+  const uint64_t s1 = min(db.n_sets, s0 + kAllChunk);
+  const size_t per_q = haus_stage_bytes(lds_rows, KS * 64);
+  QView qv[QT];
+#pragma unroll
+  for (int i = 0; i < QT; ++i) qv[i] = stage_query(qs, min(q0 + i, qs.n_q - 1), KS * 64, lds_rows, smem + i * per_q);
+  const uint32_t w = wave_id();
+  for (uint64_t j = s0 + w; j < s1; j += kHausWaves) {
+    const uint64_t o0 = db.offsets[j];
+    const uint32_t m = (uint32_t)(db.offsets[j + 1] - o0);
+    uint32_t out[QT];
+    haus_multi<KS, MAXQT, HASG, QT>(db, o0, m, qv, out);
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int i = 0; i < QT; ++i)
+        if (q0 + i < qs.n_q) h2[(uint64_t)(q0 + i) * db.n_sets + j] = out[i];
+    }
+  }
+}
+
 // Instantiation for head dimension dp, queries of up to max_rows vectors
 // and lds_rows staged rows: f(KS, MAXQT, HASG).
 template <typename F>
@@ -285,8 +320,52 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
   });
 }
 
+// Queries per tile of the all-sets kernel and the rows each stages: four
+// queries when each keeps at least 48 staged rows within the budget (or all of
+// its rows), else two, else one (k_haus_all).
+static void all_tile_shape(uint32_t max_rows, uint32_t dp, uint32_t n_q, uint32_t* qt, uint32_t* rows) {
+  const uint32_t need = std::min<uint32_t>((max_rows + 15) / 16 * 16, kMaxQueryTiles * 16);
+  for (uint32_t t : {4u, 2u}) {
+    if (n_q < t || need > 8 * 16) continue;   // haus_multi keeps up to 8 query tiles per query
+    uint32_t r = need;
+    while (r > 16 && t * haus_stage_bytes(r, dp) > kStageBudget) r -= 16;
+    if (t * haus_stage_bytes(r, dp) <= kStageBudget && (r >= 48 || r == need)) {
+      *qt = t;
+      *rows = r;
+      return;
+    }
+  }
+  *qt = 1;
+  *rows = haus_lds_rows(max_rows, dp);
+}
+
 hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipStream_t st) {
   if (q.n_q == 0 || db.n_sets == 0) return hipSuccess;
+  uint32_t QT = 1, trows = 0;
+  all_tile_shape(q.max_rows, db.dp, q.n_q, &QT, &trows);
+  if (QT > 1) {
+    const uint32_t n_chunks = (uint32_t)((db.n_sets + kAllChunk - 1) / kAllChunk);
+    const uint64_t n_units = (uint64_t)n_chunks * ((q.n_q + QT - 1) / QT);
+    const uint64_t grid = align_up(n_units, 8);
+    if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    const size_t lds = QT * haus_stage_bytes(trows, db.dp);
+    return dispatch_haus(db.dp, q.max_rows, trows, [&](auto ks, auto mqt, auto hg) -> hipError_t {
+      constexpr int KS = decltype(ks)::value, MQ = decltype(mqt)::value;
+      constexpr bool HG = decltype(hg)::value;
+      auto go = [&](auto kern) -> hipError_t {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64 * kHausWaves), lds, st, db, q, trows, n_units, h2);
+        return hipGetLastError();
+      };
+      if constexpr (MQ > 8) {
+        return hipErrorInvalidValue;
+      } else {
+        if (QT == 4) return go(k_haus_all_qt<KS, MQ, HG, 4>);
+        return go(k_haus_all_qt<KS, MQ, HG, 2>);
+      }
+    });
+  }
   const uint32_t n_chunks = (uint32_t)((db.n_sets + kAllChunk - 1) / kAllChunk);
   const uint64_t n_units = (uint64_t)n_chunks * q.n_q;
   const uint64_t grid = align_up(n_units, 8);

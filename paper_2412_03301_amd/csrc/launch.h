@@ -82,6 +82,7 @@ struct FilterArgs {
   uint32_t* any_long;          // 1 when some rank pair needs the long-sketch instance
   unsigned long long* stats;   // work counters (see bvs_stage_times), may be null
   const uint32_t* run_if;      // dense mode: skip all work unless *run_if != 0 (may be null)
+  const uint64_t* member;      // first layer from the inverted lists: [n_q][ld / 64] bitmaps (may be null)
 };
 hipError_t launch_filter_dense(FilterArgs a, hipStream_t st);
 hipError_t launch_filter_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st);
@@ -188,18 +189,36 @@ hipError_t launch_haus_queue(const HausDb& db, const HausQ& q, const QueueArgs& 
                              uint32_t blocks, hipStream_t st);
 
 // Full-scan search (Alg. 2).  pos [n][KP] uint16: the K code positions of
-// every vector (from codes [n][R] uint64).  table [n_q][G][L] uint64: bit i
-// of entry (q, g, p) says whether vector 64 g + i of query q has position p.
-// Scan: scores[q][j] = Haus^H (Hamming form of Def. 4) of query q to set j
-// for the n_sets sets listed in order [n_sets] (any order; by size keeps
-// the lanes of a wave together).
+// every vector (from codes [n][R] uint64).  Queries go in packs: runs of
+// consecutive queries of the batch, at most kPackQ, whose vectors fill
+// consecutive slots of at most kPackGroups groups of 64; packs [n_packs] =
+// {first query, queries, groups, 0}.  table [n_packs][GP][L] uint64: bit i of
+// entry (k, g, p) says whether the vector in slot 64 g + i of pack k has
+// position p (GP >= the groups of every pack).  Scan: scores[q][j] = Haus^H
+// (Hamming form of Def. 4) of query q to set j for the n_sets sets listed in
+// order [n_sets] (any order; by size keeps the lanes of a wave together).
+static constexpr int kPackQ = 8;
+static constexpr uint32_t kPackGroups = 4;
 hipError_t launch_code_positions(const uint64_t* codes, uint64_t n, uint32_t R, uint32_t K, uint32_t KP,
                                  uint16_t* pos, int n_cu, hipStream_t st);
-hipError_t launch_query_table(const uint64_t* codes, const uint64_t* q_off, uint32_t n_q, uint32_t L, uint32_t R,
-                              uint32_t G, uint64_t* table, hipStream_t st);
+hipError_t launch_query_table(const uint64_t* codes, const uint64_t* q_off, const uint4* packs, uint32_t n_packs,
+                              uint32_t L, uint32_t R, uint32_t GP, uint64_t* table, hipStream_t st);
 hipError_t launch_full_scan(const uint16_t* pos, const uint64_t* offsets, const uint32_t* order, uint64_t n_sets,
                             uint32_t K, uint32_t KP, uint32_t L, const uint64_t* table, const uint64_t* q_off,
-                            uint32_t n_q, uint32_t G, uint16_t* scores, uint64_t ld, hipStream_t st);
+                            const uint4* packs, uint32_t n_packs, uint32_t GP, uint16_t* scores, uint64_t ld,
+                            hipStream_t st);
+
+// Inverted lists (Def. 9, Alg. 4) from the position-major counts: pass
+// fill = false writes hist [L][256] (scratch), cum [L][257], len [L] and
+// start [L + 1]; fill = true writes ids [start[L]] (cursor [L][256] scratch).
+hipError_t launch_list_build(const uint8_t* cnt, uint64_t ld, uint64_t n_sets, uint32_t L, uint32_t* hist,
+                             uint32_t* cursor, uint64_t* len, uint32_t* cum, uint64_t* start, uint32_t* ids,
+                             hipStream_t st, bool fill);
+// First layer from the lists: member [n_q][ld / 64] = OR over the A positions
+// of the query of the bits of the sets with count >= M.
+hipError_t launch_list_gather(const uint32_t* ids, const uint64_t* start, const uint32_t* cum, const uint32_t* pos,
+                              uint32_t A, uint32_t M, uint32_t n_q, uint64_t ld, uint64_t* member, int n_cu,
+                              hipStream_t st);
 
 // First k by (h2, id) of each query.  ids_in may be NULL (item index = id).
 // tmp must hold 2 * n_q * ceil(n_items / 4096) * k uint64.  Reported

@@ -197,6 +197,9 @@ WORKLOADS = {
                  code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10),
     "metrics": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
                     code_bits=4096, fan_in=16, wta_k=64, n_queries=1024, top_t=1000, k=10),
+    # the parameter study: the scale database, fewer queries, many settings
+    "trends": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
+                   code_bits=4096, fan_in=16, wta_k=64, n_queries=256, top_t=1000, k=10),
     # the scale database, searched by fresh-entity queries of 1-256 vectors
     "batched": dict(n_sets=1_000_000, size_lo=5, size_hi=100, dim=384, n_topics=10_000,
                     code_bits=4096, fan_in=16, wta_k=64, n_queries=4096, max_query=256, top_t=1000, k=10),

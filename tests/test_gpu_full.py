@@ -85,3 +85,20 @@ def test_full_scan_needs_attached_codes():
     with pytest.raises(bvs.BvsError) as e:
         case.ix_gpu.search_full(case.q, case.q_off, 10)
     assert e.value.status == bvs.BVS_ESTATE
+
+
+def test_scores_of_packed_small_queries(tiny):
+    # twelve one-vector queries and then three larger ones: packs of eight
+    # queries, of several queries sharing a group of 64 slots, and a query
+    # straddling two groups
+    sizes = [1] * 12 + [30, 50, 70]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    rows = np.concatenate([np.arange(12), np.arange(12, 12 + 150) % int(tiny.q_off[-1])])
+    q = tiny.q[rows].contiguous()
+    sc = to_np(tiny.ix_gpu.full_scores(q, off)).view(np.uint16)
+    qn = q.cpu().numpy().astype(np.float64)
+    from oracle import flyhash
+    for i in range(len(sizes)):
+        Q = qn[off[i]:off[i + 1]]
+        HQ = flyhash.codes(Q, tiny.ix_oracle.idx, tiny.ix_oracle.wta_k)
+        assert np.array_equal(sc[i].astype(np.int64), biovss.full_scores(tiny.ix_oracle, HQ)), i

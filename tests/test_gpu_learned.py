@@ -123,3 +123,33 @@ def test_training_lowers_the_loss():
     losses = tr.train(w, trip)
     assert len(losses) == 6 and all(np.isfinite(losses))
     assert losses[-1] < 0.8 * losses[0], losses
+
+
+def test_training_resumes_from_a_checkpoint():
+    # four epochs in one call against two calls of two epochs with the
+    # weights and the optimizer state copied to the host and back between
+    # them: the same batches and Adam steps, equal up to the order of the
+    # gradients' floating-point sums
+    from paper_2412_03301_amd import bvs
+    db, trip = _train_case(6)
+    w0 = bvs.mlp_weights(D, H, L, seed=5)
+    tr4 = bvs.Trainer(bvs.TrainConfig(D, H, L, K, 16, 4, 3e-3, 0.5, 4.0, 0, 9), db.vectors.cuda(), db.offsets,
+                      max_batch_rows=16 * 3 * 9)
+    tr2 = bvs.Trainer(bvs.TrainConfig(D, H, L, K, 16, 2, 3e-3, 0.5, 4.0, 0, 9), db.vectors.cuda(), db.offsets,
+                      max_batch_rows=16 * 3 * 9)
+    w_one = w0.clone()
+    losses_one = tr4.train(w_one, trip)
+    w_res = w0.clone()
+    st = tr2.new_state()
+    l1 = tr2.train_resume(w_res, trip, st)
+    ckpt_w, ckpt_s = w_res.cpu().clone(), st.cpu().clone()
+    del w_res, st
+    w_res, st = ckpt_w.cuda(), ckpt_s.cuda()
+    l2 = tr2.train_resume(w_res, trip, st)
+    np.testing.assert_allclose(l1 + l2, losses_one, rtol=2e-3)
+    a, b = w_res.cpu().numpy().astype(np.float64), w_one.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b)
+    # the header counts the Adam steps and epochs done
+    n_batches = -(-len(trip) // 16)
+    hdr = st.cpu().numpy()[-256:].view(np.uint64)[:2]
+    assert hdr.tolist() == [4 * n_batches, 4]

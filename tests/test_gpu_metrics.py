@@ -27,7 +27,7 @@ def wide():
     """d = 384, L = 4096, queries of 1-256 vectors (query tiles past the
     staged rows are read from global memory)."""
     print("[metrics] d=384 workload, queries up to 256 vectors", flush=True)
-    return build_case(1500, 5, 100, 384, 30, 4096, 16, 64, 150, 5, queries=[1, 17, 64, 130, 256])
+    return build_case(1500, 5, 100, 384, 30, 4096, 16, 64, 150, 5, queries=[1, 17, 100, 64, 256])
 
 
 def _check(case, metric, k=10):
@@ -72,3 +72,21 @@ def test_bruteforce_metric(tiny, metric):
         r_ids, _, r_dist = search.bruteforce_metric(tiny.X, tiny.db.offsets, tiny.query(i), 10, metric)
         assert ids[i].astype(np.int64).tolist() == r_ids.tolist(), (metric, i)
         np.testing.assert_allclose(dist[i], r_dist, rtol=TOL[metric], atol=0)
+
+
+@pytest.mark.parametrize("name,n_q", [("tiny", 7), ("wide", 1), ("wide", 3), ("wide", 4), ("wide", 5)])
+def test_bruteforce_query_tiles_with_ragged_tail(name, n_q, request):
+    # several queries share each database set's registers (tiles of 4 small
+    # queries, or of 2 with rows past the staged ones read from global
+    # memory); the last tile of queries is partly empty; a batch holding a
+    # query of more than 128 vectors takes one query per workgroup
+    case = request.getfixturevalue(name)
+    off = case.q_off[:n_q + 1]
+    q = case.q[:int(off[-1])].contiguous()
+    for metric in ("hausdorff", "meanmin"):
+        ids, dist, cnt = case.ix_gpu.bruteforce_metric(q, off, 10, metric)
+        ids, dist = to_np(ids).view(np.uint32), to_np(dist)
+        for i in range(n_q):
+            r_ids, _, r_dist = search.bruteforce_metric(case.X, case.db.offsets, case.query(i), 10, metric)
+            assert ids[i].astype(np.int64).tolist() == r_ids.tolist(), (metric, i)
+            np.testing.assert_allclose(dist[i], r_dist, rtol=TOL[metric], atol=0)
