@@ -184,14 +184,16 @@ __device__ __forceinline__ uint64_t pack_mask(uint32_t s0, uint32_t s1, uint32_t
 }
 
 // Haus^H of the queries of pack blockIdx.y to the sets order[blockIdx.x *
-// kScanThreads + t]; scores[q][set] = 2K - 2 ov (uint16).  K = 16 KB16 + KR code
-// positions per vector (row stride KP); NB >= 5 planes hold counts up to K.
+// kScanThreads + t]; scores[q][set] = 2K - 2 ov (uint16).  K code positions
+// per vector (row stride KP): the first 16 KB16 are held in registers and
+// summed by carry-save blocks of 16, the rest added one at a time; NB >= 5
+// planes hold counts up to K.
 // LDS: the pack's tables, groups * L uint64.  Per vector, each group's
 // counts give ov for its 64 slots: the slot-wise maxima over the set update
 // (rowmax), and each query of the group takes the largest count among its
 // slots (vmax); at the end each query takes the smallest per-slot maximum
 // among its slots.
-template <int NB, int GP>
+template <int NB, int GP, int KB16>
 __global__ void __launch_bounds__(kScanThreads)
 k_full_scan(const uint16_t* __restrict__ pos, const uint64_t* __restrict__ offsets, const uint32_t* __restrict__ order,
             uint64_t n_sets, uint32_t K, uint32_t KP, uint32_t L, const uint64_t* __restrict__ table,
@@ -224,9 +226,21 @@ k_full_scan(const uint16_t* __restrict__ pos, const uint64_t* __restrict__ offse
   uint32_t colmin[kPackQ];
 #pragma unroll
   for (int i = 0; i < kPackQ; ++i) colmin[i] = 0xFFFFu;
-  const uint32_t KB16 = K / 16, KR = K % 16;
+  // each vector's first 16 KB16 positions are loaded once for every group,
+  // the whole row at once (each of its cache lines fetched once), one
+  // vector ahead of its use; one spare word: no zero-length array at KB16 = 0
+  uint4 pn[2 * KB16 + 1];
+#pragma unroll
+  for (int e = 0; e < 2 * KB16; ++e) pn[e] = *(const uint4*)(pos + o0 * KP + 8 * e);
   for (uint32_t v = 0; v < m; ++v) {
     const uint16_t* pv = pos + (o0 + v) * KP;
+    uint4 pr[2 * KB16 + 1];
+#pragma unroll
+    for (int e = 0; e < 2 * KB16; ++e) pr[e] = pn[e];
+    if (v + 1 < m) {
+#pragma unroll
+      for (int e = 0; e < 2 * KB16; ++e) pn[e] = *(const uint4*)(pv + KP + 8 * e);
+    }
     uint32_t vmax[kPackQ];
 #pragma unroll
     for (int i = 0; i < kPackQ; ++i) vmax[i] = 0;
@@ -237,10 +251,10 @@ k_full_scan(const uint16_t* __restrict__ pos, const uint64_t* __restrict__ offse
       uint64_t c[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) c[b] = 0;
-      for (uint32_t blk = 0; blk < KB16; ++blk) {
-        // 16 positions: two 16-byte loads
-        const uint4 w0 = *(const uint4*)(pv + 16 * blk);
-        const uint4 w1 = *(const uint4*)(pv + 16 * blk + 8);
+#pragma unroll
+      for (int blk = 0; blk < KB16; ++blk) {
+        // 16 positions from two 16-byte words of the row
+        const uint4 w0 = pr[2 * blk], w1 = pr[2 * blk + 1];
         const uint32_t pw[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
         uint64_t x[16];
 #pragma unroll
@@ -266,7 +280,7 @@ k_full_scan(const uint16_t* __restrict__ pos, const uint64_t* __restrict__ offse
         csa(sixteens, c[3], c[3], eightsA, eightsB);
         ripple_add<NB>(c, 4, sixteens);
       }
-      for (uint32_t e = 16 * KB16; e < 16 * KB16 + KR; ++e) ripple_add<NB>(c, 0, tg[pv[e]]);
+      for (uint32_t e = 16 * KB16; e < K; ++e) ripple_add<NB>(c, 0, tg[pv[e]]);
       bs_max<NB>(rowmax[g], c);
 #pragma unroll
       for (int i = 0; i < kPackQ; ++i) {
@@ -322,11 +336,14 @@ hipError_t launch_full_scan(const uint16_t* pos, const uint64_t* offsets, const 
                        KP, L, table, q_off, packs, scores, ld);
     return hipGetLastError();
   };
+  // blocks of 16 positions held in registers: 4 from K = 64 (7 or 8 planes),
+  // 2 from K = 32 (6 planes), none below (5 planes)
   auto by_g = [&](auto nb) -> hipError_t {
     constexpr int B = decltype(nb)::value;
-    if (gp == 1) return go(k_full_scan<B, 1>);
-    if (gp == 2) return go(k_full_scan<B, 2>);
-    return go(k_full_scan<B, 4>);
+    constexpr int KB = B >= 7 ? 4 : B == 6 ? 2 : 0;
+    if (gp == 1) return go(k_full_scan<B, 1, KB>);
+    if (gp == 2) return go(k_full_scan<B, 2, KB>);
+    return go(k_full_scan<B, 4, KB>);
   };
   switch (NB) {
     case 5: return by_g(std::integral_constant<int, 5>());
