@@ -129,14 +129,27 @@ __device__ __forceinline__ void hash_keys(const int16_t* __restrict__ av, const 
 
 // The k-th largest of the wave's 64 R unique keys.  A prefix above the
 // largest key admits no key, so those bits are skipped without counting.
+// For k <= 64 the smallest of the 64 lanes' largest keys is a lower bound
+// (64 distinct keys reach it): the answer lies between it and the largest
+// key, so it shares their common high bits, which are set without counting.
 template <int R>
 __device__ __forceinline__ uint32_t kth_largest(const uint32_t (&key)[R], uint32_t k, int topbit) {
-  uint32_t kmax = 0;
+  uint32_t lm = 0;
 #pragma unroll
-  for (int t = 0; t < R; ++t) kmax = max(kmax, key[t]);
-  kmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_dpp_u32(kmax));
+  for (int t = 0; t < R; ++t) lm = max(lm, key[t]);
+  const uint32_t kmax = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_dpp_u32(lm));
   uint32_t theta = 0;
-  for (int b = topbit; b >= 0; --b) {
+  int b0 = topbit;
+  if (k <= 64) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_dpp_u32(lm));
+    const uint32_t diff = lo ^ kmax;
+    if (diff != 0) {
+      const int hb = 31 - __builtin_clz(diff);
+      theta = hb >= 31 ? 0u : (kmax & ~((2u << hb) - 1u));
+      b0 = min(b0, hb);
+    }
+  }
+  for (int b = b0; b >= 0; --b) {
     const uint32_t cand = theta | (1u << b);
     if (cand > kmax) continue;
     // per-lane count, then one wave sum (no per-key ballots held in scalars)
