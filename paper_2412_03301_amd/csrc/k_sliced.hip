@@ -302,15 +302,15 @@ __device__ __forceinline__ Words<W> tree8(const Words<W> (&x)[8], Slices<W, S>& 
   return eights;
 }
 
-// Ripple one word of weight 16 into H.  With 9 slices every slice takes
-// it.  With 13, the first four high slices (weights 16 to 128) always do;
-// the carry out of them is nonzero at most once per 256 rows, and only then
-// (a wave-uniform test) does it ripple on.
-template <int W, int S>
-__device__ __forceinline__ void add_sixteens(Words<W> x, Slices<W, S>& c) {
+// Ripple one word of weight 2^K0 into the slices K0 and up.  With 9
+// slices every slice takes it.  With 13, the slices below 8 (weights up to
+// 128) always do; the carry out of them is nonzero at most once per 256
+// rows, and only then (a wave-uniform test) does it ripple on.
+template <int K0, int W, int S>
+__device__ __forceinline__ void add_carry(Words<W> x, Slices<W, S>& c) {
   constexpr int K1 = S <= 9 ? S : 8;
 #pragma unroll
-  for (int k = 4; k < K1; ++k)
+  for (int k = K0; k < K1; ++k)
 #pragma unroll
     for (int i = 0; i < W; ++i) {
       const uint32_t cy = c.s[k].v[i] & x.v[i];
@@ -332,6 +332,37 @@ __device__ __forceinline__ void add_sixteens(Words<W> x, Slices<W, S>& c) {
         }
     }
   }
+}
+
+// Word 3 of a raw buffer resource for dword loads (32-bit data format).
+static constexpr int kRawBufferWord3 = 0x00020000;
+
+// Row offsets of one step of 16 rows: entries 16 step .. 16 step + 15 of the
+// list part at byte offset voff of the resource.  (Loads through the buffer
+// intrinsic stay where they are issued: the offsets of a later step arrive
+// while this one counts.)
+__device__ __forceinline__ void list_offsets(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t step,
+                                             uint4 (&o)[4]) {
+  typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16 * j, step * 64, 0);
+    o[j] = make_uint4(x.x, x.y, x.z, x.w);
+  }
+}
+
+// Add the 16 rows at LDS offsets o to the counters below weight 16;
+// returns the word of weight 16.
+template <int W, int S>
+__device__ __forceinline__ Words<W> sixteen_rows(const uint4 (&o)[4], Slices<W, S>& c) {
+  Words<W> x[8];
+  load8<W>(o[0], o[1], x);
+  const Words<W> eA = tree8<W, S>(x, c);
+  load8<W>(o[2], o[3], x);
+  const Words<W> eB = tree8<W, S>(x, c);
+  Words<W> sixteens;
+  csa(sixteens, c.s[3], eA, eB);
+  return sixteens;
 }
 
 // One tile of 256 sets for the queries of part q_part (of q_parts) of the
@@ -393,38 +424,57 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
     valid.v[i] = b >= a.n_sets ? 0u : (a.n_sets - b >= 32 ? ~0u : (1u << (a.n_sets - b)) - 1u);
   }
   uint32_t pairs = 0;
-  for (uint32_t qb0 = (w + NW * q_part) * QPW; qb0 < a.n_q; qb0 += NW * q_parts * QPW) {
+  // Round r of this workgroup covers passes NW (q_part + q_parts r) .. + NW - 1
+  // (ranks are by decreasing |S_Q|, so a round's passes shorten with r and
+  // within it); wave w takes its w-th pass in even rounds and its
+  // (NW - 1 - w)-th in odd ones, so that the waves' totals even out before
+  // the tile's closing barrier.
+  for (uint32_t r = 0;; ++r) {
+    const uint32_t qb0 = (NW * (q_part + q_parts * r) + ((r & 1) ? NW - 1 - w : w)) * QPW;
+    if (NW * (q_part + q_parts * r) * QPW >= a.n_q) break;
+    if (qb0 >= a.n_q) continue;
     if (big(qb0 / kPairRanks) == kSmall) continue;   // the other instance's pass
     const uint32_t qi = qb0 + slot;
     const bool active = qi < a.n_q;
     const uint32_t q = a.order[active ? qi : a.n_q - 1];
-    // list part (of 4, 8 bytes each) that starts this lane's words
-    const uint4* lst = (const uint4*)(a.lists + ((uint64_t)qi * 4 + part * (4 / PARTS)) * a.LP);
     const uint32_t qbq = active ? a.sbits[qi] : 0u;
     const uint32_t cutq = a.cutoff[q];
     const uint32_t nblk = as_const(a.gsteps)[2 * (qb0 / kPairRanks)];
+    // The pass's row lists (QPW ranks of 4 parts) are read through a buffer
+    // resource based at the list of its first rank: a scalar base, the
+    // lane's list part (of 4, 8 bytes each: the one that starts its words)
+    // as a vector offset, the step as a scalar offset.
+    const uint32_t* lbase = a.lists + (uint64_t)qb0 * 4 * a.LP;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)lbase, (short)0, (int)(QPW * 4 * a.LP * 4), kRawBufferWord3);
+    const uint32_t voff = (slot * 4 + part * (4 / PARTS)) * a.LP * 4;
     Slices<W, S> c;
 #pragma unroll
     for (int k = 0; k < S; ++k)
 #pragma unroll
       for (int i = 0; i < W; ++i) c.s[k].v[i] = 0;
-    // 16 rows per step, in two halves of 8; the offsets of the next step
-    // load from the list while this one runs (the lists are written up to
-    // entry 16 nblk + 48, past every read here)
-    uint4 oA0 = lst[0], oA1 = lst[1], oB0 = lst[2], oB1 = lst[3];
-    uint4 nA0 = lst[4], nA1 = lst[5], nB0 = lst[6], nB1 = lst[7];
-    for (uint32_t b = 0; b < nblk; ++b) {
-      Words<W> x[8];
-      load8<W>(oA0, oA1, x);
-      const Words<W> eA = tree8<W, S>(x, c);
-      load8<W>(oB0, oB1, x);
-      oA0 = nA0; oA1 = nA1; oB0 = nB0; oB1 = nB1;
-      nA0 = lst[4 * b + 8]; nA1 = lst[4 * b + 9]; nB0 = lst[4 * b + 10]; nB1 = lst[4 * b + 11];
-      const Words<W> eB = tree8<W, S>(x, c);
-      Words<W> sixteens;
-      csa(sixteens, c.s[3], eA, eB);
-      add_sixteens<W, S>(sixteens, c);
+    // 16 rows per step, in two halves of 8; two steps per iteration, whose
+    // words of weight 16 meet in one more carry-save step (weight 32 out).
+    // The steps' row offsets are held in register sets X and Y; the offsets
+    // of step b + 2 load into X when step b is done and arrive while step
+    // b + 1 counts (the lists are written up to entry 16 nblk + 48 of every
+    // part, past every read here).
+    uint4 X[4], Y[4];
+    list_offsets(rs, voff, 0, X);
+    list_offsets(rs, voff, 1, Y);
+    uint32_t b = 0;
+    for (; b + 1 < nblk; b += 2) {
+      const Words<W> sA = sixteen_rows<W, S>(X, c);
+      list_offsets(rs, voff, b + 2, X);
+      __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of step b + 1
+      const Words<W> sB = sixteen_rows<W, S>(Y, c);
+      list_offsets(rs, voff, b + 3, Y);
+      __builtin_amdgcn_sched_barrier(0);
+      Words<W> thirtytwos;
+      csa(thirtytwos, c.s[4], sA, sB);
+      add_carry<5, W, S>(thirtytwos, c);
     }
+    if (b < nblk) add_carry<4, W, S>(sixteen_rows<W, S>(X, c), c);
 
     // first layer
     Words<W> m;
