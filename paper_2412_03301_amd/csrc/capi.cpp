@@ -298,7 +298,7 @@ struct bvs_index {
   uint2* scr;         // [N] {|hi|^2, |lo - 31.5| / 64 rounded up} for re-rank screening
   uint8_t* cnt;
   uint64_t* bits;
-  uint64_t* planes;   // [L][ld/64]: bit j of plane p set when C^(j)[p] >= 1
+  uint64_t* planes;   // [ld/256][L][4]: bit j % 256 of row p of tile j / 256 set when C^(j)[p] >= 1
   uint16_t* spop;     // [ld]: |B| of every set (0 for padding)
   // attached precision copies, by format (BVS_LOWP_BF16, BVS_LOWP_FP8)
   uint8_t* lowp[3] = {nullptr, nullptr, nullptr};
@@ -379,6 +379,8 @@ struct QueryWs {
   uint32_t* order;        // [n_q]
   uint32_t* sbits;        // [n_q]
   uint32_t* gsteps;       // [n_q rounded up to 32, / 16]
+  uint32_t* rpos;         // [n_q rounded up to 32][A] first-layer tile-row offsets by rank
+  uint32_t* rcut;         // [n_q rounded up to 32] cutoff by rank
   uint32_t* any_long;     // [1]
   uint64_t* member;       // [n_q][ld / 64] first layer from the inverted lists (lists mode only)
   uint32_t* f2_ids;
@@ -480,6 +482,8 @@ void layout_search(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Qu
   w->order = c.take<uint32_t>(n_q);
   w->sbits = c.take<uint32_t>(n_q);
   w->gsteps = c.take<uint32_t>(align_up(n_q, 32) / 16);
+  w->rpos = c.take<uint32_t>(align_up(n_q, 32) * g.A);
+  w->rcut = c.take<uint32_t>(align_up(n_q, 32));
   w->any_long = c.take<uint32_t>(1);
   w->member = lists_first_layer(ix) ? c.take<uint64_t>((uint64_t)n_q * (ix->ld / 64)) : nullptr;
   w->f2_ids = c.take<uint32_t>((uint64_t)n_q * g.T);
@@ -602,6 +606,8 @@ FilterArgs filter_args(const bvs_index* ix, uint32_t n_q, const QueryWs& w) {
   a.order = w.order;
   a.sbits = w.sbits;
   a.gsteps = w.gsteps;
+  a.rpos = w.rpos;
+  a.rcut = w.rcut;
   a.any_long = w.any_long;
   a.fail = w.status + 1;   // raised when the dense path must answer
   a.stats = nullptr;   // set by the caller when profiling
@@ -644,6 +650,8 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
       }
       if (ix->n <= w.cap) {
         // every member fits the buffer: admit them all
+        e = launch_fill_u32(w.rcut, n_q, 0xFFFFFFFFu, st);
+        if (e != hipSuccess) return e;
         return launch_fill_u32(w.cutoff, n_q, 0xFFFFFFFFu, st);
       }
       const uint32_t nsb = std::min(kSampleBlocks, n_blocks);
@@ -667,7 +675,8 @@ bvs_status run_filters(const bvs_index* ix, uint32_t n_q, uint64_t NQ, const Que
       const uint64_t r_aim = (kCutoffAlpha * (uint64_t)g.T * sampled + ix->n - 1) / ix->n;
       const uint64_t r_fit = std::max<uint64_t>(1, (uint64_t)w.cap * sampled / (2 * ix->n));
       const uint32_t r = (uint32_t)std::max<uint64_t>(1, std::max(r_aim, std::min<uint64_t>(kMinSampleRank, r_fit)));
-      return launch_cutoff(w.sample, (uint32_t)S, g.L, r, n_q, w.cutoff, st);
+      return launch_cutoff(w.sample, (uint32_t)S, g.L, r, n_q, w.cutoff, sliced ? w.order : nullptr,
+                           sliced ? w.rcut : nullptr, st);
     }));
     HIP_TRY(staged(prof, S_FILTER, [&]() -> hipError_t {
       if (sliced) return launch_filter_sliced(a, st);

@@ -402,9 +402,12 @@ hipError_t launch_transpose_sketches(const uint8_t* cnt_rm, const uint64_t* bits
 }
 
 // ---------------------------------------------------------------- bitmap planes
-// Position-major membership bitmaps of the first layer with M = 1:
-// bit (j % 64) of word [p][j / 64] is set when C^(j)[p] >= 1, i.e. set j is
-// on the inverted list of position p (Def. 9).  One thread per word.
+// Membership bitmaps of the first layer with M = 1, tile-major: for the tile
+// of 256 sets t = j / 256, row p of the tile is the four words
+// [(t L + p) 4 .. + 3], and bit (j % 64) of word (j % 256) / 64 of it is set
+// when C^(j)[p] >= 1, i.e. set j is on the inverted list of position p
+// (Def. 9).  A tile's L rows are one contiguous run of 32 L bytes.  One thread
+// per word.
 __global__ void __launch_bounds__(256)
 k_bitmap_planes(const uint8_t* __restrict__ cnt, uint64_t ld, uint32_t L, uint64_t* __restrict__ planes) {
   const uint64_t wpp = ld / 64;
@@ -421,7 +424,7 @@ k_bitmap_planes(const uint8_t* __restrict__ cnt, uint64_t ld, uint32_t L, uint64
     for (int e = 0; e < 16; ++e)
       if ((d[e / 4] >> (8 * (e % 4))) & 0xFF) bits |= 1ull << (16 * k + e);
   }
-  planes[i] = bits;
+  planes[((w / 4) * L + p) * 4 + w % 4] = bits;
 }
 
 hipError_t launch_bitmap_planes(const uint8_t* cnt, uint64_t ld, uint32_t L, uint64_t* planes, hipStream_t st) {

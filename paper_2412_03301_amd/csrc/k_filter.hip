@@ -167,12 +167,11 @@ __device__ __forceinline__ void tile_members(const FilterArgs& a, uint32_t q, ui
     for (int i = 0; i < 4; ++i) m[i] = vmask[i];
   } else if (a.M == 1) {
     // C[p] >= 1 for one of the query's A positions: OR of their bitmap rows
-    const cptr<uint64_t> pl = as_const(a.planes) + tile0 / 64;
-    const uint64_t wpp = a.ld / 64;
+    const cptr<uint64_t> pl = as_const(a.planes) + (tile0 / 256) * a.L * 4;
 #pragma unroll
     for (int i = 0; i < 4; ++i) m[i] = 0;
     for (uint32_t t = 0; t < a.A; ++t) {
-      const uint64_t r = (uint64_t)as_const(a.pos)[(uint64_t)q * a.A + t] * wpp;
+      const uint64_t r = (uint64_t)as_const(a.pos)[(uint64_t)q * a.A + t] * 4;
 #pragma unroll
       for (int i = 0; i < 4; ++i) m[i] |= pl[r + i];
     }
@@ -565,13 +564,16 @@ hipError_t launch_select(const uint16_t* scores, uint64_t ld, uint32_t L, uint32
 // ---------------------------------------------------------------- sampled cutoff
 // One block per query: histogram of the sampled scores; the cutoff is the
 // smallest score s with #{sample members with score <= s} >= r, or all ones
-// (admit every member) when the sample holds fewer than r members.
+// (admit every member) when the sample holds fewer than r members.  With
+// order, block b serves query order[b] (rank b) and also writes rcut[b].
 __global__ void __launch_bounds__(256)
-k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r, uint32_t* __restrict__ cutoff) {
+k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r, uint32_t* __restrict__ cutoff,
+         const uint32_t* __restrict__ order, uint32_t* __restrict__ rcut) {
   extern __shared__ uint32_t h[];
   __shared__ uint32_t part[256];
   __shared__ uint32_t total_s;
-  const uint32_t q = blockIdx.x, t = threadIdx.x;
+  const uint32_t t = threadIdx.x;
+  const uint32_t q = order ? order[blockIdx.x] : blockIdx.x;
   const uint32_t nb = L + 1;
   for (uint32_t i = t; i < nb; i += 256) h[i] = 0;
   __syncthreads();
@@ -594,7 +596,10 @@ k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r
   }
   __syncthreads();
   if (total_s < r) {
-    if (t == 0) cutoff[q] = 0xFFFFFFFFu;
+    if (t == 0) {
+      cutoff[q] = 0xFFFFFFFFu;
+      if (rcut) rcut[blockIdx.x] = 0xFFFFFFFFu;
+    }
     return;
   }
   const uint32_t pre = part[t];
@@ -602,15 +607,20 @@ k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r
     uint32_t cum = pre;
     for (uint32_t b = b0; b < b1; ++b) {
       cum += h[b];
-      if (cum >= r) { cutoff[q] = b; break; }
+      if (cum >= r) {
+        cutoff[q] = b;
+        if (rcut) rcut[blockIdx.x] = b;
+        break;
+      }
     }
   }
 }
 
 hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_t r, uint32_t n_q,
-                         uint32_t* cutoff, hipStream_t st) {
+                         uint32_t* cutoff, const uint32_t* order, uint32_t* rcut, hipStream_t st) {
   if (n_q == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cutoff, dim3(n_q), dim3(256), (L + 1) * sizeof(uint32_t), st, sample, S, L, r, cutoff);
+  hipLaunchKernelGGL(k_cutoff, dim3(n_q), dim3(256), (L + 1) * sizeof(uint32_t), st, sample, S, L, r, cutoff, order,
+                     rcut);
   return hipGetLastError();
 }
 

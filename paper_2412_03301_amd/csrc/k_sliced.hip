@@ -5,7 +5,8 @@
 // of positions p set in S_Q whose bit is set in B.  With the position-major
 // bitmaps (row p = bit p of every set), the inner products of one query
 // with a tile of 256 sets are the column sums of the rows p in S_Q: a
-// workgroup stages the tile's L rows in LDS (32 B each) and every lane adds
+// workgroup stages the tile's L rows in LDS (32 B each, one contiguous run of
+// the tile-major bitmaps) and every lane adds
 // its query's rows into vertical counters held as bit slices (Harley-Seal
 // carry-save tree: three logic operations per input row and 32-bit word,
 // for 32 sets at once).  The cutoff test |S_Q| + |B| - 2 <S_Q, B> <= cut is
@@ -102,10 +103,13 @@ k_order_queries(const uint32_t* __restrict__ qbits, uint32_t n_q, uint32_t nbins
 // is the largest |S_Q| or class total of the group, so the padding is small.
 // Steps from D to 16 n + 48 (n: the pair's steps of 16 rows, the same for
 // both halves) read zero rows of class (step + r) mod 4.  Lists are indexed
-// by rank; part k (of 4) adds 8 k bytes to every row offset.
+// by rank; part k (of 4) adds 8 k bytes to every row offset.  The tile-row
+// offsets of each rank's top-A positions (its first layer) are written by
+// rank to rpos.
 __global__ void __launch_bounds__(512)
 k_pass_lists(const uint64_t* __restrict__ sq, uint32_t R, uint32_t L, uint32_t n_q, const uint32_t* __restrict__ order,
-             uint32_t LP, uint32_t* __restrict__ lists, uint32_t* __restrict__ gsteps, uint32_t* __restrict__ any_long) {
+             uint32_t LP, uint32_t* __restrict__ lists, uint32_t* __restrict__ gsteps, uint32_t* __restrict__ any_long,
+             const uint32_t* __restrict__ pos, uint32_t A, uint32_t* __restrict__ rpos) {
   __shared__ uint64_t sk[kPairRanks][64];   // sketches of the 32 queries (R <= 64)
   __shared__ uint32_t cnt[8][4][4];         // [group][query][class]
   __shared__ uint32_t seg_len[8][16];
@@ -116,6 +120,10 @@ k_pass_lists(const uint64_t* __restrict__ sq, uint32_t R, uint32_t L, uint32_t n
   for (uint32_t i = threadIdx.x; i < kPairRanks * R; i += blockDim.x) {
     const uint32_t rr = i / R, t = i % R;
     sk[rr][t] = r0 + rr < n_q ? sq[(uint64_t)order[r0 + rr] * R + t] : 0ull;
+  }
+  for (uint32_t i = threadIdx.x; i < kPairRanks * A; i += blockDim.x) {
+    const uint32_t rr = i / A, t = i % A;
+    if (r0 + rr < n_q) rpos[(uint64_t)(r0 + rr) * A + t] = pos[(uint64_t)order[r0 + rr] * A + t] * kRowBytes;
   }
   __syncthreads();
   for (uint32_t r = 0; r < 4; ++r) {
@@ -214,7 +222,7 @@ hipError_t launch_query_rows(const FilterArgs& a, const uint64_t* sq, uint32_t R
   if (e != hipSuccess) return e;
   const uint32_t pairs = (a.n_q + kPairRanks - 1) / kPairRanks;
   hipLaunchKernelGGL(k_pass_lists, dim3(pairs), dim3(512), 0, st, sq, R, a.L, a.n_q, (const uint32_t*)a.order, a.LP,
-                     a.lists, a.gsteps, a.any_long);
+                     a.lists, a.gsteps, a.any_long, a.pos, a.A, a.rpos);
   return hipGetLastError();
 }
 
@@ -389,11 +397,8 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
   uint32_t* vsl = (uint32_t*)(smem + (size_t)(L + 4) * kRowBytes);  // [2][kVSlices][8]
   uint16_t* nset = (uint16_t*)(vsl + 2 * kVSlices * 8);           // [256]
   const uint64_t tile0 = (uint64_t)tile * 256;
-  const uint64_t wpp = a.ld / 64;
-  for (uint32_t i = threadIdx.x; i < 2 * L; i += blockDim.x) {
-    const uint32_t p = i >> 1, h = i & 1;
-    ((uint4*)rows)[i] = *(const uint4*)(a.planes + (uint64_t)p * wpp + tile0 / 64 + 2 * h);
-  }
+  const uint4* trows = (const uint4*)(a.planes + (uint64_t)tile * L * 4);
+  for (uint32_t i = threadIdx.x; i < 2 * L; i += blockDim.x) ((uint4*)rows)[i] = trows[i];
   if (threadIdx.x < 8) ((uint4*)rows)[2 * L + threadIdx.x] = make_uint4(0, 0, 0, 0);   // zero rows L .. L+3
   const uint32_t w = wave_id(), lane = lane_id();
   if (threadIdx.x < 256) {
@@ -434,11 +439,12 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
     if (NW * (q_part + q_parts * r) * QPW >= a.n_q) break;
     if (qb0 >= a.n_q) continue;
     if (big(qb0 / kPairRanks) == kSmall) continue;   // the other instance's pass
+    // the pass's per-rank values: independent loads, all in flight at once
     const uint32_t qi = qb0 + slot;
     const bool active = qi < a.n_q;
     const uint32_t q = a.order[active ? qi : a.n_q - 1];
     const uint32_t qbq = active ? a.sbits[qi] : 0u;
-    const uint32_t cutq = a.cutoff[q];
+    const uint32_t cutq = (SAMPLE || !active) ? 0u : a.rcut[qi];
     const uint32_t nblk = as_const(a.gsteps)[2 * (qb0 / kPairRanks)];
     // The pass's row lists (QPW ranks of 4 parts) are read through a buffer
     // resource based at the list of its first rank: a scalar base, the
@@ -484,7 +490,7 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
 #pragma unroll
       for (int i = 0; i < W; ++i) m.v[i] = 0;
       for (uint32_t t = 0; t < a.A; ++t) {
-        const Words<W> r = lds_words<W>(a.pos[(uint64_t)q * a.A + t] * kRowBytes + pbytes);
+        const Words<W> r = lds_words<W>((active ? a.rpos[(uint64_t)qi * a.A + t] : 0u) + pbytes);
 #pragma unroll
         for (int i = 0; i < W; ++i) m.v[i] |= r.v[i];
       }

@@ -38,7 +38,7 @@ hipError_t launch_transpose_sketches(const uint8_t* cnt_rm, const uint64_t* bits
                                      uint64_t n_sets, uint64_t ld, uint32_t L,
                                      uint8_t* cnt, uint64_t* bits, hipStream_t st);
 
-// Position-major bitmaps of C >= 1 from the count columns: planes [L][ld/64] u64.
+// Bitmaps of C >= 1 from the count columns, tile-major: planes [ld/256][L][4] u64.
 hipError_t launch_bitmap_planes(const uint8_t* cnt, uint64_t ld, uint32_t L, uint64_t* planes, hipStream_t st);
 
 // Query sketches from query codes: C_Q [n_q][L] u16, S_Q [n_q][R] u64,
@@ -67,7 +67,7 @@ struct FilterArgs {
   uint64_t* cand;              // append mode: [n_q][cap] keys (score << 32 | id)
   uint32_t cap;
   uint32_t* cand_count;        // append mode: [n_q]
-  const uint64_t* planes;      // position-major bitmaps [L][ld/64] (bit j of row p: set j has p)
+  const uint64_t* planes;      // tile-major bitmaps [ld/256][L][4] (bit j % 256 of row p of tile j / 256: set j has p)
   uint32_t L;                  // sketch length
   // bit-sliced scoring (see launch_filter_sliced)
   const uint16_t* spop;        // |B| of every set [ld]
@@ -78,6 +78,8 @@ struct FilterArgs {
   uint32_t* order;             // [n_q] queries by decreasing |S_Q| (blocks of 16)
   uint32_t* sbits;             // [n_q] |S_Q| by rank
   uint32_t* gsteps;            // [2 ceil(n_q / 32)] steps of 16 rows (per half of a rank pair)
+  uint32_t* rpos;              // [n_q rounded up to 32][A] tile-row byte offsets of the top-A positions, by rank
+  uint32_t* rcut;              // [n_q rounded up to 32] cutoff by rank
   uint32_t* fail;              // set to 1 when the result must come from the dense path
   uint32_t* any_long;          // 1 when some rank pair needs the long-sketch instance
   unsigned long long* stats;   // work counters (see bvs_stage_times), may be null
@@ -94,7 +96,8 @@ hipError_t launch_filter_sparse_sample(FilterArgs a, uint32_t n_sample_blocks, h
 hipError_t launch_filter_sparse_append(FilterArgs a, hipStream_t st);
 // Bit-sliced scoring (first layer M <= 1), append mode only: the same
 // appended keys as launch_filter_sparse_append.  launch_query_rows fills
-// lists, qbits and order from the query sketches sq [n_q][R] first.
+// lists, qbits, order and rpos from the query sketches sq [n_q][R] and the
+// top-A positions first.
 hipError_t launch_set_weight(const uint64_t* bits, uint32_t RC, uint64_t ld, uint16_t* w, hipStream_t st);
 hipError_t launch_query_rows(const FilterArgs& a, const uint64_t* sq, uint32_t R, hipStream_t st);
 hipError_t launch_filter_sliced(const FilterArgs& a, hipStream_t st);
@@ -104,8 +107,10 @@ hipError_t launch_filter_sliced(const FilterArgs& a, hipStream_t st);
 hipError_t launch_filter_sliced_sample(FilterArgs a, uint32_t n_sample_blocks, hipStream_t st);
 uint32_t sliced_parts();
 size_t sliced_lds_bytes(uint32_t L);
+// Per-query cutoffs from the sample; with order (ranks -> queries) also
+// written by rank into rcut.
 hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_t r, uint32_t n_q,
-                         uint32_t* cutoff, hipStream_t st);
+                         uint32_t* cutoff, const uint32_t* order, uint32_t* rcut, hipStream_t st);
 hipError_t launch_sort_append(const uint64_t* cand, const uint32_t* cand_count, const uint32_t* cutoff, uint32_t cap,
                               uint32_t T, uint32_t L, uint32_t n_q, uint32_t* f2_ids, uint16_t* f2_scores,
                               uint32_t* f2_count, uint32_t* fail, hipStream_t st);
