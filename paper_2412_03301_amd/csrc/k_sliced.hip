@@ -397,8 +397,20 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
   uint32_t* vsl = (uint32_t*)(smem + (size_t)(L + 4) * kRowBytes);  // [2][kVSlices][8]
   uint16_t* nset = (uint16_t*)(vsl + 2 * kVSlices * 8);           // [256]
   const uint64_t tile0 = (uint64_t)tile * 256;
-  const uint4* trows = (const uint4*)(a.planes + (uint64_t)tile * L * 4);
-  for (uint32_t i = threadIdx.x; i < 2 * L; i += blockDim.x) ((uint4*)rows)[i] = trows[i];
+  // The tile's rows go straight from memory into LDS (16 bytes per lane,
+  // lane-contiguous from a wave-uniform LDS base), all of them in flight at
+  // once (2 L <= 8 blocks of 1024 for L <= 4096); the wait for them comes
+  // before the barrier below.
+  {
+    const uint4* trows = (const uint4*)(a.planes + (uint64_t)tile * L * 4);
+    const uint32_t wv = wave_id(), ln = threadIdx.x % BVS_WAVE;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+      const uint32_t base = BVS_WAVE * wv + 1024 * k;
+      if (base < 2 * L)
+        __builtin_amdgcn_global_load_lds((const void*)(trows + base + ln), (BVS_LDS void*)(rows + base * 16), 16, 0, 0);
+    }
+  }
   if (threadIdx.x < 8) ((uint4*)rows)[2 * L + threadIdx.x] = make_uint4(0, 0, 0, 0);   // zero rows L .. L+3
   const uint32_t w = wave_id(), lane = lane_id();
   if (threadIdx.x < 256) {
@@ -418,6 +430,7 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
       }
     }
   }
+  __builtin_amdgcn_s_waitcnt(0);   // the tile's rows have landed in LDS
   __syncthreads();
 
   const uint32_t part = lane % PARTS, slot = lane / PARTS;
