@@ -30,6 +30,30 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BVS_LDS_AS __attribute__((address_space(3)))
+#else
+#define BVS_LDS_AS
+#endif
+
+// Copy n16 16-byte words from global memory (src) into LDS (dst), both
+// 16-byte aligned, with every word in flight at once: each wave moves whole
+// chunks of 64 words by direct loads into LDS (16 bytes per lane, lane-
+// contiguous from a wave-uniform LDS base), and a ragged tail of fewer than
+// 64 words goes through registers.  The direct loads count as memory loads:
+// wait for them (s_waitcnt) before the workgroup barrier that precedes the
+// first read.
+__device__ __forceinline__ void copy_to_lds(const uint4* __restrict__ src, void* dst, uint32_t n16) {
+  const uint32_t nw = blockDim.x / BVS_WAVE;
+  const uint32_t w = wave_id(), ln = lane_id();
+  const uint32_t full = n16 / BVS_WAVE;
+  for (uint32_t c = w; c < full; c += nw)
+    __builtin_amdgcn_global_load_lds((const void*)(src + (uint64_t)c * BVS_WAVE + ln),
+                                     (BVS_LDS_AS void*)((uint8_t*)dst + (size_t)c * BVS_WAVE * 16), 16, 0, 0);
+  const uint32_t t = full * BVS_WAVE + threadIdx.x;
+  if (t < n16) ((uint4*)dst)[t] = src[t];
+}
+
 // Read-only view of global data in the constant address space: uniform
 // loads through it become scalar loads.  Only for data that no kernel writes
 // while it is being read.

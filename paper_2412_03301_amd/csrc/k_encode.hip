@@ -181,8 +181,9 @@ __device__ __forceinline__ EncodeShared encode_setup(const HashGeom& g, uint8_t*
   const uint32_t w = wave_id();
   sh.av = (int16_t*)(smem + tab_bytes) + w * (g.dim_padded + 8);
   const uint32_t n16 = g.L * g.SP / 8;
-  for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) ((uint4*)sh.idx)[i] = ((const uint4*)g.idx)[i];
+  copy_to_lds((const uint4*)g.idx, sh.idx, n16);
   if (lane_id() < 8) sh.av[g.dim_padded + lane_id()] = 0;
+  __builtin_amdgcn_s_waitcnt(0);   // the table has landed in LDS
   __syncthreads();
   return sh;
 }

@@ -204,7 +204,7 @@ k_full_scan(const uint16_t* __restrict__ pos, const uint64_t* __restrict__ offse
   const uint32_t q0 = pk.x, nq = pk.y, ng = pk.z;
   {
     const uint4* src = (const uint4*)(table + (uint64_t)blockIdx.y * GP * L);
-    for (uint32_t i = threadIdx.x; i < ng * L / 2; i += blockDim.x) ((uint4*)tab)[i] = src[i];
+    copy_to_lds(src, tab, ng * L / 2);
   }
   uint32_t sl[kPackQ + 1];
   {
@@ -212,6 +212,7 @@ k_full_scan(const uint16_t* __restrict__ pos, const uint64_t* __restrict__ offse
 #pragma unroll
     for (int i = 0; i <= kPackQ; ++i) sl[i] = (uint32_t)(q_off[q0 + min((uint32_t)i, nq)] - v0);
   }
+  __builtin_amdgcn_s_waitcnt(0);   // the query table has landed in LDS
   __syncthreads();
   const uint64_t it = (uint64_t)blockIdx.x * kScanThreads + threadIdx.x;
   if (it >= n_sets) return;

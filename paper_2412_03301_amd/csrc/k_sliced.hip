@@ -397,20 +397,9 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
   uint32_t* vsl = (uint32_t*)(smem + (size_t)(L + 4) * kRowBytes);  // [2][kVSlices][8]
   uint16_t* nset = (uint16_t*)(vsl + 2 * kVSlices * 8);           // [256]
   const uint64_t tile0 = (uint64_t)tile * 256;
-  // The tile's rows go straight from memory into LDS (16 bytes per lane,
-  // lane-contiguous from a wave-uniform LDS base), all of them in flight at
-  // once (2 L <= 8 blocks of 1024 for L <= 4096); the wait for them comes
-  // before the barrier below.
-  {
-    const uint4* trows = (const uint4*)(a.planes + (uint64_t)tile * L * 4);
-    const uint32_t wv = wave_id(), ln = threadIdx.x % BVS_WAVE;
-#pragma unroll
-    for (uint32_t k = 0; k < 8; ++k) {
-      const uint32_t base = BVS_WAVE * wv + 1024 * k;
-      if (base < 2 * L)
-        __builtin_amdgcn_global_load_lds((const void*)(trows + base + ln), (BVS_LDS void*)(rows + base * 16), 16, 0, 0);
-    }
-  }
+  // the tile's rows go straight from memory into LDS, all in flight at once
+  // (the wait for them comes before the barrier below)
+  copy_to_lds((const uint4*)(a.planes + (uint64_t)tile * L * 4), rows, 2 * L);
   if (threadIdx.x < 8) ((uint4*)rows)[2 * L + threadIdx.x] = make_uint4(0, 0, 0, 0);   // zero rows L .. L+3
   const uint32_t w = wave_id(), lane = lane_id();
   if (threadIdx.x < 256) {
@@ -452,12 +441,16 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
     if (NW * (q_part + q_parts * r) * QPW >= a.n_q) break;
     if (qb0 >= a.n_q) continue;
     if (big(qb0 / kPairRanks) == kSmall) continue;   // the other instance's pass
-    // the pass's per-rank values: independent loads, all in flight at once
+    // the pass's per-rank values: unconditional loads at a clamped rank (no
+    // branches around them), all in flight at once
     const uint32_t qi = qb0 + slot;
     const bool active = qi < a.n_q;
-    const uint32_t q = a.order[active ? qi : a.n_q - 1];
-    const uint32_t qbq = active ? a.sbits[qi] : 0u;
-    const uint32_t cutq = (SAMPLE || !active) ? 0u : a.rcut[qi];
+    const uint32_t qc = active ? qi : a.n_q - 1;
+    const uint32_t q = a.order[qc];
+    const uint32_t sbq = a.sbits[qc];
+    const uint32_t ctq = SAMPLE ? 0u : a.rcut[qc];
+    const uint32_t qbq = active ? sbq : 0u;
+    const uint32_t cutq = active ? ctq : 0u;
     const uint32_t nblk = as_const(a.gsteps)[2 * (qb0 / kPairRanks)];
     // The pass's row lists (QPW ranks of 4 parts) are read through a buffer
     // resource based at the list of its first rank: a scalar base, the
@@ -481,6 +474,34 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
     uint4 X[4], Y[4];
     list_offsets(rs, voff, 0, X);
     list_offsets(rs, voff, 1, Y);
+    // first layer (C[p] >= 1 at one of the top-A positions): the OR of those
+    // rows of the tile, their offsets loaded four at a time (a repeated last
+    // offset ORs the same row again)
+    Words<W> m;
+    if (a.M == 0) {
+      m = valid;
+    } else {
+#pragma unroll
+      for (int i = 0; i < W; ++i) m.v[i] = 0;
+      for (uint32_t t0 = 0; t0 < a.A; t0 += 4) {
+        uint32_t o[4];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) o[j] = a.rpos[(uint64_t)qc * a.A + min(t0 + j, a.A - 1)];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+          const Words<W> r = lds_words<W>(o[j] + pbytes);
+#pragma unroll
+          for (int i = 0; i < W; ++i) m.v[i] |= r.v[i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < W; ++i) m.v[i] &= valid.v[i];
+    }
+    if (!active) {
+#pragma unroll
+      for (int i = 0; i < W; ++i) m.v[i] = 0;
+    }
+
     uint32_t b = 0;
     for (; b + 1 < nblk; b += 2) {
       const Words<W> sA = sixteen_rows<W, S>(X, c);
@@ -495,25 +516,6 @@ __device__ __forceinline__ void sliced_tile(const FilterArgs& a, uint32_t tile, 
     }
     if (b < nblk) add_carry<4, W, S>(sixteen_rows<W, S>(X, c), c);
 
-    // first layer
-    Words<W> m;
-    if (a.M == 0) {
-      m = valid;
-    } else {
-#pragma unroll
-      for (int i = 0; i < W; ++i) m.v[i] = 0;
-      for (uint32_t t = 0; t < a.A; ++t) {
-        const Words<W> r = lds_words<W>((active ? a.rpos[(uint64_t)qi * a.A + t] : 0u) + pbytes);
-#pragma unroll
-        for (int i = 0; i < W; ++i) m.v[i] |= r.v[i];
-      }
-#pragma unroll
-      for (int i = 0; i < W; ++i) m.v[i] &= valid.v[i];
-    }
-    if (!active) {
-#pragma unroll
-      for (int i = 0; i < W; ++i) m.v[i] = 0;
-    }
 #pragma unroll
     for (int i = 0; i < W; ++i) pairs += popc32(m.v[i]);
     if constexpr (SAMPLE) {
