@@ -36,6 +36,37 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 #define BVS_LDS_AS
 #endif
 
+// Copy rows 0 .. rows - 1 of NP row planes into LDS: row r of plane k is
+// c16n 16-byte chunks at src[k] + r * sstride and goes to dst[k] + r *
+// dstride; rows at or past mq become zero.  Each thread has four chunks of
+// every plane in flight at once (their loads read row min(r, mq - 1), always
+// inside the source).  rows must be 0 when mq is 0.  No barrier.
+template <int NP>
+__device__ __forceinline__ void stage_rows(const uint8_t* const (&src)[NP], uint8_t* const (&dst)[NP], uint64_t sstride,
+                                           uint32_t dstride, uint32_t c16n, uint32_t rows, uint32_t mq) {
+  const uint32_t n = rows * c16n, bd = blockDim.x;
+  for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 4 * bd) {
+    uint4 x[NP][4];
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+      const uint32_t i = min(i0 + u * bd, n - 1);
+      const uint32_t r = min(i / c16n, mq - 1), c = i % c16n;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) x[k][u] = *(const uint4*)(src[k] + r * sstride + 16 * c);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + u * bd;
+      if (i < n) {
+        const uint32_t r = i / c16n, c = i % c16n;
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+          *(uint4*)(dst[k] + r * dstride + 16 * c) = r < mq ? x[k][u] : make_uint4(0, 0, 0, 0);
+      }
+    }
+  }
+}
+
 // Copy n16 16-byte words from global memory (src) into LDS (dst), both
 // 16-byte aligned, with every word in flight at once: each wave moves whole
 // chunks of 64 words by direct loads into LDS (16 bytes per lane, lane-

@@ -463,16 +463,10 @@ __device__ __forceinline__ QView stage_query(const HausQ& qs, uint32_t q, uint32
   uint8_t* ql_s = smem + (size_t)lds_rows * QS;
   uint32_t* qn_s = (uint32_t*)(smem + (size_t)2 * lds_rows * QS);
   uint2* qs_s = (uint2*)(qn_s + lds_rows);
-  const uint32_t c16n = dp / 16;
-  for (uint32_t i = threadIdx.x; i < rows * c16n; i += blockDim.x) {
-    const uint32_t r = i / c16n, c = i % c16n;
-    uint4 h = make_uint4(0, 0, 0, 0), l = make_uint4(0, 0, 0, 0);
-    if (r < v.mq) {
-      h = *(const uint4*)(qs.hi + (o0 + r) * dp + 16 * c);
-      l = *(const uint4*)(qs.lo + (o0 + r) * dp + 16 * c);
-    }
-    *(uint4*)(qh_s + r * QS + 16 * c) = h;
-    *(uint4*)(ql_s + r * QS + 16 * c) = l;
+  {
+    const uint8_t* const src[2] = {(const uint8_t*)qs.hi + o0 * dp, qs.lo + o0 * dp};
+    uint8_t* const dst[2] = {qh_s, ql_s};
+    stage_rows<2>(src, dst, dp, QS, dp / 16, rows, v.mq);
   }
   for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x) {
     qn_s[r] = r < v.mq ? qs.norms[o0 + r] : 0u;
@@ -504,12 +498,10 @@ __device__ __forceinline__ QView stage_query_screen(const HausQ& qs, uint32_t q,
   const uint32_t QS = q_row_stride(dp);
   uint8_t* qh = smem;
   uint2* qp = (uint2*)(smem + (size_t)rows * QS);
-  const uint32_t c16n = dp / 16;
-  for (uint32_t i = threadIdx.x; i < rows * c16n; i += blockDim.x) {
-    const uint32_t r = i / c16n, c = i % c16n;
-    uint4 h = make_uint4(0, 0, 0, 0);
-    if (r < v.mq) h = *(const uint4*)(qs.hi + (o0 + r) * dp + 16 * c);
-    *(uint4*)(qh + r * QS + 16 * c) = h;
+  {
+    const uint8_t* const src[1] = {(const uint8_t*)qs.hi + o0 * dp};
+    uint8_t* const dst[1] = {qh};
+    stage_rows<1>(src, dst, dp, QS, dp / 16, rows, v.mq);
   }
   for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x)
     qp[r] = r < v.mq ? qs.scr[o0 + r] : make_uint2(kScreenPad, 0u);

@@ -289,12 +289,10 @@ __device__ __forceinline__ LpView lp_stage(const LowpQ& qs, uint32_t q, uint32_t
   const uint32_t RB = qs.row_bytes, SS = RB + 16;
   const uint32_t rows = v.nqt_s * 16;
   uint32_t* s_norm = (uint32_t*)(smem + (size_t)lds_rows * SS);
-  const uint32_t c16n = RB / 16;
-  for (uint32_t i = threadIdx.x; i < rows * c16n; i += blockDim.x) {
-    const uint32_t r = i / c16n, c = i % c16n;
-    uint4 x = make_uint4(0, 0, 0, 0);
-    if (r < v.mq) x = *(const uint4*)(qs.rows + (o0 + r) * RB + 16 * c);
-    *(uint4*)(smem + r * SS + 16 * c) = x;
+  {
+    const uint8_t* const src[1] = {qs.rows + o0 * RB};
+    uint8_t* const dst[1] = {smem};
+    stage_rows<1>(src, dst, RB, SS, RB / 16, rows, v.mq);
   }
   for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x) s_norm[r] = r < v.mq ? qs.norms[o0 + r] : 0u;
   v.s_rows = smem;
