@@ -390,6 +390,7 @@ struct QueryWs {
   uint32_t* thr;          // [n_q] re-rank bound
   uint32_t* surv;         // [n_q][T] candidates that passed the re-rank screen
   uint32_t* surv_count;   // [n_q]
+  uint32_t* qids;         // brute force: the queries grouped by size (haus_all_list_words)
   unsigned long long* stats;   // [kStatSlots][kStatCounters] work counters
   uint64_t* topk_tmp;
   // learned projection: query rows in bfloat16, hidden layer, outputs
@@ -537,6 +538,7 @@ void layout_brute(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, Que
   w->qnorm = c.take<uint32_t>(NQ);
   w->h2 = c.take<uint32_t>((uint64_t)n_q * ix->n);
   w->topk_tmp = c.take<uint64_t>(topk_tmp_words(ix->n, n_q, kMaxK));
+  w->qids = c.take<uint32_t>(haus_all_list_words(n_q));
 }
 
 bvs_status check_queries(const bvs_index* ix, const float* d_q, const uint64_t* h_q_off, uint32_t n_q,
@@ -794,8 +796,9 @@ bvs_status brute_impl(const bvs_index* ix, uint32_t metric, const float* d_q, co
   layout_brute(c, ix, n_q, NQ, &w);
   CallProf prof(st);
   BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
-  HIP_TRY(staged(prof, S_BRUTE,
-                 [&] { return launch_haus_all(haus_db(ix, metric), haus_q(w, n_q, max_rows), w.h2, st); }));
+  HIP_TRY(staged(prof, S_BRUTE, [&] {
+    return launch_haus_all(haus_db(ix, metric), haus_q(w, n_q, max_rows), w.h2, h_q_off, w.qids, st);
+  }));
   HIP_TRY(staged(prof, S_TOPK, [&] {
     return launch_topk(w.h2, nullptr, nullptr, ix->n, ix->n, n_q, k, w.topk_tmp, d_ids, d_dist, d_count, st,
                        metric == kMetricMeanMin);
@@ -1142,7 +1145,8 @@ bvs_status bvs_hausdorff_all(const bvs_index* ix, const float* d_q, const uint64
   layout_brute(c, ix, n_q, NQ, &w);
   CallProf prof(st);
   BVS_TRY(prepare_queries(ix, d_q, h_q_off, n_q, w, st, prof));
-  HIP_TRY(staged(prof, S_BRUTE, [&] { return launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), d_h2, st); }));
+  HIP_TRY(staged(prof, S_BRUTE,
+                 [&] { return launch_haus_all(haus_db(ix), haus_q(w, n_q, max_rows), d_h2, h_q_off, w.qids, st); }));
   const bvs_status s = read_status(w.status, st, "queries");
   prof.finish();
   return s;
@@ -1721,7 +1725,7 @@ struct TrainWs {
   uint16_t* dy16;        // [cap][L]
   float* dh;             // [cap][H]
   uint16_t* dp16;        // [cap][H]
-  float* loss;           // [1]
+  float* loss;           // [4]: the batch loss (float), then the epoch sum (double at word 2)
   float* grad;           // packed like the weights
   uint16_t* w16;         // packed bfloat16 weights
   float* adam_m;
@@ -1765,14 +1769,48 @@ bvs_status check_train_config(const bvs_train_config* t) {
 
 // One batch of triplets: forward, loss, gradients into w.grad (packed).
 // Sets are rows h_off[s] .. h_off[s+1] of d_vectors.
+// Pinned host buffers that a batch's row and triplet lists are built in and
+// copied from; `copied` is recorded once the copies have been enqueued, and
+// the buffers are refilled only after it has completed, so the host builds
+// the next batch while the device trains on this one.
+struct TrainStage {
+  uint64_t* rows = nullptr;   // [cap]
+  uint32_t* roff = nullptr;   // [3 batch_triplets + 1]
+  uint32_t* tl = nullptr;     // [3 batch_triplets]
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+  TrainStage() = default;
+  TrainStage(const TrainStage&) = delete;
+  TrainStage& operator=(const TrainStage&) = delete;
+  ~TrainStage() {
+    if (copied) {
+      (void)hipEventSynchronize(copied);
+      (void)hipEventDestroy(copied);
+    }
+    if (rows) (void)hipHostFree(rows);
+    if (roff) (void)hipHostFree(roff);
+    if (tl) (void)hipHostFree(tl);
+  }
+  hipError_t alloc(uint64_t cap, uint32_t batch_triplets) {
+    hipError_t e = hipHostMalloc((void**)&rows, std::max<uint64_t>(cap, 1) * 8, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&roff, (3ull * batch_triplets + 1) * 4, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&tl, 3ull * batch_triplets * 4, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&copied, hipEventDisableTiming);
+    return e;
+  }
+};
+
 bvs_status train_batch(const bvs_train_config& t, const float* d_vectors, const uint64_t* h_off, uint64_t n_sets,
                        const uint32_t* trips, uint32_t nt, uint64_t cap, const uint16_t* w16, const float* w32,
-                       TrainWs& w, hipStream_t st, std::vector<uint64_t>& rows, std::vector<uint32_t>& roff,
-                       std::vector<uint32_t>& tl) {
+                       TrainWs& w, hipStream_t st, TrainStage& hs) {
+  if (hs.pending) {
+    HIP_TRY(hipEventSynchronize(hs.copied));
+    hs.pending = false;
+  }
   // distinct sets of the batch, in first-seen order
   std::map<uint32_t, uint32_t> local;
   std::vector<uint32_t> sets;
-  tl.resize(3ull * nt);
+  uint32_t* tl = hs.tl;
   for (uint32_t i = 0; i < nt; ++i) {
     for (int k = 0; k < 3; ++k) {
       const uint32_t sid = trips[3ull * i + k];
@@ -1785,21 +1823,26 @@ bvs_status train_batch(const bvs_train_config& t, const float* d_vectors, const 
       tl[3ull * i + k] = it->second;
     }
   }
-  rows.clear();
-  roff.assign(1, 0);
-  for (uint32_t sid : sets) {
-    for (uint64_t r = h_off[sid]; r < h_off[sid + 1]; ++r) rows.push_back(r);
-    roff.push_back((uint32_t)rows.size());
-  }
-  const uint64_t nb = rows.size();
+  uint64_t nb = 0;
+  for (uint32_t sid : sets) nb += h_off[sid + 1] - h_off[sid];
   if (nb > cap)
     return fail(BVS_ENOSPC, "a batch holds %llu rows; the workspace fits %llu", (unsigned long long)nb,
                 (unsigned long long)cap);
+  uint64_t* rows = hs.rows;
+  uint32_t* roff = hs.roff;
+  uint64_t at = 0;
+  roff[0] = 0;
+  for (size_t i = 0; i < sets.size(); ++i) {
+    for (uint64_t r = h_off[sets[i]]; r < h_off[sets[i] + 1]; ++r) rows[at++] = r;
+    roff[i + 1] = (uint32_t)at;
+  }
   const uint32_t d = t.dim, H = t.hidden, L = t.code_bits;
   const uint32_t ns = (uint32_t)sets.size();
-  HIP_TRY(hipMemcpyAsync(w.rows, rows.data(), nb * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(w.row_off, roff.data(), roff.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(w.trip, tl.data(), tl.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w.rows, rows, nb * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w.row_off, roff, (sets.size() + 1) * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w.trip, tl, 3ull * nt * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(hs.copied, st));
+  hs.pending = true;
   const uint16_t* W1 = w16;
   const uint16_t* W2 = w16 + (uint64_t)H * d + H;
   const float* b1 = w32 + (uint64_t)H * d;
@@ -1891,8 +1934,10 @@ bvs_status train_impl(const bvs_train_config* t, const float* d_vectors, const u
   HIP_TRY(launch_f32_to_bf16(d_weights, nw, w.w16, st));
   std::vector<uint64_t> order(n_triplets);
   std::vector<uint32_t> batch;
-  std::vector<uint64_t> rows;
-  std::vector<uint32_t> roff, tl;
+  TrainStage hs[2];
+  HIP_TRY(hs[0].alloc(cap, t->batch_triplets));
+  HIP_TRY(hs[1].alloc(cap, t->batch_triplets));
+  double* d_ep_loss = (double*)(w.loss + 2);
   uint32_t step = (uint32_t)hdr[0];
   for (uint32_t ep = 0; ep < t->epochs; ++ep) {
     const uint64_t e_abs = hdr[1] + ep;
@@ -1906,23 +1951,26 @@ bvs_status train_impl(const bvs_train_config* t, const float* d_vectors, const u
     };
     for (uint64_t i = 0; i < n_triplets; ++i) order[i] = i;
     for (uint64_t i = n_triplets - 1; i > 0; --i) std::swap(order[i], order[next() % (i + 1)]);
-    double ep_loss = 0.0;
+    HIP_TRY(launch_fill_u32((uint32_t*)d_ep_loss, 2, 0u, st));
     uint64_t n_batches = 0;
     for (uint64_t b0 = 0; b0 < n_triplets; b0 += t->batch_triplets) {
       const uint32_t nt = (uint32_t)std::min<uint64_t>(t->batch_triplets, n_triplets - b0);
       batch.resize(3ull * nt);
       for (uint32_t i = 0; i < nt; ++i)
         for (int k = 0; k < 3; ++k) batch[3ull * i + k] = h_triplets[3 * order[b0 + i] + k];
-      BVS_TRY(train_batch(*t, d_vectors, h_offsets, n_sets, batch.data(), nt, cap, w.w16, d_weights, w, st, rows,
-                          roff, tl));
+      BVS_TRY(train_batch(*t, d_vectors, h_offsets, n_sets, batch.data(), nt, cap, w.w16, d_weights, w, st,
+                          hs[n_batches & 1]));
       HIP_TRY(launch_adam(d_weights, w.grad, adam_m, adam_v, nw, t->lr, 0.9f, 0.999f, 1e-8f, ++step, w.w16, st));
-      float l = 0.f;
-      HIP_TRY(hipMemcpyAsync(&l, w.loss, 4, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      ep_loss += l;
+      HIP_TRY(launch_add_loss(w.loss, d_ep_loss, st));
       ++n_batches;
     }
-    if (h_epoch_loss) h_epoch_loss[ep] = (float)(ep_loss / std::max<uint64_t>(1, n_batches));
+    if (h_epoch_loss) {
+      // the one host round trip of an epoch
+      double ep_loss = 0.0;
+      HIP_TRY(hipMemcpyAsync(&ep_loss, d_ep_loss, sizeof ep_loss, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      h_epoch_loss[ep] = (float)(ep_loss / std::max<uint64_t>(1, n_batches));
+    }
   }
   if (d_hdr) {
     hdr[0] = step;
@@ -2095,11 +2143,10 @@ bvs_status bvs_train_gradients(const bvs_train_config* t, const float* d_vectors
   TrainWs w;
   layout_train(c, *t, cap, &w);
   const uint64_t nw = mlp_floats(t->dim, t->hidden, t->code_bits);
-  std::vector<uint64_t> rows;
-  std::vector<uint32_t> roff, tl;
+  TrainStage hs;
+  HIP_TRY(hs.alloc(cap, t->batch_triplets));
   HIP_TRY(launch_f32_to_bf16(d_weights, nw, w.w16, st));
-  BVS_TRY(train_batch(*t, d_vectors, h_offsets, n_sets, h_triplets, n_triplets, cap, w.w16, d_weights, w, st, rows,
-                      roff, tl));
+  BVS_TRY(train_batch(*t, d_vectors, h_offsets, n_sets, h_triplets, n_triplets, cap, w.w16, d_weights, w, st, hs));
   HIP_TRY(hipMemcpyAsync(d_grads, w.grad, nw * 4, hipMemcpyDeviceToDevice, st));
   float l = 0.f;
   HIP_TRY(hipMemcpyAsync(&l, w.loss, 4, hipMemcpyDeviceToHost, st));

@@ -148,18 +148,21 @@ hipError_t launch_kth_bound(const uint32_t* vals, const uint32_t* count, uint32_
 // All-sets mode.  Work units (query, chunk of kAllChunk sets) are numbered so
 // that units sharing a chunk of the database run at the same time on the same
 // XCD: consecutive workgroup ids are dealt round-robin over the 8 XCDs, so the
-// unit index is rebuilt from (id % 8, id / 8).
+// unit index is rebuilt from (id % 8, id / 8).  The queries are qids[0 ..
+// nql) (a class of the size grouping below).
 static constexpr uint32_t kAllChunk = 128;
+static constexpr uint32_t kNoQuery = 0xFFFFFFFFu;   // padding of a query tile
 
 template <int KS, int MAXQT, bool HASG>
 __global__ void __launch_bounds__(64 * kHausWaves)
-k_haus_all(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, uint32_t* __restrict__ h2) {
+k_haus_all(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, const uint32_t* __restrict__ qids, uint32_t nql,
+           uint32_t* __restrict__ h2) {
   extern __shared__ __align__(16) uint8_t smem[];
   const uint64_t b = blockIdx.x, nb = gridDim.x;   // nb is a multiple of 8
   const uint64_t unit = (b % 8) * (nb / 8) + b / 8;
   if (unit >= n_units) return;
-  const uint32_t q = (uint32_t)(unit % qs.n_q);
-  const uint32_t chunk = (uint32_t)(unit / qs.n_q);
+  const uint32_t q = qids[unit % nql];
+  const uint32_t chunk = (uint32_t)(unit / nql);
   const uint64_t s0 = (uint64_t)chunk * kAllChunk;
   const uint64_t s1 = min(db.n_sets, s0 + kAllChunk);
   const QView qv = stage_query(qs, q, KS * 64, lds_rows, smem);
@@ -172,27 +175,33 @@ k_haus_all(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, uint32_t* _
   }
 }
 
-// Query-tiled all-sets mode: a unit is (tile of QT consecutive queries, chunk
-// of kAllChunk sets); the workgroup stages the QT queries (lds_rows rows
-// each, the rest read from global memory) and each wave computes its sets
-// against all of them (haus_multi), so every set is read once per QT
-// queries.  Units are numbered over the XCDs as in k_haus_all.
+// Query-tiled all-sets mode: a unit is (tile of QT queries, chunk of
+// kAllChunk sets); the tile's queries are qids[QT tile .. + QT) (kNoQuery
+// pads the last tile of a class; its first entry is always a query).  The
+// workgroup stages the QT queries (lds_rows rows each, the rest read from
+// global memory) and each wave computes its sets against all of them
+// (haus_multi), so every set is read once per QT queries.  Units are numbered
+// over the XCDs as in k_haus_all.
 template <int KS, int MAXQT, bool HASG, int QT>
 __global__ void __launch_bounds__(64 * kHausWaves)
-k_haus_all_qt(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, uint32_t* __restrict__ h2) {
+k_haus_all_qt(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, const uint32_t* __restrict__ qids,
+              uint32_t n_tiles, uint32_t* __restrict__ h2) {
   extern __shared__ __align__(16) uint8_t smem[];
   const uint64_t b = blockIdx.x, nb = gridDim.x;   // nb is a multiple of 8
   const uint64_t unit = (b % 8) * (nb / 8) + b / 8;
   if (unit >= n_units) return;
-  const uint32_t n_tiles = (qs.n_q + QT - 1) / QT;
-  const uint32_t q0 = (uint32_t)(unit % n_tiles) * QT;
+  const uint32_t* tq = qids + (uint64_t)(unit % n_tiles) * QT;
   const uint32_t chunk = (uint32_t)(unit / n_tiles);
   const uint64_t s0 = (uint64_t)chunk * kAllChunk;
   const uint64_t s1 = min(db.n_sets, s0 + kAllChunk);
   const size_t per_q = haus_stage_bytes(lds_rows, KS * 64);
+  uint32_t qid[QT];
   QView qv[QT];
 #pragma unroll
-  for (int i = 0; i < QT; ++i) qv[i] = stage_query(qs, min(q0 + i, qs.n_q - 1), KS * 64, lds_rows, smem + i * per_q);
+  for (int i = 0; i < QT; ++i) {
+    qid[i] = tq[i];
+    qv[i] = stage_query(qs, qid[i] == kNoQuery ? tq[0] : qid[i], KS * 64, lds_rows, smem + i * per_q);
+  }
   const uint32_t w = wave_id();
   for (uint64_t j = s0 + w; j < s1; j += kHausWaves) {
     const uint64_t o0 = db.offsets[j];
@@ -202,7 +211,7 @@ k_haus_all_qt(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, uint32_t
     if (lane_id() == 0) {
 #pragma unroll
       for (int i = 0; i < QT; ++i)
-        if (q0 + i < qs.n_q) h2[(uint64_t)(q0 + i) * db.n_sets + j] = out[i];
+        if (qid[i] != kNoQuery) h2[(uint64_t)qid[i] * db.n_sets + j] = out[i];
     }
   }
 }
@@ -323,68 +332,123 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
 // Queries per tile of the all-sets kernel and the rows each stages: four
 // queries when each keeps at least 48 staged rows within the budget (or all of
 // its rows), else two, else one (k_haus_all).
-static void all_tile_shape(uint32_t max_rows, uint32_t dp, uint32_t n_q, uint32_t* qt, uint32_t* rows) {
-  const uint32_t need = std::min<uint32_t>((max_rows + 15) / 16 * 16, kMaxQueryTiles * 16);
-  for (uint32_t t : {4u, 2u}) {
-    if (n_q < t || need > 8 * 16) continue;   // haus_multi keeps up to 8 query tiles per query
-    uint32_t r = need;
-    while (r > 16 && t * haus_stage_bytes(r, dp) > kStageBudget) r -= 16;
-    if (t * haus_stage_bytes(r, dp) <= kStageBudget && (r >= 48 || r == need)) {
-      *qt = t;
-      *rows = r;
-      return;
+// The brute force groups the queries by their tiles of 16 vectors: those of
+// one or two tiles share a pass over the database QT = 8 or 4 at a time,
+// those of three to eight tiles two at a time (up to 64 rows staged, the
+// rest from global memory), larger ones one at a time; QT is the largest of
+// {8, 4, 2} whose staged rows fit the LDS budget at dp (else one at a time).
+// Each class is one launch over its tiles of query ids.
+struct AllClass {
+  uint32_t qt, rows, mqt;   // queries per tile, staged rows per query, tiles kept per query
+  bool hg;                  // query tiles past the staged rows come from global memory
+};
+
+static AllClass all_class(uint32_t nqt, uint32_t dp) {
+  AllClass c{1, 0, 16, false};
+  if (nqt > 8) {
+    c.rows = haus_lds_rows(nqt * 16, dp);
+    c.hg = c.rows < nqt * 16;
+    return c;
+  }
+  const uint32_t need = nqt * 16;
+  c.mqt = nqt <= 2 ? 2 : nqt <= 4 ? 4 : 8;
+  c.rows = std::min<uint32_t>(need, 64);
+  for (uint32_t t : {8u, 4u, 2u}) {
+    if (t == 8 && c.mqt != 2) continue;   // eight queries per tile only for the smallest class
+    if (t * haus_stage_bytes(c.rows, dp) <= kStageBudget) {
+      c.qt = t;
+      c.hg = c.rows < need;
+      return c;
     }
   }
-  *qt = 1;
-  *rows = haus_lds_rows(max_rows, dp);
+  c.qt = 1;
+  c.mqt = 16;
+  c.rows = haus_lds_rows(need, dp);
+  c.hg = c.rows < need;
+  return c;
 }
 
-hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipStream_t st) {
+template <typename F>
+static hipError_t dispatch_ks(uint32_t dp, F&& f) {
+  switch (dp / 64) {
+    case 1: return f(std::integral_constant<int, 1>());
+    case 2: return f(std::integral_constant<int, 2>());
+    case 4: return f(std::integral_constant<int, 4>());
+    case 6: return f(std::integral_constant<int, 6>());
+    case 8: return f(std::integral_constant<int, 8>());
+    case 12: return f(std::integral_constant<int, 12>());
+    case 16: return f(std::integral_constant<int, 16>());
+    default: return hipErrorInvalidValue;
+  }
+}
+
+uint32_t haus_all_list_words(uint32_t n_q) { return n_q + 7 * 5; }   // padding: < 8 per class
+
+hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, const uint64_t* h_q_off, uint32_t* d_qids,
+                           hipStream_t st) {
   if (q.n_q == 0 || db.n_sets == 0) return hipSuccess;
-  uint32_t QT = 1, trows = 0;
-  all_tile_shape(q.max_rows, db.dp, q.n_q, &QT, &trows);
-  if (QT > 1) {
-    const uint32_t n_chunks = (uint32_t)((db.n_sets + kAllChunk - 1) / kAllChunk);
-    const uint64_t n_units = (uint64_t)n_chunks * ((q.n_q + QT - 1) / QT);
+  // classes: 1, 2, 3-4, 5-8 and more than 8 query tiles
+  std::vector<uint32_t> cls[5];
+  for (uint32_t i = 0; i < q.n_q; ++i) {
+    const uint32_t nqt = (uint32_t)((h_q_off[i + 1] - h_q_off[i] + 15) / 16);
+    cls[nqt <= 1 ? 0 : nqt <= 2 ? 1 : nqt <= 4 ? 2 : nqt <= 8 ? 3 : 4].push_back(i);
+  }
+  static constexpr uint32_t kClassTiles[5] = {1, 2, 4, 8, 16};
+  std::vector<uint32_t> list;
+  AllClass cc[5];
+  size_t at[5];
+  for (int c = 0; c < 5; ++c) {
+    cc[c] = all_class(kClassTiles[c], db.dp);
+    at[c] = list.size();
+    list.insert(list.end(), cls[c].begin(), cls[c].end());
+    while ((list.size() - at[c]) % cc[c].qt) list.push_back(kNoQuery);
+  }
+  if (list.size() > haus_all_list_words(q.n_q)) return hipErrorInvalidValue;
+  hipError_t e = hipMemcpyAsync(d_qids, list.data(), list.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // the list is a local
+  if (e != hipSuccess) return e;
+  const uint32_t n_chunks = (uint32_t)((db.n_sets + kAllChunk - 1) / kAllChunk);
+  for (int c = 0; c < 5; ++c) {
+    if (cls[c].empty()) continue;
+    const AllClass k = cc[c];
+    const uint32_t* qids = d_qids + at[c];
+    const uint32_t n_list = (uint32_t)((c + 1 < 5 ? at[c + 1] : list.size()) - at[c]);
+    const uint32_t n_tiles = n_list / k.qt;
+    const uint64_t n_units = (uint64_t)n_chunks * n_tiles;
     const uint64_t grid = align_up(n_units, 8);
     if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    const size_t lds = QT * haus_stage_bytes(trows, db.dp);
-    return dispatch_haus(db.dp, q.max_rows, trows, [&](auto ks, auto mqt, auto hg) -> hipError_t {
-      constexpr int KS = decltype(ks)::value, MQ = decltype(mqt)::value;
-      constexpr bool HG = decltype(hg)::value;
-      auto go = [&](auto kern) -> hipError_t {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64 * kHausWaves), lds, st, db, q, trows, n_units, h2);
+    const size_t lds = k.qt * haus_stage_bytes(k.rows, db.dp);
+    e = dispatch_ks(db.dp, [&](auto ks) -> hipError_t {
+      constexpr int KS = decltype(ks)::value;
+      auto go = [&](auto kern, auto... args) -> hipError_t {
+        hipError_t r = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64 * kHausWaves), lds, st, db, q, k.rows, n_units,
+                           args..., h2);
         return hipGetLastError();
       };
-      if constexpr (MQ > 8) {
-        return hipErrorInvalidValue;
-      } else {
-        if (QT == 4) return go(k_haus_all_qt<KS, MQ, HG, 4>);
-        return go(k_haus_all_qt<KS, MQ, HG, 2>);
+      if (k.qt == 1) {
+        if (k.hg) {
+          if constexpr (haus_variant_used<KS, 16, true>()) return go(k_haus_all<KS, 16, true>, qids, n_list);
+          return hipErrorInvalidValue;
+        }
+        return go(k_haus_all<KS, 16, false>, qids, n_list);
       }
+      if (k.qt == 8) return go(k_haus_all_qt<KS, 2, false, 8>, qids, n_tiles);
+      auto by_mq = [&](auto mq) -> hipError_t {
+        constexpr int MQ = decltype(mq)::value;
+        if (k.qt == 4) return k.hg ? go(k_haus_all_qt<KS, MQ, true, 4>, qids, n_tiles)
+                                   : go(k_haus_all_qt<KS, MQ, false, 4>, qids, n_tiles);
+        return k.hg ? go(k_haus_all_qt<KS, MQ, true, 2>, qids, n_tiles)
+                    : go(k_haus_all_qt<KS, MQ, false, 2>, qids, n_tiles);
+      };
+      if (k.mqt == 2) return by_mq(std::integral_constant<int, 2>());
+      if (k.mqt == 4) return by_mq(std::integral_constant<int, 4>());
+      return by_mq(std::integral_constant<int, 8>());
     });
+    if (e != hipSuccess) return e;
   }
-  const uint32_t n_chunks = (uint32_t)((db.n_sets + kAllChunk - 1) / kAllChunk);
-  const uint64_t n_units = (uint64_t)n_chunks * q.n_q;
-  const uint64_t grid = align_up(n_units, 8);
-  if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  const uint32_t lds_rows = haus_lds_rows(q.max_rows, db.dp);
-  const size_t lds = haus_stage_bytes(lds_rows, db.dp);
-  return dispatch_haus(db.dp, q.max_rows, lds_rows, [&](auto ks, auto mqt, auto hg) -> hipError_t {
-    constexpr int KS = decltype(ks)::value, MQ = decltype(mqt)::value;
-    constexpr bool HG = decltype(hg)::value;
-    if constexpr (!haus_variant_used<KS, MQ, HG>()) {
-      return hipErrorInvalidValue;
-    } else {
-      auto kern = k_haus_all<KS, MQ, HG>;
-      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, n_units, h2);
-      return hipGetLastError();
-    }
-  });
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------- top-k

@@ -163,7 +163,13 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
                             uint32_t* h2, unsigned long long* stats, uint32_t* sel, uint32_t* sel_count,
                             hipStream_t st);
 // All sets: h2 [n_q][n_sets].
-hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, hipStream_t st);
+// Exact value of every (query, set) pair into h2 [n_q][n_sets]; h_q_off are
+// the query offsets on the host, d_qids a device list of
+// haus_all_list_words(n_q) words (the queries grouped by size; the call
+// synchronises the stream after uploading it).
+uint32_t haus_all_list_words(uint32_t n_q);
+hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, const uint64_t* h_q_off, uint32_t* d_qids,
+                           hipStream_t st);
 size_t haus_lds_bytes(uint32_t max_rows, uint32_t dp);
 uint32_t haus_lds_rows(uint32_t max_rows, uint32_t dp);
 uint32_t haus_max_rows_supported(uint32_t dp);
@@ -301,6 +307,7 @@ hipError_t launch_soft_backward(const float* Y, const float* thr, const uint32_t
 hipError_t launch_relu_backward(const float* dH, const uint16_t* H16, uint64_t n, float* dP, uint16_t* dP16,
                                 hipStream_t st);
 hipError_t launch_colsum(const float* X, uint64_t n, uint32_t C, float* out, hipStream_t st);
+hipError_t launch_add_loss(const float* loss, double* acc, hipStream_t st);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, uint64_t n, float lr, float b1, float b2,
                        float eps, uint32_t step, uint16_t* w16, hipStream_t st);
 hipError_t launch_mlp_init(float* w, uint32_t d, uint32_t H, uint32_t L, uint64_t seed, hipStream_t st);
