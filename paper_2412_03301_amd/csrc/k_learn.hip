@@ -512,6 +512,14 @@ hipError_t launch_colsum(const float* X, uint64_t n, uint32_t C, float* out, hip
   return hipGetLastError();
 }
 
+// acc += (double)loss: the sum of an epoch's batch losses, in batch order.
+__global__ void k_add_loss(const float* __restrict__ loss, double* __restrict__ acc) { *acc += (double)*loss; }
+
+hipError_t launch_add_loss(const float* loss, double* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_loss, dim3(1), dim3(1), 0, st, loss, acc);
+  return hipGetLastError();
+}
+
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, uint64_t n, float lr, float b1, float b2,
                        float eps, uint32_t step, uint16_t* w16, hipStream_t st) {
   if (n == 0) return hipSuccess;

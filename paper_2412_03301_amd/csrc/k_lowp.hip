@@ -335,24 +335,30 @@ k_haus_lp(LowpDb db, LowpQ qs, uint32_t lds_rows, const uint32_t* __restrict__ i
   if (bounds && bounds[q] != 0xFFFFFFFFu) thr = __float_as_uint(__uint_as_float(bounds[q]) * factor);
   const LpView qv = lp_stage(qs, q, lds_rows, smem);
   uint32_t rows = 0;
-  for (uint32_t it = b0 + NS * wave_id(); it < b1; it += NS * kLpWaves) {
-    uint64_t o0[NS];
-    uint32_t m[NS], res[NS];
-    float sv[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const bool here = it + s < b1;
-      const uint32_t j = here ? ids[(uint64_t)q * stride + it + s] : 0u;
-      o0[s] = db.offsets[j];
-      m[s] = here ? (uint32_t)(db.offsets[j + 1] - o0[s]) : 0u;
-      sv[s] = db.scale ? db.scale[j] : 1.0f;
-    }
-    lp_items<FMT, KC, MAXQT, HASG, NS>(db, o0, m, sv, qv, res, thr, rows);
-    if (lane_id() == 0) {
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        if (it + s < b1) out[(uint64_t)q * stride + it + s] = res[s];
-    }
+  static_assert(NS == 1, "one set per wave");
+  // the id of the candidate after next and the offsets and scale of the next
+  // one load while this one is computed (out-of-range ids read set 0, unused)
+  const uint32_t w = wave_id();
+  const cptr<uint32_t> idq = as_const(ids) + (uint64_t)q * stride;
+  const cptr<uint64_t> offs = as_const(db.offsets);
+  auto id_at = [&](uint32_t i) { return i < b1 ? idq[i] : 0u; };
+  auto scale_of = [&](uint32_t j) { return db.scale ? db.scale[j] : 1.0f; };
+  uint32_t jn = id_at(b0 + w);
+  uint64_t c0 = offs[jn], c1 = offs[jn + 1];
+  float cs = scale_of(jn);
+  jn = id_at(b0 + w + kLpWaves);
+  for (uint32_t it = b0 + w; it < b1; it += kLpWaves) {
+    const uint64_t n0 = offs[jn], n1 = offs[jn + 1];
+    const float ns = scale_of(jn);
+    jn = id_at(it + 2 * kLpWaves);
+    uint64_t o0[1] = {c0};
+    uint32_t m[1] = {(uint32_t)(c1 - c0)}, res[1];
+    float sv[1] = {cs};
+    lp_items<FMT, KC, MAXQT, HASG, 1>(db, o0, m, sv, qv, res, thr, rows);
+    if (lane_id() == 0) out[(uint64_t)q * stride + it] = res[0];
+    c0 = n0;
+    c1 = n1;
+    cs = ns;
   }
   if (stats) stats_add(stats, 6, rows);
 }
