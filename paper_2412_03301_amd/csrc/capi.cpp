@@ -144,6 +144,59 @@ void make_projection(const Geometry& g, uint64_t seed, uint16_t* out /* [L][s] *
   }
 }
 
+// Order of the gathers in the device projection table.  The encode kernel's
+// lane l sums output j = 64 t + l from its row, entry i at step i, all 64
+// lanes at once; an output's sum does not depend on the order of its
+// entries, so each group of 64 rows is reordered to spread every step's 64
+// reads over the LDS banks: step by step, each row (rows with the fewest
+// distinct banks left first) takes the entry whose 4-byte word is already
+// read in this step or else whose bank is least loaded so far.  Element e of
+// the staged vector lies in word e / 2 of a wave-aligned slot; banks are
+// words mod 64.
+void order_projection_gathers(const Geometry& g, uint16_t* tab /* [L][SP] */) {
+  constexpr uint32_t kBanks = 64;
+  const uint32_t SP = g.SP;
+  std::vector<std::vector<uint16_t>> left(64);
+  std::vector<uint32_t> lanes(64), load(kBanks);
+  std::vector<uint16_t> step_words;
+  for (uint32_t j0 = 0; j0 + 64 <= g.L; j0 += 64) {
+    for (uint32_t l = 0; l < 64; ++l) left[l].assign(tab + (size_t)(j0 + l) * SP, tab + (size_t)(j0 + l + 1) * SP);
+    for (uint32_t i = 0; i < SP; ++i) {
+      std::fill(load.begin(), load.end(), 0u);
+      step_words.clear();
+      auto distinct_banks = [&](uint32_t l) {
+        uint64_t m = 0;
+        for (uint16_t e : left[l]) m |= 1ull << ((e / 2u) % kBanks);
+        return __builtin_popcountll(m);
+      };
+      for (uint32_t l = 0; l < 64; ++l) lanes[l] = l;
+      std::stable_sort(lanes.begin(), lanes.end(),
+                       [&](uint32_t a, uint32_t b) { return distinct_banks(a) < distinct_banks(b); });
+      for (uint32_t l : lanes) {
+        size_t best = 0;
+        uint32_t best_cost = ~0u;
+        for (size_t k = 0; k < left[l].size(); ++k) {
+          const uint16_t w = left[l][k] / 2u;
+          const bool shared = std::find(step_words.begin(), step_words.end(), w) != step_words.end();
+          const uint32_t cost = shared ? 0u : load[w % kBanks] + 1u;
+          if (cost < best_cost) {
+            best_cost = cost;
+            best = k;
+          }
+        }
+        const uint16_t e = left[l][best];
+        left[l].erase(left[l].begin() + (ptrdiff_t)best);
+        tab[(size_t)(j0 + l) * SP + i] = e;
+        const uint16_t w = e / 2u;
+        if (std::find(step_words.begin(), step_words.end(), w) == step_words.end()) {
+          step_words.push_back(w);
+          ++load[w % kBanks];
+        }
+      }
+    }
+  }
+}
+
 bvs_status check_offsets(const uint64_t* off, uint64_t n, uint32_t max_size, const char* what, uint32_t* max_m) {
   if (!off) return fail(BVS_EINVAL, "%s offsets are NULL", what);
   if (off[0] != 0) return fail(BVS_EINVAL, "%s offsets[0] must be 0", what);
@@ -934,6 +987,7 @@ bvs_status bvs_build_index(const bvs_params* p, const float* d_vectors, const ui
   make_projection(g, p->seed, proj.data());
   for (uint32_t j = 0; j < g.L; ++j)
     for (uint32_t i = 0; i < g.s; ++i) padded[(size_t)j * g.SP + i] = proj[(size_t)j * g.s + i];
+  order_projection_gathers(g, padded.data());
 
   auto run = [&]() -> bvs_status {
     HIP_TRY(hipMemcpyAsync(ix->idx, padded.data(), padded.size() * 2, hipMemcpyHostToDevice, st));
