@@ -416,7 +416,8 @@ def batched(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
     ids = b.ids.cpu().numpy().view(np.uint32)
 
     # stage times and work: the same plan shape launched eagerly with events
-    e = bvs.Batch(ix, q, q_off, k, lds_rows=info["lds_rows"], waves=info["waves"], graph=False)
+    phases = info["waves"] == 0   # the tuner chose the phase sequence by size class
+    e = bvs.Batch(ix, q, q_off, k, lds_rows=info["lds_rows"], waves=info["waves"], graph=False, phases=phases)
     e.run()
     bvs.profile_enable(True)
     for i in range(args.steps):
@@ -471,7 +472,8 @@ def batched(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
         log(f"brute force on {nb} queries: {brute_qps:.1f} q/s; recall@10 {recall:.4f}")
 
     work["sketch_rows"] = sketch_rows(ix, q, q_off)
-    roof, rerank_roof = rooflines(per_step, work, w["code_bits"], ix.dim_padded, "k_haus_queue", "k_batch.hip",
+    roof, rerank_roof = rooflines(per_step, work, w["code_bits"], ix.dim_padded,
+                                  "k_haus_cand" if phases else "k_haus_queue", "k_haus.hip" if phases else "k_batch.hip",
                                   w["n_sets"], counted=False)
     cpu = None
     if not args.no_cpu_baseline:
@@ -492,7 +494,7 @@ def batched(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "exact int16 grid values as int8 hi/lo planes (4 int8 MFMA products, int32 accumulation)",
         "data": "synthetic",
         "config": {
             "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={w['dim']}, "
@@ -668,7 +670,8 @@ def precision(args, w, cfg, ix, q, q_off, n_vec, build_s, cpu_db, db_offsets):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"exact": "int8", "bf16": "bf16", "fp8": "fp8-e4m3"}[best],
+        "dtype": {"exact": "exact int16 grid values as int8 hi/lo planes", "bf16": "bf16",
+                  "fp8": "fp8-e4m3"}[best],
         "data": "synthetic",
         "config": {
             "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={w['dim']}, "
@@ -827,7 +830,7 @@ def learned_bench(args, w, cfg, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "bf16 projection network; exact int16 grid values as int8 hi/lo planes in the re-rank",
         "data": "synthetic",
         "config": {
             "workload": (f"{w['n_sets']} sets, sizes {w['size_lo']}-{w['size_hi']}, d={d}, {w['n_topics']} topics; "

@@ -356,10 +356,13 @@ bvs_status bvs_index_set_first_layer(bvs_index* ix, int mode);
 /* ------------------------------------------------------------------------
  * Batched search: many query sets of uneven size through the whole cascade
  * (Alg. 6) with no host round trip.  The exact re-rank of every query runs
- * in ONE persistent launch: resident workgroups take (query, 64-candidate
- * chunk) items from a device counter, largest queries first.  Results are
- * identical to bvs_search on the same queries (the cascade is exact given
- * F2, and F2 is a function of the query alone).
+ * either in ONE persistent launch (resident workgroups take (query,
+ * 64-candidate chunk) items from a device counter, largest queries first)
+ * or as the phase sequence of bvs_search run once per size class of the
+ * queries (up to 2, 4, 8 and 16 tiles of 16 vectors, each class with
+ * kernels sized for it).  Results are identical to bvs_search on the same
+ * queries (the cascade is exact given F2, and F2 is a function of the query
+ * alone).
  *
  * Life cycle: bvs_batch_create (host only: validates the offsets, orders the
  * queries by size, sizes the workspace) -> bvs_batch_bind (uploads the
@@ -376,8 +379,9 @@ bvs_status bvs_index_set_first_layer(bvs_index* ix, int mode);
  * Autotuner: with lds_rows or waves = 0, bind times every valid shape of the
  * persistent re-rank, query rows staged in LDS in {32, 64, 128} x waves per
  * workgroup (sets in flight against one staged query, one wave per set) in
- * {2, 4, 8}, on the bound batch itself, after running the cascade up to F2
- * once; shapes whose kernel spills registers or does not fit a CU are
+ * {2, 4, 8}, and (with both 0) the phase sequence by size class, reported
+ * as shape 0 x 0, on the bound batch itself, after running the cascade up to
+ * F2 once; shapes whose kernel spills registers or does not fit a CU are
  * skipped.  The fastest shape is cached per process for the shape class
  * (dim, T, k, largest query tile count, log2 n_q) and reused by later binds
  * of the same class without timing.
@@ -388,16 +392,21 @@ typedef struct bvs_batch_config {
   uint32_t lds_rows;   /* 16..256, multiple of 16; 0 = autotune */
   uint32_t waves;      /* 2, 4 or 8; 0 = autotune */
   uint32_t graph;      /* nonzero: capture the launch sequence at bind */
-  uint32_t flags;      /* must be 0 */
+  uint32_t flags;      /* 0 or BVS_BATCH_PHASES */
 } bvs_batch_config;
+
+/* config.flags: re-rank with the phase sequence by size class, no tuning
+ * (lds_rows and waves must then be 0). */
+#define BVS_BATCH_PHASES 1u
 
 #define BVS_TUNE_MAX 16
 typedef struct bvs_batch_info {
   uint32_t n_q, max_rows;          /* queries, vectors in the largest */
   uint64_t n_q_vectors;            /* vectors over all queries */
   uint64_t workspace_bytes;        /* needed by bvs_batch_bind */
-  uint32_t lds_rows, waves;        /* re-rank shape in use (0 before bind) */
-  uint32_t blocks;                 /* persistent workgroups launched */
+  uint32_t lds_rows, waves;        /* re-rank shape in use (0 before bind; 0 and 0:
+                                      the phase sequence by size class) */
+  uint32_t blocks;                 /* persistent workgroups launched (0: phases) */
   uint32_t from_cache;             /* shape taken from the tuner cache */
   uint32_t graph;                  /* launches replay a captured graph */
   uint32_t n_tried;                /* shapes timed by the tuner */

@@ -42,6 +42,7 @@ FIRST_LAYER = {"bitmaps": 0, "lists": 1}
 METRIC = {"hausdorff": 0, "meanmin": 1, "min": 2}
 LOWP = {"bf16": 1, "fp8": 2}
 TUNE_MAX = 16
+BVS_BATCH_PHASES = 1   # bvs_batch_config.flags: the phase sequence by size class
 N_STAGES = 14
 N_COUNTERS = 7
 COUNTER_NAMES = ("filter_pairs", "rerank_vectors", "rerank_abandoned", "rerank_candidates",
@@ -563,18 +564,20 @@ def as_u16(t: torch.Tensor) -> np.ndarray:
 
 class Batch:
     """A batched search plan over one index (bvs_batch_*): the whole cascade
-    for many query sets with one persistent re-rank launch, optionally
-    captured once in a hipGraph.  Outputs as for Index.search.  Graph capture
-    needs a non-default stream; by default the plan makes its own."""
+    for many query sets, the re-rank as one persistent launch or as the phase
+    sequence of Index.search by size class (phases=True, or the autotuner's
+    choice), optionally captured once in a hipGraph.  Outputs as for
+    Index.search.  Graph capture needs a non-default stream; by default the
+    plan makes its own."""
 
     def __init__(self, index: Index, q: torch.Tensor, q_offsets, k: int, lds_rows: int = 0, waves: int = 0,
-                 graph: bool = True, stream=None):
+                 graph: bool = True, stream=None, phases: bool = False):
         L = lib()
         self.index = index
         off, n_q, NQ = index._qargs(q, q_offsets)
         self.n_q, self.k = n_q, k
         self.q = q
-        cfg = BatchConfig(lds_rows, waves, 1 if graph else 0, 0)
+        cfg = BatchConfig(lds_rows, waves, 1 if graph else 0, BVS_BATCH_PHASES if phases else 0)
         h = C.c_void_p()
         check(L.bvs_batch_create(index._h, _u64p(off), n_q, k, C.byref(cfg), C.byref(h)))
         self._h = h

@@ -786,6 +786,7 @@ HausQ haus_q(const QueryWs& w, uint32_t n_q, uint32_t max_rows) {
   q.offsets = w.qoff;
   q.n_q = n_q;
   q.max_rows = max_rows;
+  q.qids = nullptr;
   return q;
 }
 
@@ -1225,6 +1226,12 @@ struct bvs_batch {
   QueryWs w{};
   uint32_t* d_order = nullptr;
   uint32_t* d_ctl = nullptr;
+  // phase sequence of the re-rank: the queries by size class (up to 2, 4, 8
+  // and 16 tiles of 16 vectors), each class with its own kernels
+  std::vector<uint32_t> bucket;   // query ids, class after class
+  uint32_t bucket_off[5] = {0, 0, 0, 0, 0};
+  uint32_t bucket_rows[4] = {0, 0, 0, 0};
+  uint32_t* d_bucket = nullptr;
   hipGraphExec_t exec = nullptr;
   std::unique_ptr<CallProf> pending;   // stage events of an eager launch
 };
@@ -1258,6 +1265,7 @@ void layout_batch(Carver& c, const bvs_index* ix, uint32_t n_q, uint64_t NQ, bvs
   layout_search(c, ix, n_q, NQ, &b->w);
   b->d_order = c.take<uint32_t>(n_q);
   b->d_ctl = c.take<uint32_t>(1ull + n_q);
+  b->d_bucket = c.take<uint32_t>(n_q);
 }
 
 QueueArgs queue_args(const bvs_batch* b) {
@@ -1288,6 +1296,23 @@ bvs_status batch_filters(bvs_batch* b, hipStream_t st, CallProf& prof) {
 }
 
 bvs_status batch_rerank(bvs_batch* b, hipStream_t st, CallProf& prof) {
+  if (b->info.waves == 0) {
+    // the phase sequence of bvs_search, one size class at a time
+    const QueryWs& w = b->w;
+    HIP_TRY(staged(prof, S_RERANK, [&]() -> hipError_t {
+      hipError_t e = launch_fill_u32(w.surv_count, b->n_q, 0, st);
+      for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+        const uint32_t n = b->bucket_off[c + 1] - b->bucket_off[c];
+        if (n == 0) continue;
+        HausQ hq = haus_q(w, n, b->bucket_rows[c]);
+        hq.qids = b->d_bucket + b->bucket_off[c];
+        e = launch_haus_cand(haus_db(b->ix), hq, w.f2_ids, w.f2_count, b->ix->g.T, b->k, w.thr, w.h2,
+                             prof.count ? w.stats : nullptr, w.surv, w.surv_count, st);
+      }
+      return e;
+    }));
+    return BVS_OK;
+  }
   QueueArgs a = queue_args(b);
   if (prof.count) a.stats = b->w.stats;
   HIP_TRY(staged(prof, S_RERANK, [&] {
@@ -1371,6 +1396,31 @@ bvs_status batch_tune(bvs_batch* b, hipStream_t st) {
     }
     if (status != BVS_OK) break;
   }
+  if (status == BVS_OK && !b->cfg.lds_rows && !b->cfg.waves && b->info.n_tried < BVS_TUNE_MAX) {
+    // the phase sequence of bvs_search by size class (shape 0 x 0)
+    b->info.lds_rows = 0;
+    b->info.waves = 0;
+    b->info.blocks = 0;
+    float ms = 0.f;
+    status = [&]() -> bvs_status {
+      BVS_TRY(batch_rerank(b, st, off));
+      HIP_TRY(hipEventRecord(e0, st));
+      BVS_TRY(batch_rerank(b, st, off));
+      BVS_TRY(batch_rerank(b, st, off));
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      return BVS_OK;
+    }();
+    if (status == BVS_OK) {
+      ms *= 0.5f;
+      const uint32_t i = b->info.n_tried++;
+      b->info.tried_lds_rows[i] = 0;
+      b->info.tried_waves[i] = 0;
+      b->info.tried_ms[i] = ms;
+      if (i == 0 || ms < best) best = ms;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (status != BVS_OK) return status;
@@ -1382,7 +1432,7 @@ bvs_status batch_tune(bvs_batch* b, hipStream_t st) {
       break;
     }
   }
-  b->info.blocks = shape_blocks(b, b->info.lds_rows, b->info.waves);
+  b->info.blocks = b->info.waves ? shape_blocks(b, b->info.lds_rows, b->info.waves) : 0;
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune[tune_key(b)] = {b->info.lds_rows, b->info.waves};
   return BVS_OK;
@@ -1434,7 +1484,9 @@ bvs_status bvs_batch_create(const bvs_index* ix, const uint64_t* h_q_off, uint32
   if (k < 1 || k > kMaxK || k > ix->g.T) return fail(BVS_EINVAL, "k %u outside 1..min(64, top_t)", k);
   bvs_batch_config c{};
   if (cfg) c = *cfg;
-  if (c.flags != 0) return fail(BVS_EINVAL, "config.flags must be 0");
+  if (c.flags & ~BVS_BATCH_PHASES) return fail(BVS_EINVAL, "config.flags %u: unknown flag", c.flags);
+  if ((c.flags & BVS_BATCH_PHASES) && (c.lds_rows || c.waves))
+    return fail(BVS_EINVAL, "config.flags BVS_BATCH_PHASES excludes a persistent shape (lds_rows, waves)");
   if (c.lds_rows && (c.lds_rows % 16 != 0 || c.lds_rows > 256))
     return fail(BVS_EINVAL, "config.lds_rows %u is not a multiple of 16 in 16..256", c.lds_rows);
   if (c.lds_rows && haus_queue_lds_bytes(c.lds_rows, ix->g.dp) > kQueueLdsLimit)
@@ -1455,6 +1507,21 @@ bvs_status bvs_batch_create(const bvs_index* ix, const uint64_t* h_q_off, uint32
     return h_q_off[x + 1] - h_q_off[x] > h_q_off[y + 1] - h_q_off[y];
   });
   b->cfg = c;
+  {
+    std::vector<uint32_t> cls[4];
+    for (uint32_t i = 0; i < n_q; ++i) {
+      const uint64_t m = h_q_off[i + 1] - h_q_off[i];
+      const uint32_t nqt = (uint32_t)((m + 15) / 16);
+      const int k = nqt <= 2 ? 0 : nqt <= 4 ? 1 : nqt <= 8 ? 2 : 3;
+      cls[k].push_back(i);
+      b->bucket_rows[k] = std::max<uint32_t>(b->bucket_rows[k], (uint32_t)m);
+    }
+    for (int k = 0; k < 4; ++k) {
+      b->bucket_off[k] = (uint32_t)b->bucket.size();
+      b->bucket.insert(b->bucket.end(), cls[k].begin(), cls[k].end());
+    }
+    b->bucket_off[4] = (uint32_t)b->bucket.size();
+  }
   Carver cv(nullptr);
   bvs_batch tmp;
   layout_batch(cv, ix, n_q, b->NQ, &tmp);
@@ -1482,11 +1549,16 @@ bvs_status bvs_batch_bind(bvs_batch* b, const float* d_q, void* d_ws, uint64_t w
   layout_batch(c, b->ix, b->n_q, b->NQ, b);
   HIP_TRY(hipMemcpyAsync(b->w.qoff, b->off.data(), b->off.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b->d_order, b->order.data(), b->order.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b->d_bucket, b->bucket.data(), b->bucket.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                         st));
   HIP_TRY(hipStreamSynchronize(st));
   // re-rank shape: given, cached, or tuned now
   b->info.from_cache = 0;
   b->info.n_tried = 0;
-  if (b->cfg.lds_rows && b->cfg.waves) {
+  if (b->cfg.flags & BVS_BATCH_PHASES) {
+    b->info.lds_rows = 0;
+    b->info.waves = 0;
+  } else if (b->cfg.lds_rows && b->cfg.waves) {
     b->info.lds_rows = b->cfg.lds_rows;
     b->info.waves = b->cfg.waves;
   } else {
@@ -1504,8 +1576,8 @@ bvs_status bvs_batch_bind(bvs_batch* b, const float* d_q, void* d_ws, uint64_t w
     if (hit) b->info.from_cache = 1;
     else BVS_TRY(batch_tune(b, st));
   }
-  b->info.blocks = shape_blocks(b, b->info.lds_rows, b->info.waves);
-  if (!b->info.blocks)
+  b->info.blocks = b->info.waves ? shape_blocks(b, b->info.lds_rows, b->info.waves) : 0;
+  if (b->info.waves && !b->info.blocks)
     return fail(BVS_ENOTSUP, "re-rank shape lds_rows %u, waves %u does not fit a CU", b->info.lds_rows,
                 b->info.waves);
   b->info.graph = 0;

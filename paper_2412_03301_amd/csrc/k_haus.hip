@@ -40,7 +40,7 @@ k_haus_cand(HausDb db, HausQ qs, uint32_t lds_rows, const uint32_t* __restrict__
             const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2, unsigned long long* __restrict__ stats,
             const uint32_t* __restrict__ sel) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const uint32_t q = blockIdx.y;
+  const uint32_t q = qs.qids ? qs.qids[blockIdx.y] : blockIdx.y;
   const uint32_t i1 = min(count[q], lim);
   const uint32_t b0 = i0 + blockIdx.x * kCandPerBlock;
   if (b0 >= i1) return;
@@ -85,7 +85,7 @@ k_haus_screen(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint3
               uint32_t i0, const uint32_t* __restrict__ bounds, uint32_t* __restrict__ h2, uint32_t* __restrict__ sel,
               uint32_t* __restrict__ sel_count, unsigned long long* __restrict__ stats) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const uint32_t q = blockIdx.y;
+  const uint32_t q = qs.qids ? qs.qids[blockIdx.y] : blockIdx.y;
   const uint32_t i1 = count[q];
   const uint32_t b0 = i0 + blockIdx.x * kCandPerBlock;
   if (b0 >= i1) return;
@@ -126,11 +126,12 @@ k_haus_screen(HausDb db, HausQ qs, const uint32_t* __restrict__ ids, const uint3
 }
 
 // One wave per query: bounds[q] = k-th smallest of h2[q][0 .. min(count, n)),
-// n <= 64, or all ones when fewer than k are there.
+// n <= 64, or all ones when fewer than k are there.  With qids, wave b
+// serves query qids[b].
 __global__ void __launch_bounds__(64)
 k_kth_bound(const uint32_t* __restrict__ h2, const uint32_t* __restrict__ count, uint32_t T, uint32_t n, uint32_t k,
-            uint32_t* __restrict__ bounds) {
-  const uint32_t q = blockIdx.x, lane = lane_id();
+            uint32_t* __restrict__ bounds, const uint32_t* __restrict__ qids) {
+  const uint32_t q = qids ? qids[blockIdx.x] : blockIdx.x, lane = lane_id();
   const uint32_t nv = min(count[q], n);
   const uint32_t v = lane < nv ? h2[(uint64_t)q * T + lane] : 0xFFFFFFFFu;
   const uint32_t kth = wave_kth_smallest(v, nv, k);
@@ -141,7 +142,8 @@ hipError_t launch_kth_bound(const uint32_t* vals, const uint32_t* count, uint32_
                             uint32_t n_q, uint32_t* bounds, hipStream_t st) {
   if (n > 64 || k == 0) return hipErrorInvalidValue;
   if (n_q == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_kth_bound, dim3(n_q), dim3(64), 0, st, vals, count, T, n, k, bounds);
+  hipLaunchKernelGGL(k_kth_bound, dim3(n_q), dim3(64), 0, st, vals, count, T, n, k, bounds,
+                     (const uint32_t*)nullptr);
   return hipGetLastError();
 }
 
@@ -296,20 +298,20 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if (T <= na) return hipSuccess;
       if (na < n0) {
-        hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, na, k, thr);
+        hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, na, k, thr, q.qids);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(1, q.n_q), dim3(64 * kHausWaves), lds, st, db, q, lds_rows, ids, count, T, na,
                            n0, (const uint32_t*)thr, h2, stats, (const uint32_t*)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (T <= n0) return hipSuccess;
       }
-      hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, n0, k, thr);
+      hipLaunchKernelGGL(k_kth_bound, dim3(q.n_q), dim3(64), 0, st, h2, count, T, n0, k, thr, q.qids);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const uint32_t G = (T - n0 + kCandPerBlock - 1) / kCandPerBlock;
       const size_t slds = screen_stage_bytes((q.max_rows + 15) / 16 * 16, db.dp);
       if (sel && sel_count && db.scr && q.scr && slds <= kStageBudget) {
         // the rest: high-plane screen, then the exact pass over the survivors
-        if ((e = launch_fill_u32(sel_count, q.n_q, 0, st)) != hipSuccess) return e;
+        if (!q.qids && (e = launch_fill_u32(sel_count, q.n_q, 0, st)) != hipSuccess) return e;
         auto skern = k_haus_screen<KS, MQ>;
         if ((e = hipFuncSetAttribute((const void*)skern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds)) !=
             hipSuccess)
@@ -329,9 +331,6 @@ hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* id
   });
 }
 
-// Queries per tile of the all-sets kernel and the rows each stages: four
-// queries when each keeps at least 48 staged rows within the budget (or all of
-// its rows), else two, else one (k_haus_all).
 // The brute force groups the queries by their tiles of 16 vectors: those of
 // one or two tiles share a pass over the database QT = 8 or 4 at a time,
 // those of three to eight tiles two at a time (up to 64 rows staged, the

@@ -152,12 +152,16 @@ struct HausQ {
   const int8_t* hi; const uint8_t* lo; const uint32_t* norms; const uint64_t* offsets;
   uint32_t n_q; uint32_t max_rows;
   const uint2* scr;
+  // candidate mode: the n_q queries served are qids[0 .. n_q) (null: 0 .. n_q);
+  // ids, counts, results and bounds stay indexed by query
+  const uint32_t* qids;
 };
 // Candidate mode: items are ids[q][0 .. count[q]) with stride T.  Items that
 // provably cannot be among the k nearest may be abandoned (h2 = all ones);
 // thr [n_q] is scratch for the shared bound.
 // sel [n_q][T] and sel_count [n_q] (both may be null: no screening) are
-// scratch for the candidates that pass the high-plane screen.
+// scratch for the candidates that pass the high-plane screen; with q.qids
+// the caller zeroes sel_count of the listed queries beforehand.
 hipError_t launch_haus_cand(const HausDb& db, const HausQ& q, const uint32_t* ids,
                             const uint32_t* count, uint32_t T, uint32_t k, uint32_t* thr,
                             uint32_t* h2, unsigned long long* stats, uint32_t* sel, uint32_t* sel_count,

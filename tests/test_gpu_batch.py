@@ -85,6 +85,21 @@ def test_batch_shapes_match_per_call(mixed, per_call, oracle_res, rows, waves, g
     b.close()
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_phase_sequence_matches_per_call(mixed, per_call, oracle_res, graph):
+    from paper_2412_03301_amd import bvs
+    _say(f"phase sequence by size class, graph={graph}")
+    b = bvs.Batch(mixed.ix_gpu, mixed.q, mixed.q_off, K, graph=graph, phases=True)
+    info = b.info()
+    assert (info["lds_rows"], info["waves"], info["blocks"], info["graph"]) == (0, 0, 0, graph)
+    assert not info["tried"]
+    for _ in range(2):   # a replay sees the device state of the previous one
+        out = [to_np(t) for t in b.run()]
+        _same(out, per_call)
+    _check_oracle(oracle_res, *out)
+    b.close()
+
+
 def test_graph_replays_with_eager_work_between(mixed, per_call):
     from paper_2412_03301_amd import bvs
     _say("graph replays")
@@ -115,6 +130,7 @@ def test_autotuner_picks_a_timed_shape_and_caches_it(mixed, per_call):
         assert not tried
     else:
         assert len(tried) >= 2 and all(ms > 0 for _, _, ms in tried)
+        assert (0, 0) in [t[:2] for t in tried]   # the phase sequence is timed too
         best = min(tried, key=lambda t: t[2])
         assert (info["lds_rows"], info["waves"]) == best[:2]
     _same([to_np(t) for t in b.run()], per_call)
@@ -226,7 +242,8 @@ def test_batch_argument_errors(mixed):
     assert create(rows=40)[0] == bvs.BVS_EINVAL
     assert create(rows=256)[0] == bvs.BVS_ENOTSUP     # 205 KB of LDS at d = 384
     assert create(waves=3)[0] == bvs.BVS_EINVAL
-    assert create(flags=1)[0] == bvs.BVS_EINVAL
+    assert create(flags=2)[0] == bvs.BVS_EINVAL
+    assert create(rows=32, flags=bvs.BVS_BATCH_PHASES)[0] == bvs.BVS_EINVAL
     big = np.array([0, 257], np.uint64)
     assert create(offsets=big, n=1)[0] == bvs.BVS_ENOTSUP
     st, h = create(rows=32, waves=4)
