@@ -150,9 +150,9 @@ void make_projection(const Geometry& g, uint64_t seed, uint16_t* out /* [L][s] *
 // entries, so each group of 64 rows is reordered to spread every step's 64
 // reads over the LDS banks: step by step, each row (rows with the fewest
 // distinct banks left first) takes the entry whose 4-byte word is already
-// read in this step or else whose bank is least loaded so far.  Element e of
-// the staged vector lies in word e / 2 of a wave-aligned slot; banks are
-// words mod 64.
+// read in this step or else whose bank is least loaded so far.  Entries are
+// byte offsets into the staged vector (2 bytes per element, a wave-aligned
+// slot), so entry e lies in word e / 4; banks are words mod 64.
 void order_projection_gathers(const Geometry& g, uint16_t* tab /* [L][SP] */) {
   constexpr uint32_t kBanks = 64;
   const uint32_t SP = g.SP;
@@ -166,7 +166,7 @@ void order_projection_gathers(const Geometry& g, uint16_t* tab /* [L][SP] */) {
       step_words.clear();
       auto distinct_banks = [&](uint32_t l) {
         uint64_t m = 0;
-        for (uint16_t e : left[l]) m |= 1ull << ((e / 2u) % kBanks);
+        for (uint16_t e : left[l]) m |= 1ull << ((e / 4u) % kBanks);
         return __builtin_popcountll(m);
       };
       for (uint32_t l = 0; l < 64; ++l) lanes[l] = l;
@@ -176,7 +176,7 @@ void order_projection_gathers(const Geometry& g, uint16_t* tab /* [L][SP] */) {
         size_t best = 0;
         uint32_t best_cost = ~0u;
         for (size_t k = 0; k < left[l].size(); ++k) {
-          const uint16_t w = left[l][k] / 2u;
+          const uint16_t w = left[l][k] / 4u;
           const bool shared = std::find(step_words.begin(), step_words.end(), w) != step_words.end();
           const uint32_t cost = shared ? 0u : load[w % kBanks] + 1u;
           if (cost < best_cost) {
@@ -187,7 +187,7 @@ void order_projection_gathers(const Geometry& g, uint16_t* tab /* [L][SP] */) {
         const uint16_t e = left[l][best];
         left[l].erase(left[l].begin() + (ptrdiff_t)best);
         tab[(size_t)(j0 + l) * SP + i] = e;
-        const uint16_t w = e / 2u;
+        const uint16_t w = e / 4u;
         if (std::find(step_words.begin(), step_words.end(), w) == step_words.end()) {
           step_words.push_back(w);
           ++load[w % kBanks];
@@ -983,11 +983,12 @@ bvs_status bvs_build_index(const bvs_params* p, const float* d_vectors, const ui
   uint8_t* cnt_rm = wc.take<uint8_t>(n_sets * g.L);
   uint64_t* bits_rm = wc.take<uint64_t>(n_sets * g.R);
 
-  // Projection rows padded to SP entries; padding indexes the zero slot dp.
-  std::vector<uint16_t> proj((size_t)g.L * g.s), padded((size_t)g.L * g.SP, (uint16_t)g.dp);
+  // Projection rows as byte offsets into the staged vector (2 per element),
+  // padded to SP entries; padding reads the zero slot dp.
+  std::vector<uint16_t> proj((size_t)g.L * g.s), padded((size_t)g.L * g.SP, (uint16_t)(2 * g.dp));
   make_projection(g, p->seed, proj.data());
   for (uint32_t j = 0; j < g.L; ++j)
-    for (uint32_t i = 0; i < g.s; ++i) padded[(size_t)j * g.SP + i] = proj[(size_t)j * g.s + i];
+    for (uint32_t i = 0; i < g.s; ++i) padded[(size_t)j * g.SP + i] = (uint16_t)(2 * proj[(size_t)j * g.s + i]);
   order_projection_gathers(g, padded.data());
 
   auto run = [&]() -> bvs_status {

@@ -111,6 +111,8 @@ __device__ __forceinline__ void hash_keys(const int16_t* __restrict__ av, const 
   // them live across the vector loop (which spills at R = 64).
   uint32_t ln = lane;
   asm volatile("" : "+v"(ln));
+  const uint8_t* avb = (const uint8_t*)av;
+  auto at = [avb](uint32_t off) { return (int)*(const int16_t*)(avb + off); };
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     // bound the gathers in flight
@@ -120,8 +122,9 @@ __device__ __forceinline__ void hash_keys(const int16_t* __restrict__ av, const 
     int y = 0;
     for (uint32_t i0 = 0; i0 < SP; i0 += 8) {
       const uint4 w = *(const uint4*)(row + i0);
-      y += av[w.x & 0xFFFF] + av[w.x >> 16] + av[w.y & 0xFFFF] + av[w.y >> 16] +
-           av[w.z & 0xFFFF] + av[w.z >> 16] + av[w.w & 0xFFFF] + av[w.w >> 16];
+      // entries are byte offsets: the address is one add with a half-word operand
+      y += at(w.x & 0xFFFF) + at(w.x >> 16) + at(w.y & 0xFFFF) + at(w.y >> 16) +
+           at(w.z & 0xFFFF) + at(w.z >> 16) + at(w.w & 0xFFFF) + at(w.w >> 16);
     }
     key[t] = ((uint32_t)(y + (int)koff) << lgL) | (L - 1u - j);
   }
@@ -204,7 +207,7 @@ __device__ __forceinline__ uint32_t kth_largest(const uint32_t (&key)[R], uint32
 }
 
 struct EncodeShared {
-  uint16_t* idx;   // [L][SP]
+  uint16_t* idx;   // [L][SP] byte offsets into av
   int16_t* av;     // this wave's staged vector, dim_padded + 8 entries (tail zero)
 };
 

@@ -13,7 +13,7 @@ struct HashGeom {
   uint32_t L, lgL, R;          // code bits, log2 L (L is a power of two) or 0, L / 64
   uint32_t s, SP;              // fan-in and fan-in rounded up to 8 (row stride of idx)
   uint32_t wta_k;
-  const uint16_t* idx;         // device [L][SP]; padding entries index the zero slot dim_padded
+  const uint16_t* idx;         // device [L][SP] byte offsets 2 i into the staged vector; padding reads the zero slot dim_padded
 };
 
 // float32 rows -> exact int8 planes a = 64 * hi + lo (a = 4096 x), squared
