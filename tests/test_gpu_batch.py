@@ -70,6 +70,20 @@ def test_bruteforce_big_queries_matches_oracle(mixed):
         np.testing.assert_allclose(dist[0], np.sqrt(rh2), rtol=REL_TOL, atol=0)
 
 
+def test_bruteforce_grouping_matches_single_queries(mixed):
+    """One brute-force call over all 24 queries groups them by size (8, 4, 2
+    and 1 per pass over the database, padded tiles included); every query's
+    top-k equals that of a call holding it alone (whose grouping differs)."""
+    _say("brute force: all queries at once against one call per query")
+    ids, dist, cnt = [to_np(t) for t in mixed.ix_gpu.bruteforce(mixed.q, mixed.q_off, K)]
+    for i in range(len(SIZES)):
+        o0, o1 = mixed.q_off[i], mixed.q_off[i + 1]
+        i1, d1, c1 = [to_np(t) for t in mixed.ix_gpu.bruteforce(mixed.q[o0:o1].contiguous(), [0, o1 - o0], K)]
+        assert cnt[i] == c1[0], f"query {i} ({SIZES[i]} vectors)"
+        assert np.array_equal(ids[i], i1[0]), f"query {i} ({SIZES[i]} vectors)"
+        assert np.array_equal(dist[i], d1[0]), f"query {i} ({SIZES[i]} vectors)"
+
+
 @pytest.mark.parametrize("rows,waves,graph", [(16, 2, True), (32, 4, True), (64, 8, False), (128, 4, True),
                                               (144, 2, False), (48, 8, True)])
 def test_batch_shapes_match_per_call(mixed, per_call, oracle_res, rows, waves, graph):

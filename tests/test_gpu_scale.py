@@ -143,3 +143,21 @@ def test_screen_identity_whole_batch(big, monkeypatch):
     assert out["1c"]["rerank_screened"] > 0 and out["0c"]["rerank_screened"] == 0
     for a, b in zip(out["1"], out["0"]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("shape", ["phases", "persistent"])
+def test_batched_plan_identity_whole_batch(big, shape):
+    """The batched plan, replayed from its graph, returns for every one of the
+    1,024 queries exactly what one search call over the batch returns, with
+    the re-rank as the phase sequence by size class and as the persistent
+    launch."""
+    from paper_2412_03301_amd import bvs
+    print(f"[scale] batched plan ({shape}) against one search call", flush=True)
+    ref = [t.cpu().numpy() for t in big["ix"].search(big["q"], big["q_off"], K)]
+    kw = dict(phases=True) if shape == "phases" else dict(lds_rows=64, waves=4)
+    b = bvs.Batch(big["ix"], big["q"], big["q_off"], K, graph=True, **kw)
+    for _ in range(2):   # two replays
+        got = [t.cpu().numpy() for t in b.run()]
+        for a, c in zip(got, ref):
+            assert np.array_equal(a, c)
+    b.close()
