@@ -172,7 +172,7 @@ __device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c)
 // keys.  (At L = 4096 and k = 64 a lane holds more than 6 of the 64 largest
 // keys for about one vector in a hundred.)
 template <int R>
-__device__ __forceinline__ uint32_t kth_largest(const uint32_t (&key)[R], uint32_t k, int topbit) {
+__device__ __forceinline__ uint32_t kth_largest(uint32_t (&key)[R], uint32_t k, int topbit) {
   uint32_t lm = 0;
 #pragma unroll
   for (int t = 0; t < R; ++t) lm = max(lm, key[t]);
@@ -188,6 +188,11 @@ __device__ __forceinline__ uint32_t kth_largest(const uint32_t (&key)[R], uint32
       b0 = min(b0, hb);
     }
     if constexpr (R >= 16) {
+      // The keys are all computed before the first is kept: left free to
+      // interleave the keeping with the key gathers, the compiler holds
+      // more values live than the register budget and spills.
+#pragma unroll
+      for (int t = 0; t < R; ++t) asm volatile("" : "+v"(key[t]));
       constexpr int KT = 6;
       uint32_t c[KT];
 #pragma unroll
