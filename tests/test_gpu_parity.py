@@ -94,6 +94,50 @@ def test_candidates_bit_exact(tiny):
     _check_candidates(tiny, res, 200)
 
 
+def test_candidates_with_large_ties():
+    """Candidate lists stay bit-exact when many candidates share a score:
+    400, 300 and 100 exact copies of three sets (ties at the smallest score
+    larger than T = 200, about T and below it, broken by set id) among
+    1,200 other sets; the queries are the three copied sets and four other
+    sets."""
+    from oracle import prng
+    from paper_2412_03301_amd import bvs
+    _print_case("score ties of 400, 300 and 100 candidates")
+    rng = np.random.default_rng(5)
+    d = 128
+
+    def grid(x):
+        x = x / np.linalg.norm(x, axis=1, keepdims=True)
+        return (np.rint(x * 4096) / 4096).astype(np.float32)
+
+    bases = [grid(rng.normal(size=(int(rng.integers(4, 16)), d))) for _ in range(3)]
+    sets = []
+    for b, n in zip(bases, (400, 300, 100)):
+        sets += [b] * n
+    sets += [grid(rng.normal(size=(int(rng.integers(4, 16)), d))) for _ in range(1200)]
+    order = rng.permutation(len(sets))
+    sets = [sets[i] for i in order]
+    off = np.concatenate([[0], np.cumsum([len(x) for x in sets])]).astype(np.int64)
+    X = np.concatenate(sets)
+    qs = bases + [sets[i] for i in (3, 500, 1000, 1500)]
+    q_off = np.concatenate([[0], np.cumsum([len(x) for x in qs])]).astype(np.int64)
+    Q = np.concatenate(qs)
+    T = 200
+    p = bvs.Params.make(dim=d, code_bits=1024, fan_in=8, wta_k=32, access_lists=3, min_count=1, top_t=T, seed=4)
+    ix_g = bvs.Index(p, torch.from_numpy(X).cuda(), off)
+    ix_o = search.build_index(X.astype(np.float64), off, prng.projection_rows(4, d, 1024, 8), 32)
+    ids, sc, cnt = ix_g.candidates(torch.from_numpy(Q).cuda().contiguous(), q_off)
+    ids, sc, cnt = to_np(ids).view(np.uint32), to_np(sc).view(np.uint16), to_np(cnt)
+    for i in range(len(q_off) - 1):
+        r = search.search(ix_o, Q[q_off[i]:q_off[i + 1]].astype(np.float64), A=3, M=1, T=T, k=10)
+        c = len(r["f2_ids"])
+        assert cnt[i] == c
+        assert ids[i, :c].astype(np.int64).tolist() == r["f2_ids"].tolist()
+        assert sc[i, :c].astype(np.int64).tolist() == r["f2_scores"].tolist()
+        if i < 3:
+            assert (r["f2_scores"][: min(T, (400, 300, 100)[i])] == 0).all()
+
+
 def test_search_matches_oracle(tiny):
     res = _oracle_results(tiny, 3, 1, 200, 10)
     _check_search(tiny, res, 10)
