@@ -180,33 +180,68 @@ k_pass_lists(const uint64_t* __restrict__ sq, uint32_t R, uint32_t L, uint32_t n
   const uint32_t nblk = (dmax + 15) / 16;
   if (threadIdx.x < 2) gsteps[2 * pair + threadIdx.x] = nblk;
   if (threadIdx.x == 0 && nblk > kSmallSteps) atomicOr(any_long, 1u);
-  const uint32_t part = lane & 3, c = (lane >> 2) & 3, r = lane >> 4;
-  const uint64_t cmask = 0x1111111111111111ull << c;
-  const uint32_t zero_row = (L + c) * kRowBytes + part * 8;
+  // Each (rank, class) of the group is written by the whole wave: lane t
+  // takes sketch word t, whose members of class c are the j0-th and on of
+  // the class in row order (j0: the members in the words before t), and the
+  // class's j-th member goes to the j-th step whose permutation gives rank r
+  // class c.  The class's steps past its members read its zero row; steps
+  // from the depth to the end read zero rows by step.  The segments are held
+  // in registers (16 at most; lengths past nseg read as 0).
+  const uint32_t ns = nseg[g], dep = depth[g];
   const uint32_t end = 16 * nblk + 48;   // the scoring kernels read below this
-  const uint32_t rank = r0 + 4 * g + r;
-  uint32_t* out = lists + ((uint64_t)rank * 4 + part) * LP;
-  const uint64_t* qw = sk[4 * g + r];
-  uint32_t t = 0;
-  uint64_t w = qw[0] & cmask;
-  uint32_t slot = 0;
-  for (uint32_t k = 0; k < nseg[g]; ++k) {
-    const uint32_t len = seg_len[g][k];
-    if (((seg_perm[g][k] >> (2 * r)) & 3) == c) {
-      for (uint32_t j = 0; j < len; ++j) {
-        while (w == 0 && t + 1 < R) w = qw[++t] & cmask;
-        uint32_t v = zero_row;
-        if (w) {
-          v = (t * 64 + (uint32_t)__builtin_ctzll(w)) * kRowBytes + part * 8;
-          w &= w - 1;
+  uint32_t sl[16], sp[16];
+#pragma unroll
+  for (uint32_t i = 0; i < 16; ++i) {
+    sl[i] = i < ns ? seg_len[g][i] : 0u;
+    sp[i] = seg_perm[g][i];
+  }
+#pragma unroll 1
+  for (uint32_t r = 0; r < 4; ++r) {
+    const uint32_t rank = r0 + 4 * g + r;
+    uint32_t* out = lists + (uint64_t)rank * 4 * LP;   // part k's list at out + k LP
+    const uint64_t word = lane < R ? sk[4 * g + r][lane] : 0ull;
+#pragma unroll 1
+    for (uint32_t c = 0; c < 4; ++c) {
+      uint64_t w = word & (0x1111111111111111ull << c);
+      const uint32_t cnt = popc64(w);
+      uint32_t inc = cnt;
+#pragma unroll
+      for (int d = 1; d < BVS_WAVE; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)inc, d, BVS_WAVE);
+        if (lane >= (uint32_t)d) inc += o;
+      }
+      const uint32_t total = (uint32_t)__shfl((int)inc, BVS_WAVE - 1, BVS_WAVE);
+      const uint32_t zero_row = (L + c) * kRowBytes;
+      uint32_t j = inc - cnt;
+      // segment i holds the class's steps cum .. cum + len - 1 at list steps
+      // start .. start + len - 1
+      uint32_t start = 0, cum = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < 16; ++i) {
+        const uint32_t len = sl[i];
+        if (((sp[i] >> (2 * r)) & 3) == c) {
+          const uint32_t shift = start - cum;   // list step - class step (start >= cum)
+          for (; w && j < cum + len; ++j) {
+            const uint32_t v = (lane * 64 + (uint32_t)__builtin_ctzll(w)) * kRowBytes;
+            w &= w - 1;
+#pragma unroll
+            for (uint32_t p = 0; p < 4; ++p) out[p * LP + j + shift] = v + p * 8;
+          }
+          for (uint32_t jz = max(cum, total) + lane; jz < cum + len; jz += BVS_WAVE) {
+#pragma unroll
+            for (uint32_t p = 0; p < 4; ++p) out[p * LP + jz + shift] = zero_row + p * 8;
+          }
+          cum += len;
         }
-        out[slot + j] = v;
+        start += len;
       }
     }
-    slot += len;
+    for (uint32_t s2 = dep + lane; s2 < end; s2 += BVS_WAVE) {
+      const uint32_t zero_row = (L + ((s2 + r) & 3)) * kRowBytes;
+#pragma unroll
+      for (uint32_t p = 0; p < 4; ++p) out[p * LP + s2] = zero_row + p * 8;
+    }
   }
-  for (uint32_t s2 = depth[g]; s2 < end; ++s2)
-    if (((s2 + r) & 3) == c) out[s2] = zero_row;
 }
 
 hipError_t launch_query_rows(const FilterArgs& a, const uint64_t* sq, uint32_t R, hipStream_t st) {
