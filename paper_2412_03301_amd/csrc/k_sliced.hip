@@ -139,40 +139,62 @@ k_pass_lists(const uint64_t* __restrict__ sq, uint32_t R, uint32_t L, uint32_t n
       if (lane == 0) cnt[g][r][c] = v;
     }
   }
-  if (lane == 0) {
+  uint32_t D = 0;
+  {
+    wave_lds_sync();   // the counts written above by lane 0
     uint32_t (&N)[4][4] = cnt[g];
-    uint32_t rs[4] = {0, 0, 0, 0}, cs[4] = {0, 0, 0, 0}, D = 0;
+    uint32_t rs[4] = {0, 0, 0, 0}, cs[4] = {0, 0, 0, 0};
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 4; ++c) { rs[r] += N[r][c]; cs[c] += N[r][c]; }
     for (int i = 0; i < 4; ++i) D = max(D, max(rs[i], cs[i]));
-    // pad to row and column sums D (north-west corner)
-    for (int r = 0, c = 0; r < 4 && c < 4;) {
-      const uint32_t x = min(D - rs[r], D - cs[c]);
-      N[r][c] += x; rs[r] += x; cs[c] += x;
-      if (rs[r] == D) ++r; else ++c;
+    wave_lds_sync();
+    if (lane == 0) {
+      // pad to row and column sums D (north-west corner)
+      for (int r = 0, c = 0; r < 4 && c < 4;) {
+        const uint32_t x = min(D - rs[r], D - cs[c]);
+        N[r][c] += x; rs[r] += x; cs[c] += x;
+        if (rs[r] == D) ++r; else ++c;
+      }
     }
-    // peel permutations with all entries positive, largest minimum first;
-    // each peel empties an entry, so 16 always suffice
+    wave_lds_sync();
+  }
+  {
+    // peel permutations with all entries positive, largest minimum first
+    // (the first in the order a, b, c ascending on ties); each peel empties
+    // an entry, so 16 always suffice.  Lane i < 24 evaluates permutation i.
+    uint32_t mine = 0;
+    for (uint32_t a = 0, i = 0; a < 4; ++a)
+      for (uint32_t b = 0; b < 4; ++b)
+        for (uint32_t c = 0; c < 4; ++c) {
+          if (a == b || a == c || b == c) continue;
+          if (i++ == lane) mine = a | b << 2 | c << 4 | (6 - a - b - c) << 6;
+        }
     uint32_t left = D, k = 0;
     while (left > 0 && k < 16) {
-      uint32_t best = 0, bperm = 0;
-      for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b)
-          for (int c = 0; c < 4; ++c) {
-            if (a == b || a == c || b == c) continue;
-            const int d = 6 - a - b - c;
-            const uint32_t m = min(min(N[0][a], N[1][b]), min(N[2][c], N[3][d]));
-            if (m > best) { best = m; bperm = (uint32_t)(a | b << 2 | c << 4 | d << 6); }
-          }
+      uint32_t m = 0;
+      if (lane < 24) {
+        m = cnt[g][0][mine & 3];
+#pragma unroll
+        for (uint32_t r = 1; r < 4; ++r) m = min(m, cnt[g][r][(mine >> (2 * r)) & 3]);
+      }
+      const uint32_t top = wave_max_dpp_u32(lane < 24 ? m << 5 | (31u - lane) : 0u);   // D < 2^27
+      const uint32_t best = top >> 5;
       if (best == 0) break;   // cannot happen for equal row and column sums
-      for (int r = 0; r < 4; ++r) N[r][(bperm >> (2 * r)) & 3] -= best;
-      seg_len[g][k] = best;
-      seg_perm[g][k] = bperm;
+      const uint32_t bperm = (uint32_t)__shfl((int)mine, (int)(31u - (top & 31u)), BVS_WAVE);
+      wave_lds_sync();
+      if (lane < 4) cnt[g][lane][(bperm >> (2 * lane)) & 3] -= best;
+      if (lane == 0) {
+        seg_len[g][k] = best;
+        seg_perm[g][k] = bperm;
+      }
+      wave_lds_sync();
       left -= best;
       ++k;
     }
-    nseg[g] = k;
-    depth[g] = D - left;
+    if (lane == 0) {
+      nseg[g] = k;
+      depth[g] = D - left;
+    }
   }
   __syncthreads();
   uint32_t dmax = 0;
