@@ -183,9 +183,11 @@ k_haus_all(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, const uint3
 // workgroup stages the QT queries (lds_rows rows each, the rest read from
 // global memory) and each wave computes its sets against all of them
 // (haus_multi), so every set is read once per QT queries.  Units are numbered
-// over the XCDs as in k_haus_all.
-template <int KS, int MAXQT, bool HASG, int QT>
-__global__ void __launch_bounds__(64 * kHausWaves)
+// over the XCDs as in k_haus_all.  WV waves per workgroup: the staged
+// queries take most of the LDS, so one workgroup runs per CU and WV sets its
+// waves per SIMD (12 where the registers allow three per SIMD, else 8).
+template <int KS, int MAXQT, bool HASG, int QT, int WV>
+__global__ void __launch_bounds__(64 * WV)
 k_haus_all_qt(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, const uint32_t* __restrict__ qids,
               uint32_t n_tiles, uint32_t* __restrict__ h2) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -205,7 +207,7 @@ k_haus_all_qt(HausDb db, HausQ qs, uint32_t lds_rows, uint64_t n_units, const ui
     qv[i] = stage_query(qs, qid[i] == kNoQuery ? tq[0] : qid[i], KS * 64, lds_rows, smem + i * per_q);
   }
   const uint32_t w = wave_id();
-  for (uint64_t j = s0 + w; j < s1; j += kHausWaves) {
+  for (uint64_t j = s0 + w; j < s1; j += WV) {
     const uint64_t o0 = db.offsets[j];
     const uint32_t m = (uint32_t)(db.offsets[j + 1] - o0);
     uint32_t out[QT];
@@ -419,13 +421,13 @@ hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, const
     const size_t lds = k.qt * haus_stage_bytes(k.rows, db.dp);
     e = dispatch_ks(db.dp, [&](auto ks) -> hipError_t {
       constexpr int KS = decltype(ks)::value;
-      auto go = [&](auto kern, auto... args) -> hipError_t {
+      auto go_w = [&](uint32_t waves, auto kern, auto... args) -> hipError_t {
         hipError_t r = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (r != hipSuccess) return r;
-        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64 * kHausWaves), lds, st, db, q, k.rows, n_units,
-                           args..., h2);
+        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64 * waves), lds, st, db, q, k.rows, n_units, args..., h2);
         return hipGetLastError();
       };
+      auto go = [&](auto kern, auto... args) { return go_w(kHausWaves, kern, args...); };
       if (k.qt == 1) {
         if (k.hg) {
           if constexpr (haus_variant_used<KS, 16, true>()) return go(k_haus_all<KS, 16, true>, qids, n_list);
@@ -433,13 +435,21 @@ hipError_t launch_haus_all(const HausDb& db, const HausQ& q, uint32_t* h2, const
         }
         return go(k_haus_all<KS, 16, false>, qids, n_list);
       }
-      if (k.qt == 8) return go(k_haus_all_qt<KS, 2, false, 8>, qids, n_tiles);
+      // 12 waves where that instance fits 168 VGPRs without spilling
+      auto qt_kernel = [&](auto mq, auto hg, auto qt) -> hipError_t {
+        constexpr int MQ = decltype(mq)::value, QT = decltype(qt)::value;
+        constexpr bool HG = decltype(hg)::value;
+        constexpr int WV = !HG && KS <= 6 && (QT == 2 || (QT == 4 && MQ == 2)) ? 12 : (int)kHausWaves;
+        return go_w(WV, k_haus_all_qt<KS, MQ, HG, QT, WV>, qids, n_tiles);
+      };
+      using std::integral_constant;
+      if (k.qt == 8)
+        return qt_kernel(integral_constant<int, 2>(), std::false_type(), integral_constant<int, 8>());
       auto by_mq = [&](auto mq) -> hipError_t {
-        constexpr int MQ = decltype(mq)::value;
-        if (k.qt == 4) return k.hg ? go(k_haus_all_qt<KS, MQ, true, 4>, qids, n_tiles)
-                                   : go(k_haus_all_qt<KS, MQ, false, 4>, qids, n_tiles);
-        return k.hg ? go(k_haus_all_qt<KS, MQ, true, 2>, qids, n_tiles)
-                    : go(k_haus_all_qt<KS, MQ, false, 2>, qids, n_tiles);
+        if (k.qt == 4) return k.hg ? qt_kernel(mq, std::true_type(), integral_constant<int, 4>())
+                                   : qt_kernel(mq, std::false_type(), integral_constant<int, 4>());
+        return k.hg ? qt_kernel(mq, std::true_type(), integral_constant<int, 2>())
+                    : qt_kernel(mq, std::false_type(), integral_constant<int, 2>());
       };
       if (k.mqt == 2) return by_mq(std::integral_constant<int, 2>());
       if (k.mqt == 4) return by_mq(std::integral_constant<int, 4>());
