@@ -492,12 +492,24 @@ k_query_sketch(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ 
 #pragma unroll
   for (int b = 0; b < 64; ++b) c[b] = 0;
   if (own) {
+    // Eight vectors' words in flight at once (read at a clamped vector,
+    // masked); their bits are summed in 4-bit fields (bit 4 i + j of the word
+    // in field i of nib[j], at most 8 per batch) and then added to the counts.
     uint64_t orw = 0;
-    for (uint64_t v = o0; v < o1; ++v) {
-      const uint64_t w = codes[v * R + lane];
-      orw |= w;
+    for (uint64_t v0 = o0; v0 < o1; v0 += 8) {
+      uint64_t w[8];
 #pragma unroll
-      for (int b = 0; b < 64; ++b) c[b] += (uint32_t)((w >> b) & 1);
+      for (int u = 0; u < 8; ++u) w[u] = codes[min(v0 + u, o1 - 1) * R + lane];
+      uint64_t nib[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint64_t x = v0 + u < o1 ? w[u] : 0ull;
+        orw |= x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) nib[j] += (x >> j) & 0x1111111111111111ull;
+      }
+#pragma unroll
+      for (int b = 0; b < 64; ++b) c[b] += (uint32_t)(nib[b & 3] >> (4 * (b >> 2))) & 15u;
     }
     sq[(uint64_t)q * R + lane] = orw;
 #pragma unroll

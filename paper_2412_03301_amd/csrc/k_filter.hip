@@ -570,8 +570,7 @@ __global__ void __launch_bounds__(256)
 k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r, uint32_t* __restrict__ cutoff,
          const uint32_t* __restrict__ order, uint32_t* __restrict__ rcut) {
   extern __shared__ uint32_t h[];
-  __shared__ uint32_t part[256];
-  __shared__ uint32_t total_s;
+  __shared__ uint32_t wsum[4];
   const uint32_t t = threadIdx.x;
   const uint32_t q = order ? order[blockIdx.x] : blockIdx.x;
   const uint32_t nb = L + 1;
@@ -587,22 +586,30 @@ k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r
   const uint32_t b0 = min(nb, t * per), b1 = min(nb, b0 + per);
   uint32_t s = 0;
   for (uint32_t b = b0; b < b1; ++b) s += h[b];
-  part[t] = s;
-  __syncthreads();
-  if (t == 0) {
-    uint32_t run = 0;
-    for (uint32_t i = 0; i < 256; ++i) { const uint32_t v = part[i]; part[i] = run; run += v; }
-    total_s = run;
+  // block exclusive scan of the threads' sums: a wave scan, then the four
+  // waves' totals
+  const uint32_t lane = lane_id(), wv = t / BVS_WAVE;
+  uint32_t inc = s;
+#pragma unroll
+  for (int d = 1; d < BVS_WAVE; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)inc, d, BVS_WAVE);
+    if (lane >= (uint32_t)d) inc += o;
   }
+  if (lane == BVS_WAVE - 1) wsum[wv] = inc;
   __syncthreads();
-  if (total_s < r) {
+  uint32_t pre = inc - s, total = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) {
+    if (i < wv) pre += wsum[i];
+    total += wsum[i];
+  }
+  if (total < r) {
     if (t == 0) {
       cutoff[q] = 0xFFFFFFFFu;
       if (rcut) rcut[blockIdx.x] = 0xFFFFFFFFu;
     }
     return;
   }
-  const uint32_t pre = part[t];
   if (pre < r && pre + s >= r) {
     uint32_t cum = pre;
     for (uint32_t b = b0; b < b1; ++b) {
