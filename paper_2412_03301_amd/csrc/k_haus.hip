@@ -527,6 +527,62 @@ k_topk(const uint32_t* __restrict__ h2, const uint32_t* __restrict__ ids_in, con
   }
 }
 
+// Small lists: one wave per query over at most 64 kTopkLaneKeys keys (the
+// same keys as k_topk), k rounds of a wave minimum, each taking the winner
+// out of its lane (keys are unique: ids or positions differ; padding keys
+// are all ones and end the rounds).
+static constexpr uint32_t kTopkLaneKeys = 16;
+static constexpr uint32_t kTopkWaveMaxK = 64;
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const uint32_t lo = shfl_xor_u32((uint32_t)v, m), hi = shfl_xor_u32((uint32_t)(v >> 32), m);
+    v = min(v, (uint64_t)hi << 32 | lo);
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(256)
+k_topk_wave(const uint32_t* __restrict__ h2, const uint32_t* __restrict__ ids_in, const uint32_t* __restrict__ count_in,
+            const uint64_t* __restrict__ keys_in, uint64_t n_items, uint64_t stride, uint32_t k, uint32_t n_q,
+            uint32_t* __restrict__ ids, float* __restrict__ dist, uint32_t* __restrict__ count,
+            uint32_t n_valid_total, uint32_t key_is_dist) {
+  const uint32_t q = blockIdx.x * 4 + wave_id(), lane = lane_id();
+  if (q >= n_q) return;
+  const uint64_t n_valid = count_in ? (uint64_t)count_in[q] : n_items;
+  uint64_t key[kTopkLaneKeys];
+#pragma unroll
+  for (uint32_t u = 0; u < kTopkLaneKeys; ++u) {
+    const uint64_t it = lane + (uint64_t)BVS_WAVE * u;
+    key[u] = ~0ull;
+    if (it < n_valid) {
+      if (keys_in) {
+        key[u] = keys_in[(uint64_t)q * stride + it];
+      } else {
+        const uint32_t id = ids_in ? ids_in[(uint64_t)q * stride + it] : (uint32_t)it;
+        key[u] = ((uint64_t)h2[(uint64_t)q * stride + it] << 32) | id;
+      }
+    }
+  }
+  for (uint32_t i = 0; i < k; ++i) {
+    uint64_t m = key[0];
+#pragma unroll
+    for (uint32_t u = 1; u < kTopkLaneKeys; ++u) m = min(m, key[u]);
+    const uint64_t w = wave_min_u64(m);
+    if (lane == 0) {
+      const bool ok = w != ~0ull;
+      ids[(uint64_t)q * k + i] = ok ? (uint32_t)w : 0xFFFFFFFFu;
+      const uint32_t hk = (uint32_t)(w >> 32);
+      dist[(uint64_t)q * k + i] =
+          !ok ? __builtin_inff() : key_is_dist ? __uint_as_float(hk) : sqrtf((float)hk) * (1.0f / 4096.0f);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kTopkLaneKeys; ++u) key[u] = key[u] == w ? ~0ull : key[u];
+  }
+  if (lane == 0) count[q] = min(k, count_in ? count_in[q] : n_valid_total);
+}
+
 uint64_t topk_tmp_words(uint64_t n_items, uint32_t n_q, uint32_t k) {
   const uint64_t chunks = (n_items + kTopkChunk - 1) / kTopkChunk;
   return 2 * (uint64_t)n_q * chunks * k + 16;
@@ -541,9 +597,14 @@ hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_
   uint64_t chunks = (n_items + kTopkChunk - 1) / kTopkChunk;
   if (chunks == 0) chunks = 1;
   if (count_in && chunks != 1) return hipErrorInvalidValue;   // candidate lists hold at most 4096 items
+  const bool wave = k <= kTopkWaveMaxK;   // lists of up to 64 kTopkLaneKeys keys
   if (chunks == 1) {
-    hipLaunchKernelGGL(k_topk, dim3(1, n_q), dim3(1024), 0, st, h2, ids_in, count_in, (const uint64_t*)nullptr,
-                       n_items, stride, k, (uint64_t*)nullptr, ids, dist, count, n_valid_total, kd);
+    if (wave && n_items <= BVS_WAVE * kTopkLaneKeys)
+      hipLaunchKernelGGL(k_topk_wave, dim3((n_q + 3) / 4), dim3(256), 0, st, h2, ids_in, count_in,
+                         (const uint64_t*)nullptr, n_items, stride, k, n_q, ids, dist, count, n_valid_total, kd);
+    else
+      hipLaunchKernelGGL(k_topk, dim3(1, n_q), dim3(1024), 0, st, h2, ids_in, count_in, (const uint64_t*)nullptr,
+                         n_items, stride, k, (uint64_t*)nullptr, ids, dist, count, n_valid_total, kd);
     return hipGetLastError();
   }
   // First pass: per chunk top-k keys into tmp[0 ..], then merge passes.
@@ -560,9 +621,14 @@ hipError_t launch_topk(const uint32_t* h2, const uint32_t* ids_in, const uint32_
     const uint64_t c2 = (n_in + kTopkChunk - 1) / kTopkChunk;
     if (c2 == 1) {
       // Padding keys (all ones) sort last; count = min(k, n_items).
-      hipLaunchKernelGGL(k_topk, dim3(1, n_q), dim3(1024), 0, st, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
-                         (const uint32_t*)nullptr, a, n_in, n_in, k, (uint64_t*)nullptr, ids, dist, count,
-                         n_valid_total, kd);
+      if (wave && n_in <= BVS_WAVE * kTopkLaneKeys)
+        hipLaunchKernelGGL(k_topk_wave, dim3((n_q + 3) / 4), dim3(256), 0, st, (const uint32_t*)nullptr,
+                           (const uint32_t*)nullptr, (const uint32_t*)nullptr, a, n_in, n_in, k, n_q, ids, dist,
+                           count, n_valid_total, kd);
+      else
+        hipLaunchKernelGGL(k_topk, dim3(1, n_q), dim3(1024), 0, st, (const uint32_t*)nullptr,
+                           (const uint32_t*)nullptr, (const uint32_t*)nullptr, a, n_in, n_in, k, (uint64_t*)nullptr,
+                           ids, dist, count, n_valid_total, kd);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       return hipSuccess;
