@@ -36,25 +36,42 @@ k_convert(const float* __restrict__ x, uint64_t n_rows, uint32_t d, uint32_t dp,
   const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / BVS_WAVE;
   const uint64_t nwaves = (gridDim.x * (uint64_t)blockDim.x) / BVS_WAVE;
   uint32_t bad = 0;
+  // four consecutive elements per lane (one 16-byte load when rows of d
+  // floats keep that alignment), their plane bytes stored as one word each
+  const bool vec = d % 4 == 0 && ((uintptr_t)x & 15) == 0;
   for (uint64_t r = wave; r < n_rows; r += nwaves) {
     const float* xr = x + r * d;
     uint64_t ss = 0;
     uint32_t hs = 0, es = 0;
-    for (uint32_t e = lane; e < dp; e += BVS_WAVE) {
-      int a = 0;
-      if (e < d) {
-        const float v = xr[e];
-        const float s = v * 4096.0f;
-        float ri = rintf(s);
-        if (!(ri == s) || !(fabsf(v) <= 1.0f)) { bad |= ST_OFF_GRID; ri = 0.0f; }
-        a = (int)ri;
-        const int e2 = 2 * (a & 63) - 63;   // 2 (lo - 31.5), zero on padding
-        es += (uint32_t)(e2 * e2);
+    for (uint32_t e0 = 4 * lane; e0 < dp; e0 += 4 * BVS_WAVE) {
+      float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (vec && e0 + 3 < d) {
+        const float4 f = *(const float4*)(xr + e0);
+        v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+      } else {
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+          if (e0 + j < d) v[j] = xr[e0 + j];
       }
-      hi[r * dp + e] = (int8_t)(a >> 6);   // floor(a / 64) in [-64, 64]
-      lo[r * dp + e] = (uint8_t)(a & 63);  // a - 64 floor(a / 64) in [0, 63]
-      ss += (uint64_t)(a * a);
-      hs += (uint32_t)((a >> 6) * (a >> 6));
+      uint32_t hw = 0, lw = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {
+        int a = 0;
+        if (e0 + j < d) {
+          const float s = v[j] * 4096.0f;
+          float ri = rintf(s);
+          if (!(ri == s) || !(fabsf(v[j]) <= 1.0f)) { bad |= ST_OFF_GRID; ri = 0.0f; }
+          a = (int)ri;
+          const int e2 = 2 * (a & 63) - 63;   // 2 (lo - 31.5), zero on padding
+          es += (uint32_t)(e2 * e2);
+        }
+        hw |= (uint32_t)(uint8_t)(int8_t)(a >> 6) << (8 * j);   // floor(a / 64) in [-64, 64]
+        lw |= (uint32_t)(a & 63) << (8 * j);                     // a - 64 floor(a / 64) in [0, 63]
+        ss += (uint64_t)(a * a);
+        hs += (uint32_t)((a >> 6) * (a >> 6));
+      }
+      *(uint32_t*)(hi + r * dp + e0) = hw;   // dp is a multiple of 64
+      *(uint32_t*)(lo + r * dp + e0) = lw;
     }
     ss = wave_sum_u64(ss);
     if (ss > (1ull << 26)) bad |= ST_NORM;  // ||x|| > 2
@@ -75,6 +92,7 @@ k_convert(const float* __restrict__ x, uint64_t n_rows, uint32_t d, uint32_t dp,
 hipError_t launch_convert(const float* x, uint64_t n_rows, uint32_t d, uint32_t dp, int8_t* hi,
                           uint8_t* lo, uint32_t* norms, uint2* scr, uint32_t* status, int n_cu, hipStream_t st) {
   if (n_rows == 0) return hipSuccess;
+  if (dp % 4 != 0 || (((uintptr_t)hi | (uintptr_t)lo) & 3) != 0) return hipErrorInvalidValue;   // word stores
   const uint64_t want = (n_rows + 3) / 4;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)n_cu * 32);
   hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, st, x, n_rows, d, dp, hi, lo, norms, scr, status);

@@ -576,10 +576,22 @@ k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r
   const uint32_t nb = L + 1;
   for (uint32_t i = t; i < nb; i += 256) h[i] = 0;
   __syncthreads();
-  const uint16_t* sq = sample + (uint64_t)q * S;
-  for (uint32_t i = t; i < S; i += 256) {
-    const uint32_t v = sq[i];
-    if (v != 0xFFFFu) atomicAdd(&h[v], 1u);
+  // S is a multiple of 256 (whole sampled blocks): eight scores per 16-byte
+  // load, a thread's loads all in flight before its histogram updates
+  const uint4* sq = (const uint4*)(sample + (uint64_t)q * S);
+  for (uint32_t i0 = t; i0 < S / 8; i0 += 256 * 8) {
+    uint4 x[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) x[u] = i0 + 256 * u < S / 8 ? sq[i0 + 256 * u] : make_uint4(~0u, ~0u, ~0u, ~0u);
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) {
+      const uint32_t w4[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+      for (uint32_t e = 0; e < 8; ++e) {
+        const uint32_t v = (w4[e / 2] >> (16 * (e & 1))) & 0xFFFFu;
+        if (v != 0xFFFFu) atomicAdd(&h[v], 1u);
+      }
+    }
   }
   __syncthreads();
   const uint32_t per = (nb + 255) / 256;
@@ -626,6 +638,7 @@ k_cutoff(const uint16_t* __restrict__ sample, uint32_t S, uint32_t L, uint32_t r
 hipError_t launch_cutoff(const uint16_t* sample, uint32_t S, uint32_t L, uint32_t r, uint32_t n_q,
                          uint32_t* cutoff, const uint32_t* order, uint32_t* rcut, hipStream_t st) {
   if (n_q == 0) return hipSuccess;
+  if (S % 256 != 0 || ((uintptr_t)sample & 15) != 0) return hipErrorInvalidValue;   // read 8 scores at a time
   hipLaunchKernelGGL(k_cutoff, dim3(n_q), dim3(256), (L + 1) * sizeof(uint32_t), st, sample, S, L, r, cutoff, order,
                      rcut);
   return hipGetLastError();
