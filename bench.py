@@ -1098,7 +1098,7 @@ def trends_bench(args, w, dev):
         ix.set_first_layer("bitmaps")
         row = {"label": label, "A": A, "M": M, "T": T, "first_layer": first_layer, "qps": n_q * args.steps / el, **rec,
                "first_layer_ms": st.get("cutoff", 0.0) + st.get("filter", 0.0) + st.get("select", 0.0)
-               + st.get("fallback", 0.0), "rerank_ms": st.get("rerank"),
+               + st.get("fallback", 0.0) + st.get("lists", 0.0), "rerank_ms": st.get("rerank"),
                "f2_count_mean_first8": float(cnt.float().mean().item())}
         del ws, out, f1
         log(f"{label} A={A} M={M} T={T} {first_layer}: {row['qps']:.0f} q/s, recall@3/5/10 {rec['recall_at_3']:.3f} "
