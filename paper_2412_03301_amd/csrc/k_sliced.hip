@@ -225,8 +225,8 @@ k_pass_lists(const uint64_t* __restrict__ sq, uint32_t R, uint32_t L, uint32_t n
 #pragma unroll 1
     for (uint32_t c = 0; c < 4; ++c) {
       uint64_t w = word & (0x1111111111111111ull << c);
-      const uint32_t cnt = popc64(w);
-      uint32_t inc = cnt;
+      const uint32_t nc = popc64(w);   // the word's members of class c
+      uint32_t inc = nc;
 #pragma unroll
       for (int d = 1; d < BVS_WAVE; d <<= 1) {
         const uint32_t o = (uint32_t)__shfl_up((int)inc, d, BVS_WAVE);
@@ -234,7 +234,7 @@ k_pass_lists(const uint64_t* __restrict__ sq, uint32_t R, uint32_t L, uint32_t n
       }
       const uint32_t total = (uint32_t)__shfl((int)inc, BVS_WAVE - 1, BVS_WAVE);
       const uint32_t zero_row = (L + c) * kRowBytes;
-      uint32_t j = inc - cnt;
+      uint32_t j = inc - nc;
       // segment i holds the class's steps cum .. cum + len - 1 at list steps
       // start .. start + len - 1
       uint32_t start = 0, cum = 0;
