@@ -23,23 +23,31 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 //   B(k, n) = B[n * ldb + k] (BT = false) or B[k * ldb + n] (BT = true)
 // Epilogue: v = acc + bias[n] (bias may be null), relu if asked, then v to
 // C32[m * ldc + n] and / or bfloat16(v) to C16 (either may be null).
-// Workgroup tile 128 x 128 x 32 staged in LDS with k contiguous; four waves,
-// each a 64 x 64 block of 16 x 16 x 32 bf16 matrix-core products.
+// Workgroup tile 128 x 128 x 32 staged in LDS with k contiguous (two
+// buffers); four waves, each a 64 x 64 block of 16 x 16 x 32 bf16
+// matrix-core products.
 // Leading dimensions are multiples of 8 elements (16-byte rows).
 static constexpr int GM = 128, GN = 128, GK = 32, GPAD = 8;
 
+// One 128 x 32 operand step in registers: two 16-byte chunks per thread,
+// zero past the matrix, loaded ahead of the products of the step before.
+struct GemmRegs {
+  uint4 v[2];
+};
+
+// Load the chunks of the step at k0.  TR false: rows r0.., 32 contiguous k
+// (128 rows x 4 chunks of 8); TR true: 32 k rows of 128 contiguous r (32 x
+// 16 chunks of 8), transposed when stored.
 template <bool TR>
-__device__ __forceinline__ void gemm_stage(const uint16_t* __restrict__ X, uint64_t ld, uint32_t r0, uint32_t R,
-                                           uint32_t k0, uint32_t K, uint16_t (*s)[GK + GPAD]) {
+__device__ __forceinline__ void gemm_load(const uint16_t* __restrict__ X, uint64_t ld, uint32_t r0, uint32_t R,
+                                          uint32_t k0, uint32_t K, GemmRegs& g) {
   const uint32_t t = threadIdx.x;
-  if (!TR) {
-    // rows r0.., 32 contiguous k: 128 rows x 4 chunks of 8
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const uint32_t c = t + 256 * it;
-      const uint32_t r = c >> 2, kc = (c & 3) * 8;
-      const uint32_t gr = r0 + r, gk = k0 + kc;
-      uint4 v = make_uint4(0, 0, 0, 0);
+  for (int it = 0; it < 2; ++it) {
+    const uint32_t c = t + 256 * it;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (!TR) {
+      const uint32_t gr = r0 + (c >> 2), gk = k0 + (c & 3) * 8;
       if (gr < R) {
         const uint16_t* p = X + (uint64_t)gr * ld + gk;
         if (gk + 8 <= K) {
@@ -52,44 +60,53 @@ __device__ __forceinline__ void gemm_stage(const uint16_t* __restrict__ X, uint6
                          e[6] | (uint32_t)e[7] << 16);
         }
       }
-      *(uint4*)&s[r][kc] = v;
-    }
-  } else {
-    // 32 k rows of 128 contiguous r: 32 x 16 chunks of 8, stored transposed
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const uint32_t c = t + 256 * it;
-      const uint32_t kk = c >> 4, rc = (c & 15) * 8;
-      const uint32_t gk = k0 + kk, gr = r0 + rc;
-      uint16_t e[8];
+    } else {
+      const uint32_t gk = k0 + (c >> 4), gr = r0 + (c & 15) * 8;
       if (gk < K) {
         const uint16_t* p = X + (uint64_t)gk * ld + gr;
         if (gr + 8 <= R) {
-          const uint4 v = *(const uint4*)p;
-          const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-          for (int i = 0; i < 8; ++i) e[i] = (uint16_t)(w[i / 2] >> (16 * (i % 2)));
+          v = *(const uint4*)p;
         } else {
+          uint16_t e[8];
 #pragma unroll
           for (int i = 0; i < 8; ++i) e[i] = gr + i < R ? p[i] : (uint16_t)0;
+          v = make_uint4(e[0] | (uint32_t)e[1] << 16, e[2] | (uint32_t)e[3] << 16, e[4] | (uint32_t)e[5] << 16,
+                         e[6] | (uint32_t)e[7] << 16);
         }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) e[i] = 0;
       }
+    }
+    g.v[it] = v;
+  }
+}
+
+// Store loaded chunks into the LDS step, k contiguous per row.
+template <bool TR>
+__device__ __forceinline__ void gemm_store(const GemmRegs& g, uint16_t (*s)[GK + GPAD]) {
+  const uint32_t t = threadIdx.x;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) s[rc + i][kk] = e[i];
+  for (int it = 0; it < 2; ++it) {
+    const uint32_t c = t + 256 * it;
+    if (!TR) {
+      *(uint4*)&s[c >> 2][(c & 3) * 8] = g.v[it];
+    } else {
+      const uint32_t kk = c >> 4, rc = (c & 15) * 8;
+      const uint32_t w[4] = {g.v[it].x, g.v[it].y, g.v[it].z, g.v[it].w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s[rc + i][kk] = (uint16_t)(w[i / 2] >> (16 * (i % 2)));
     }
   }
 }
 
+// Two LDS steps: step i is stored into buffer i mod 2 behind one barrier,
+// and the loads of step i + 1 are in flight while step i's products run
+// (buffer (i + 1) mod 2 was last read in step i - 1, before that barrier).
 template <bool AT, bool BT>
 __global__ void __launch_bounds__(256)
 k_gemm(const uint16_t* __restrict__ A, uint64_t lda, const uint16_t* __restrict__ B, uint64_t ldb, uint32_t M,
        uint32_t N, uint32_t K, const float* __restrict__ bias, int relu, float* __restrict__ C32,
        uint16_t* __restrict__ C16, uint64_t ldc) {
-  __shared__ __align__(16) uint16_t sA[GM][GK + GPAD];
-  __shared__ __align__(16) uint16_t sB[GN][GK + GPAD];
+  __shared__ __align__(16) uint16_t sA[2][GM][GK + GPAD];
+  __shared__ __align__(16) uint16_t sB[2][GN][GK + GPAD];
   const uint32_t m0 = blockIdx.y * GM, n0 = blockIdx.x * GN;
   const uint32_t w = wave_id(), lane = lane_id();
   const uint32_t wm = (w >> 1) * 64, wn = (w & 1) * 64;
@@ -99,20 +116,27 @@ k_gemm(const uint16_t* __restrict__ A, uint64_t lda, const uint16_t* __restrict_
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (uint32_t k0 = 0; k0 < K; k0 += GK) {
-    gemm_stage<AT>(A, lda, m0, M, k0, K, sA);
-    gemm_stage<BT>(B, ldb, n0, N, k0, K, sB);
+  GemmRegs ra, rb;
+  gemm_load<AT>(A, lda, m0, M, 0, K, ra);
+  gemm_load<BT>(B, ldb, n0, N, 0, K, rb);
+  uint32_t buf = 0;
+  for (uint32_t k0 = 0; k0 < K; k0 += GK, buf ^= 1) {
+    gemm_store<AT>(ra, sA[buf]);
+    gemm_store<BT>(rb, sB[buf]);
     __syncthreads();
+    if (k0 + GK < K) {
+      gemm_load<AT>(A, lda, m0, M, k0 + GK, K, ra);
+      gemm_load<BT>(B, ldb, n0, N, k0 + GK, K, rb);
+    }
     v8bf af[4], bf[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) af[i] = *(const v8bf*)&sA[wm + 16 * i + r][8 * g];
+    for (int i = 0; i < 4; ++i) af[i] = *(const v8bf*)&sA[buf][wm + 16 * i + r][8 * g];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bf[j] = *(const v8bf*)&sB[wn + 16 * j + r][8 * g];
+    for (int j = 0; j < 4; ++j) bf[j] = *(const v8bf*)&sB[buf][wn + 16 * j + r][8 * g];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
