@@ -23,7 +23,7 @@ OUT = os.path.join(PKG, "libbvs.so")
 
 SOURCES = ["capi.cpp", "k_encode.hip", "k_filter.hip", "k_sliced.hip", "k_haus.hip", "k_batch.hip", "k_lowp.hip", "k_learn.hip",
            "k_full.hip", "k_lists.hip"]
-HEADERS = ["device.h", "launch.h", "haus_core.h", os.path.join(INCLUDE, "bvs.h")]
+HEADERS = ["device.h", "launch.h", "haus_core.h", "wta.h", os.path.join(INCLUDE, "bvs.h")]
 ARCH = "gfx950"
 
 

@@ -5,6 +5,7 @@
 // soft Hamming triplet loss, backward pass, Adam).
 #include "device.h"
 #include "launch.h"
+#include "wta.h"
 
 namespace bvs {
 
@@ -236,20 +237,6 @@ hipError_t launch_f32_to_bf16(const float* x, uint64_t n, uint16_t* out, hipStre
 // Order-preserving 16-bit key of a bfloat16 value.
 __device__ __forceinline__ uint32_t bf16_order(uint16_t b) { return (b & 0x8000u) ? (~b & 0xFFFFu) : (b | 0x8000u); }
 
-// Largest threshold th with #{keys >= th} >= k, keys unique: the k-th largest key.
-template <int R>
-__device__ __forceinline__ uint32_t wave_kth_key(const uint32_t (&key)[R], uint32_t k, int topbit) {
-  uint32_t th = 0;
-  for (int b = topbit; b >= 0; --b) {
-    const uint32_t cand = th | (1u << b);
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int t = 0; t < R; ++t) cnt += popc64(ballot(key[t] >= cand));
-    if (cnt >= k) th = cand;
-  }
-  return th;
-}
-
 // One wave per row of Y (float32 [n][L], row stride ldy): codes [n][L/64]
 // of the k largest bfloat16(y), ties to the lower index.
 template <int R>
@@ -266,7 +253,7 @@ k_wta_rows(const float* __restrict__ Y, uint64_t ldy, uint64_t n, uint32_t lgL, 
     const uint32_t j = 64 * t + lane;
     key[t] = (bf16_order(f2bf(Y[row * ldy + j])) << lgL) | (L - 1 - j);
   }
-  const uint32_t th = wave_kth_key<R>(key, k, 15 + (int)lgL);
+  const uint32_t th = kth_largest<R>(key, k, 15 + (int)lgL);
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     const uint64_t wv = ballot(key[t] >= th);
