@@ -1215,8 +1215,8 @@ def trends_bench(args, w, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build's path runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not an implementation).", file=sys.stderr)
+        print("bench.py measures one GPU only: the search runs on a single MI355X "
+              "(sharding across GPUs is described in the design notes, not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
